@@ -1,0 +1,202 @@
+/*
+ * mdx.h -- C ABI of libmdx: batched McMurchie-Davidson (MD) electron-repulsion
+ * integrals (ERIs) over contracted Gaussian shells, on one AMD MI355X (gfx950).
+ *
+ * The integrals are those of Asadchev & Valeev, "Implementation of
+ * McMurchie-Davidson algorithm for Gaussian AO integrals suited for SIMD
+ * processors" (arXiv:2506.12501):
+ *   4-centre (ab|cd)   Sec. 2.1, Eq. (3), over contracted shells, Eq. (5)
+ *   3-centre (a|cd)    Sec. 2.1, Eq. (4)
+ *   2-centre (a|c)     Eq. (4) with a single ket function (Sec. 2.2.3)
+ * evaluated in batches of shellsets of one class (Sec. 2.1, paragraph after
+ * Eq. (19); Sec. 3.1), in the [ij,ab,cd,kl] column-major layout of Sec. 3.1.
+ *
+ * Conventions (all entry points):
+ *  - Atomic units.  A primitive Cartesian Gaussian is
+ *    x_A^ax y_A^ay z_A^az exp(-zeta r_A^2) (Eq. (1)); contraction
+ *    coefficients are applied exactly as given (no normalisation).
+ *  - Cartesian component order within a shell: (l,0,0), (l-1,1,0),
+ *    (l-1,0,1), (l-2,2,0), ... (x power descending, then y descending).
+ *  - Real solid harmonics (default; Eqs. (18)-(19)): order m = -l..l, each
+ *    normalised to the norm of the x^l Cartesian of the same exponent.
+ *  - Everything runs asynchronously on the caller's stream.  The caller owns
+ *    every buffer; outputs are overwritten, never accumulated.  No call
+ *    allocates device memory: scratch lives in the caller's workspace.
+ *  - On any error no kernel is launched and no output is written.
+ *  - One mdx_ctx per device and per host thread (a context is not
+ *    thread-safe).  No C++ exception crosses this interface.
+ */
+#ifndef MDX_H
+#define MDX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* hipStream_t without pulling in the HIP headers */
+typedef struct ihipStream_t *mdx_stream_t;
+
+typedef enum {
+    MDX_OK = 0,
+    MDX_EINVAL = 1,       /* bad argument (null pointer, bad index, mixed classes, ...) */
+    MDX_EUNSUPPORTED = 2, /* angular momentum or order beyond the compiled limits */
+    MDX_EWORKSPACE = 3,   /* workspace smaller than the matching *_workspace_size */
+    MDX_ENOMEM = 4,       /* host-side allocation failed (planning only) */
+    MDX_EDEVICE = 5       /* HIP runtime error; mdx_last_error() has the text */
+} mdx_status;
+
+/* compiled limits */
+#define MDX_LMAX_4C 4      /* l per shell, 4-centre                      */
+#define MDX_LMAX_3C 6      /* l of the single-function side, 3-/2-centre */
+#define MDX_BOYS_MAX_M 32  /* highest Boys order of mdx_boys             */
+
+/* flags */
+#define MDX_SPHERICAL 0    /* real solid harmonics (default)             */
+#define MDX_CARTESIAN 1    /* Cartesian components                       */
+#define MDX_FUSED 2        /* plans: one graph launch, persistent kernels */
+
+typedef struct mdx_ctx mdx_ctx;
+
+/*
+ * Shell table, structure of arrays.  Numeric data live on the device (read
+ * only, caller-owned); integer metadata live on the host because batching and
+ * validation are planned there.
+ *   center   DEVICE double[3*nshell]   centre of shell s at center[3s..3s+2]
+ *   exponent DEVICE double[nprim_tot]  exponents (> 0) of all primitives
+ *   coef     DEVICE double[nprim_tot]  contraction coefficients (as given)
+ *   l        HOST int32[nshell]        angular momentum
+ *   nprim    HOST int32[nshell]        contraction degree K >= 1
+ *   prim_offset HOST int32[nshell]     first primitive of shell s in exponent/coef
+ */
+typedef struct {
+    int32_t nshell;
+    const double *center;
+    const double *exponent;
+    const double *coef;
+    const int32_t *l;
+    const int32_t *nprim;
+    const int32_t *prim_offset;
+} mdx_shells;
+
+/* Context: uploads the Boys table and the Cartesian->solid tables to
+ * `device`.  Returns MDX_EDEVICE if the device is not a usable gfx950. */
+mdx_status mdx_create(int device, mdx_ctx **out);
+void mdx_destroy(mdx_ctx *ctx);
+
+const char *mdx_status_string(mdx_status s);
+/* text of the last error raised on this thread (static storage) */
+const char *mdx_last_error(void);
+
+/*
+ * Boys function F_m(x) = int_0^1 y^{2m} exp(-x y^2) dy (Eq. (28)), m = 0..mmax,
+ * for n arguments: F[m*n + i] = F_m(x[i]).
+ *   x  DEVICE double[n], x >= 0 (finite)
+ *   F  DEVICE double[(mmax+1)*n]
+ *   0 <= mmax <= MDX_BOYS_MAX_M, n >= 0.
+ * Method: tabulated Taylor expansion at the highest order, then downward
+ * recursion (Sec. 3.2.1 notes this as the GPU-friendly choice); x >= 45 uses
+ * the asymptotic F_0 and upward recursion.
+ */
+mdx_status mdx_boys(mdx_ctx *ctx, int32_t n, const double *x, int mmax, double *F,
+                    mdx_stream_t stream);
+
+/*
+ * One class of shellsets, dense outer product of bra pairs x ket pairs.
+ *   ncentre 4: bra[2*ij], bra[2*ij+1] are the shells a, b of bra pair ij;
+ *              ket[2*kl], ket[2*kl+1] the shells c, d.
+ *   ncentre 3: bra[2*ij] is the single shell a (bra[2*ij+1] ignored), ket pairs.
+ *   ncentre 2: bra[2*ij] = a, ket[2*kl] = c (second entries ignored).
+ *   bra, ket HOST int32 arrays.  Every bra entry must have the same
+ *   (l_a, l_b) and every ket entry the same (l_c, l_d).
+ *   out DEVICE double, [ij, ab, cd, kl] column-major (Sec. 3.1):
+ *       out[ij + nbra*(ab + nab*(cd + ncd*kl))],  ab = a*nb + b, cd = c*nd + d,
+ *       nab = n(l_a)*n(l_b) (n(l) = 2l+1 spherical, (l+1)(l+2)/2 Cartesian;
+ *       a single-function side has nab = n(l_a)).
+ *   flags: MDX_SPHERICAL or MDX_CARTESIAN.
+ *   ws, ws_bytes: DEVICE workspace of at least mdx_eri_workspace_size(...)
+ *   bytes, 256-byte aligned; its contents on entry do not matter.
+ * Limits: l <= MDX_LMAX_4C per shell for 4-centre; l_a <= MDX_LMAX_3C and
+ * l_c, l_d <= MDX_LMAX_4C for 3-centre; both <= MDX_LMAX_3C for 2-centre.
+ */
+size_t mdx_eri_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
+                              const int32_t *bra, int32_t nket, const int32_t *ket, int flags);
+mdx_status mdx_eri_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
+                         const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
+                         double *out, void *ws, size_t ws_bytes, mdx_stream_t stream);
+
+/*
+ * Centre derivatives contracted with an adjoint (backward pass of
+ * mdx_eri_batch; the paper has no derivatives -- they follow from
+ * differentiating Eq. (1): d/dA_i phi_a = 2 zeta_a phi_{a+1_i} - a_i phi_{a-1_i}).
+ *   adjoint DEVICE double, same layout and size as mdx_eri_batch's out
+ *   grad    DEVICE double[nbra*12*nket]:
+ *       grad[ij + nbra*(3*X + i + 12*kl)] = sum_{ab,cd} W[ij,ab,cd,kl] d(ab|cd)/dX_i
+ *       X = 0..3 for the centres of a, b, c, d; i = x, y, z.  A slot whose
+ *       function is absent (3-/2-centre) is written as 0.  Centres that
+ *       coincide are still reported separately; the caller sums them.
+ * Same other arguments, limits and workspace query as mdx_eri_batch
+ * (mdx_eri_grad_workspace_size).
+ */
+size_t mdx_eri_grad_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int ncentre,
+                                   int32_t nbra, const int32_t *bra, int32_t nket,
+                                   const int32_t *ket, int flags);
+mdx_status mdx_eri_grad_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
+                              const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
+                              const double *adjoint, double *grad, void *ws, size_t ws_bytes,
+                              mdx_stream_t stream);
+
+/*
+ * Multi-class plans (batch-level screening of Sec. 3.1; mixed classes in one
+ * launch).  A plan holds host-side planning and device-side index tables; it
+ * is built once and executed many times.
+ *
+ * Each batch is one class (same rules as mdx_eri_batch) with a ragged
+ * outer product: for ket pair kl only the first bra_count[kl] bra pairs are
+ * computed (bra_count NULL = all).  Sorting bra pairs by decreasing Schwarz
+ * factor turns a Schwarz screen into such prefixes.  Output of batch b:
+ *   out[out_offset + base_kl + ij + n_kl*(ab + nab*cd)],
+ *   n_kl = bra_count[kl], base_kl = nab*ncd*sum_{k<kl} n_k.
+ * All arrays in the descriptor are HOST arrays, copied by mdx_plan_create.
+ */
+typedef struct {
+    int ncentre;
+    int32_t nbra;
+    const int32_t *bra;
+    int32_t nket;
+    const int32_t *ket;
+    const int32_t *bra_count;
+    int64_t out_offset;
+} mdx_batch_desc;
+
+typedef struct mdx_plan mdx_plan;
+
+/* flags: MDX_SPHERICAL/MDX_CARTESIAN | MDX_FUSED.  Without MDX_FUSED the plan
+ * issues one plain launch per class (and per pair-data side); with it, the
+ * whole plan is one captured graph with persistent work-queue kernels. */
+mdx_status mdx_plan_create(mdx_ctx *ctx, const mdx_shells *shells, int nbatch,
+                           const mdx_batch_desc *batches, int flags, mdx_plan **out);
+size_t mdx_plan_workspace_size(const mdx_plan *plan);
+/* total number of doubles the plan writes (max over batches of offset+size) */
+int64_t mdx_plan_output_size(const mdx_plan *plan);
+/* shells must describe the same basis (same metadata) as at creation; its
+ * device arrays may hold new values.  With MDX_FUSED the device pointers,
+ * out, ws and stream must stay the same across executions (the graph keeps
+ * them); changing any of them rebuilds the graph. */
+mdx_status mdx_plan_execute(mdx_plan *plan, const mdx_shells *shells, double *out, void *ws,
+                            size_t ws_bytes, mdx_stream_t stream);
+void mdx_plan_destroy(mdx_plan *plan);
+
+/* Tile-shape override used by the autotuner: kernel variant for one class
+ * key; see the Python autotuner for the meaning of `variant`.  Returns
+ * MDX_EINVAL for an unknown class/variant.  Affects later plans/calls. */
+mdx_status mdx_set_variant(mdx_ctx *ctx, int ncentre, int la, int lb, int lc, int ld, int flags,
+                           int variant);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MDX_H */

@@ -1,0 +1,297 @@
+// eri.cpp -- planning and launching one class of shellsets (mdx_eri_batch).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+
+#include "runtime.h"
+
+namespace mdx {
+
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static SideGeom make_geom(int la, int lb, bool cart, int role, int npair, int kmax)
+{
+    SideGeom g{};
+    g.la = la;
+    g.lb = lb;
+    g.L = la + std::max(lb, 0);
+    g.cart = cart ? 1 : 0;
+    g.grouped = (lb < 0 && !cart) ? 1 : 0;
+    g.role = role;
+    g.npair = npair;
+    g.kmax = kmax;
+    g.ncol = nfunc(la, cart) * (lb >= 0 ? nfunc(lb, cart) : 1);
+    g.ncolp = round_up(g.ncol, 16);
+    if (g.grouped) {
+        g.nh = ncart(la);
+        g.nterm = ncart(la);
+        g.ntpad = 0;
+        g.rows_per_block = role == 0 ? round_up(g.nterm, 16) : g.nterm;
+        g.nblocks = 1;
+    } else if (role == 0) {
+        g.nh = nherm(g.L);
+        g.nterm = 0;
+        g.ntpad = 0;
+        g.rows_per_block = round_up(kmax * g.nh, 16);
+        g.nblocks = 1;
+    } else {
+        g.nh = nherm(g.L);
+        g.ntpad = round_up(nherm(g.L - 1), 4);
+        g.nterm = ncart(g.L);
+        g.rows_per_block = g.ntpad + g.nterm;
+        g.nblocks = kmax;
+    }
+    g.pair_stride = (int64_t)g.nblocks * g.rows_per_block * g.ncolp;
+    return g;
+}
+
+mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
+                      int32_t nket, const int32_t *ket, const int32_t *bra_count, int flags, ClassPlan &cp)
+{
+    if (!c) return fail(MDX_EINVAL, "null context");
+    if (!sh) return fail(MDX_EINVAL, "null shell table");
+    if (ncentre < 2 || ncentre > 4) return fail(MDX_EINVAL, "ncentre = %d (must be 2, 3 or 4)", ncentre);
+    if (nbra < 0 || nket < 0) return fail(MDX_EINVAL, "negative pair count");
+    if ((nbra > 0 && !bra) || (nket > 0 && !ket)) return fail(MDX_EINVAL, "null pair list");
+    if (flags & ~(MDX_CARTESIAN | MDX_FUSED)) return fail(MDX_EINVAL, "unknown flags 0x%x", flags);
+    if (sh->nshell < 0 || (sh->nshell > 0 && (!sh->l || !sh->nprim || !sh->prim_offset || !sh->center ||
+                                               !sh->exponent || !sh->coef)))
+        return fail(MDX_EINVAL, "incomplete shell table");
+    const bool cart = (flags & MDX_CARTESIAN) != 0;
+    cp = ClassPlan{};
+    cp.ncentre = ncentre;
+    cp.cart = cart;
+    if (nbra == 0 || nket == 0) return MDX_OK;
+    const bool bra2 = ncentre == 4, ket2 = ncentre >= 3;
+    auto check_shell = [&](int32_t s) -> bool { return s >= 0 && s < sh->nshell && sh->nprim[s] >= 1; };
+    // class of the first entries, then every entry must match
+    for (int side = 0; side < 2; ++side) {
+        const int32_t n = side == 0 ? nbra : nket;
+        const int32_t *lst = side == 0 ? bra : ket;
+        const bool two = side == 0 ? bra2 : ket2;
+        if (!check_shell(lst[0]) || (two && !check_shell(lst[1])))
+            return fail(MDX_EINVAL, "%s pair 0: bad shell index or nprim < 1", side ? "ket" : "bra");
+        const int l0 = sh->l[lst[0]], l1 = two ? sh->l[lst[1]] : -1;
+        for (int32_t i = 0; i < n; ++i) {
+            const int32_t s0 = lst[2 * i], s1 = lst[2 * i + 1];
+            if (!check_shell(s0) || (two && !check_shell(s1)))
+                return fail(MDX_EINVAL, "%s pair %d: bad shell index or nprim < 1", side ? "ket" : "bra", i);
+            if (sh->l[s0] != l0 || (two && sh->l[s1] != l1))
+                return fail(MDX_EINVAL, "%s pair %d: mixed classes in one batch", side ? "ket" : "bra", i);
+        }
+        if (side == 0) { cp.la = l0; cp.lb = l1; }
+        else { cp.lc = l0; cp.ld = l1; }
+    }
+    const int lmax_pair = MDX_LMAX_4C, lmax_single = MDX_LMAX_3C;
+    auto lok = [&](int l, bool single) { return l >= 0 && l <= (single ? lmax_single : lmax_pair); };
+    if (cp.la < 0 || cp.lc < 0) return fail(MDX_EINVAL, "negative angular momentum");
+    if (!lok(cp.la, !bra2) || (bra2 && !lok(cp.lb, false)) || !lok(cp.lc, !ket2) || (ket2 && !lok(cp.ld, false)))
+        return fail(MDX_EUNSUPPORTED, "angular momentum beyond the compiled limits (l <= %d per pair shell, %d single)",
+                    lmax_pair, lmax_single);
+    if (ncentre == 2 && (cp.lc > lmax_single)) return fail(MDX_EUNSUPPORTED, "2-centre l beyond limit");
+
+    const int Lb = cp.la + std::max(cp.lb, 0), Lk = cp.lc + std::max(cp.ld, 0);
+    cp.swapped = (ncentre == 4 && Lb < Lk && !bra_count);
+    // kernel sides
+    for (int side = 0; side < 2; ++side) {
+        const bool from_bra = (side == 0) != cp.swapped;
+        const int32_t n = from_bra ? nbra : nket;
+        const int32_t *lst = from_bra ? bra : ket;
+        const bool two = from_bra ? bra2 : ket2;
+        SidePlan &sp = side == 0 ? cp.bra : cp.ket;
+        sp.pairs.resize(n);
+        int kmax = 1;
+        for (int32_t i = 0; i < n; ++i) {
+            PairRec r{};
+            r.sa = lst[2 * i];
+            r.sb = two ? lst[2 * i + 1] : -1;
+            r.ka = sh->nprim[r.sa];
+            r.kb = two ? sh->nprim[r.sb] : 1;
+            r.offa = sh->prim_offset[r.sa];
+            r.offb = two ? sh->prim_offset[r.sb] : 0;
+            sp.pairs[i] = r;
+            kmax = std::max(kmax, r.ka * r.kb);
+        }
+        const int l0 = from_bra ? cp.la : cp.lc, l1 = from_bra ? cp.lb : cp.ld;
+        sp.g = make_geom(l0, two ? l1 : -1, cart, side, n, kmax);
+    }
+    cp.key.LB = cp.bra.g.L;
+    cp.key.LK = cp.ket.g.L;
+    cp.key.NAB = cp.bra.g.ncol;
+    cp.key.NCD = cp.ket.g.ncol;
+    cp.key.GB = cp.bra.g.grouped != 0;
+    cp.key.GK = cp.ket.g.grouped != 0;
+
+    // kernel choice: tuned override, else the register kernel when it exists
+    auto it = c->variant.find(std::make_tuple(ncentre, cp.la, cp.lb, cp.lc, cp.ld, cart ? 1 : 0));
+    const int var = it != c->variant.end() ? it->second : -1;
+    const bool has_valu = eri_valu_has(cp.key), has_mfma = eri_mfma_has(cp.key);
+    if (var == 0 && has_valu) cp.kind = K_VALU;
+    else if (var >= 1 && has_mfma) { cp.kind = K_MFMA; cp.variant = var; }
+    else if (has_valu) cp.kind = K_VALU;
+    else if (has_mfma) cp.kind = K_MFMA;
+    else
+        return fail(MDX_EUNSUPPORTED, "no kernel compiled for class (%d %d|%d %d) ncentre %d %s", cp.la, cp.lb, cp.lc,
+                    cp.ld, ncentre, cart ? "Cartesian" : "spherical");
+    if (cp.kind == K_MFMA && cp.variant == 0) cp.variant = 1;
+
+    // terminal ket matrix
+    const int kl0 = cp.ket.g.la, kl1 = cp.ket.g.lb;
+    cp.tket = c->tket + (kl1 >= 0 ? c->tket_off[cart][kl0][kl1] : c->tket1_off[cart][kl0]);
+
+    // output map (caller layout [ij, ab, cd, kl])
+    const int nab_c = nfunc(cp.la, cart) * (bra2 ? nfunc(cp.lb, cart) : 1);
+    const int ncd_c = nfunc(cp.lc, cart) * (ket2 ? nfunc(cp.ld, cart) : 1);
+    OutMap &om = cp.om;
+    const int nabk = cp.bra.g.ncol, ncdk = cp.ket.g.ncol;
+    if (nabk > MAXF || ncdk > MAXF) return fail(MDX_EUNSUPPORTED, "too many functions per pair");
+    if (!bra_count) {
+        if (!cp.swapped) {
+            om.sI = 1;
+            om.sJ = (int64_t)nbra * nab_c * ncd_c;
+            om.mult = nbra;
+            for (int i = 0; i < nabk; ++i) om.oab[i] = i;
+            for (int j = 0; j < ncdk; ++j) om.ocd[j] = j * nab_c;
+        } else {
+            om.sJ = 1;
+            om.sI = (int64_t)nbra * nab_c * ncd_c;
+            om.mult = nbra;
+            for (int i = 0; i < nabk; ++i) om.oab[i] = i * nab_c;
+            for (int j = 0; j < ncdk; ++j) om.ocd[j] = j;
+        }
+        cp.out_doubles = (int64_t)nbra * nket * nab_c * ncd_c;
+    } else {
+        cp.count.resize(nket);
+        cp.obase.resize(nket);
+        int64_t off = 0;
+        for (int32_t k = 0; k < nket; ++k) {
+            const int32_t n = bra_count[k];
+            if (n < 0 || n > nbra) return fail(MDX_EINVAL, "bra_count[%d] = %d outside [0, %d]", k, n, nbra);
+            cp.count[k] = n;
+            cp.obase[k] = off;
+            off += (int64_t)n * nab_c * ncd_c;
+            for (int32_t i0 = 0; i0 < n; i0 += 64) cp.tiles.push_back(make_int2(k, i0));
+        }
+        om.sI = 1;
+        om.sJ = 0;
+        om.mult = 0;
+        for (int i = 0; i < nabk; ++i) om.oab[i] = i;
+        for (int j = 0; j < ncdk; ++j) om.ocd[j] = j * nab_c;
+        cp.out_doubles = off;
+    }
+    return MDX_OK;
+}
+
+WsLayout ws_layout(const ClassPlan &cp, size_t base)
+{
+    WsLayout L{};
+    size_t o = align256(base);
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
+    L.pairs_bra = take(nb * sizeof(PairRec));
+    L.pairs_ket = take(nk * sizeof(PairRec));
+    L.np_bra = take(nb * sizeof(int32_t));
+    L.np_ket = take(nk * sizeof(int32_t));
+    L.prim_bra = take(nb * cp.bra.g.kmax * sizeof(PrimRec));
+    L.prim_ket = take(nk * cp.ket.g.kmax * sizeof(PrimRec));
+    L.H_bra = take(nb * (size_t)cp.bra.g.pair_stride * sizeof(double));
+    L.H_ket = take(nk * (size_t)cp.ket.g.pair_stride * sizeof(double));
+    L.count = take(cp.count.size() * sizeof(int32_t));
+    L.obase = take(cp.obase.size() * sizeof(int64_t));
+    L.tiles = take(cp.tiles.size() * sizeof(int2));
+    L.total = o - base;
+    return L;
+}
+
+mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
+                         double *out, hipStream_t s, bool upload)
+{
+    const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
+    if (nb == 0 || nk == 0) return MDX_OK;
+    if (upload) {
+        HIP_TRY2(hipMemcpyAsync(ws + L.pairs_bra, cp.bra.pairs.data(), nb * sizeof(PairRec), hipMemcpyHostToDevice, s));
+        HIP_TRY2(hipMemcpyAsync(ws + L.pairs_ket, cp.ket.pairs.data(), nk * sizeof(PairRec), hipMemcpyHostToDevice, s));
+        if (!cp.count.empty()) {
+            HIP_TRY2(hipMemcpyAsync(ws + L.count, cp.count.data(), cp.count.size() * 4, hipMemcpyHostToDevice, s));
+            HIP_TRY2(hipMemcpyAsync(ws + L.obase, cp.obase.data(), cp.obase.size() * 8, hipMemcpyHostToDevice, s));
+        }
+        if (!cp.tiles.empty())
+            HIP_TRY2(hipMemcpyAsync(ws + L.tiles, cp.tiles.data(), cp.tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    }
+    for (int side = 0; side < 2; ++side) {
+        const SidePlan &sp = side == 0 ? cp.bra : cp.ket;
+        PairDataArgs pa{};
+        pa.g = sp.g;
+        pa.pairs = (const PairRec *)(ws + (side == 0 ? L.pairs_bra : L.pairs_ket));
+        pa.center = sh->center;
+        pa.expo = sh->exponent;
+        pa.coef = sh->coef;
+        pa.Ca = c->solid + c->solid_off[sp.g.la];
+        pa.Cb = sp.g.lb >= 0 ? c->solid + c->solid_off[sp.g.lb] : nullptr;
+        pa.prim = (PrimRec *)(ws + (side == 0 ? L.prim_bra : L.prim_ket));
+        pa.H = (double *)(ws + (side == 0 ? L.H_bra : L.H_ket));
+        pa.nprim = (int32_t *)(ws + (side == 0 ? L.np_bra : L.np_ket));
+        launch_pairdata(pa, s);
+    }
+    EriArgs a{};
+    a.bra = SideDev{(const PrimRec *)(ws + L.prim_bra), (const double *)(ws + L.H_bra),
+                    (const int32_t *)(ws + L.np_bra), cp.bra.g.kmax, cp.bra.g.pair_stride};
+    a.ket = SideDev{(const PrimRec *)(ws + L.prim_ket), (const double *)(ws + L.H_ket),
+                    (const int32_t *)(ws + L.np_ket), cp.ket.g.kmax, cp.ket.g.pair_stride};
+    a.nbra = (int)nb;
+    a.nket = (int)nk;
+    a.boys = c->boys;
+    a.Tket = cp.tket;
+    a.om = cp.om;
+    a.om.out = out;
+    int nblocks;
+    const int tile = cp.kind == K_VALU ? 64 : 1;
+    if (cp.count.empty()) {
+        a.tiles = nullptr;
+        a.tiles_per_J = (int)((nb + tile - 1) / tile);
+        nblocks = a.tiles_per_J * (int)nk;
+    } else {
+        a.om.count = (const int32_t *)(ws + L.count);
+        a.om.obase = (const int64_t *)(ws + L.obase);
+        a.tiles = (const int2 *)(ws + L.tiles);
+        nblocks = (int)cp.tiles.size();
+    }
+    a.ntile_total = nblocks;
+    if (nblocks == 0) return MDX_OK;
+    bool ok = cp.kind == K_VALU ? eri_valu_launch(cp.key, a, nblocks, s)
+                                : eri_mfma_launch(cp.key, a, nblocks, cp.variant, s);
+    if (!ok) return fail(MDX_EUNSUPPORTED, "kernel instance missing");
+    HIP_TRY2(hipGetLastError());
+    return MDX_OK;
+}
+
+}  // namespace mdx
+
+using namespace mdx;
+
+extern "C" size_t mdx_eri_workspace_size(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra,
+                                         const int32_t *bra, int32_t nket, const int32_t *ket, int flags)
+{
+    ClassPlan cp;
+    if (plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp) != MDX_OK) return 0;
+    return ws_layout(cp, 0).total + 256;
+}
+
+extern "C" mdx_status mdx_eri_batch(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
+                                    int32_t nket, const int32_t *ket, int flags, double *out, void *ws,
+                                    size_t ws_bytes, mdx_stream_t stream)
+{
+    if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_batch: MDX_FUSED applies to plans only");
+    ClassPlan cp;
+    mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp);
+    if (st != MDX_OK) return st;
+    if (nbra == 0 || nket == 0) return MDX_OK;
+    if (!out) return fail(MDX_EINVAL, "mdx_eri_batch: null output");
+    if (!ws) return fail(MDX_EINVAL, "mdx_eri_batch: null workspace");
+    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_eri_batch: workspace not 256-byte aligned");
+    const WsLayout L = ws_layout(cp, 0);
+    if (ws_bytes < L.total) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, L.total);
+    HIP_TRY2(hipSetDevice(c->device));
+    return enqueue_class(c, sh, cp, L, (char *)ws, out, (hipStream_t)stream, true);
+}

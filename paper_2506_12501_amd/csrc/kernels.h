@@ -1,0 +1,47 @@
+// kernels.h -- launch interfaces of the gfx950 kernels (host side).
+#pragma once
+
+#include "mdx_internal.h"
+
+namespace mdx {
+
+__device__ __forceinline__ double rsqrt_d(double x) { return 1.0 / sqrt(x); }
+
+// class key of an integral kernel (kernel orientation)
+struct EriKey {
+    int LB, LK;     // total Hermite order of bra and ket
+    int NAB, NCD;   // functions per bra / ket pair
+    bool GB, GK;    // single-function solid sides (primitives summed in [0]^(m))
+};
+
+struct EriArgs {
+    SideDev bra, ket;
+    int nbra, nket;
+    int tiles_per_J;          // dense tiling: bra tiles per ket pair
+    const int2 *tiles;        // explicit (J, I0) tile list, or null
+    const double *boys;       // Boys table
+    const double *Tket;       // terminal ket matrix [ncart(LK) pad 4][ncolp] (MFMA kernel)
+    int ntile_total;          // number of tiles (persistent kernels)
+    int *counter;             // work counter (persistent kernels)
+    OutMap om;
+};
+
+struct PairDataArgs {
+    SideGeom g;
+    const PairRec *pairs;
+    const double *center, *expo, *coef;
+    const double *Ca, *Cb;   // solid coefficients [nsph(l)][ncart(l)], null for Cartesian
+    PrimRec *prim;
+    double *H;
+    int32_t *nprim;
+};
+void launch_pairdata(const PairDataArgs &a, hipStream_t s);
+
+bool eri_valu_has(const EriKey &k);
+bool eri_valu_launch(const EriKey &k, const EriArgs &a, int nblocks, hipStream_t s);
+bool eri_mfma_has(const EriKey &k);
+bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
+
+void launch_boys(const double *x, int n, int mmax, double *F, const double *tab, hipStream_t s);
+
+}  // namespace mdx

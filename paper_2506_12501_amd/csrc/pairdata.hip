@@ -1,0 +1,201 @@
+// pairdata.hip -- primitive-pair data for one side of a class of shellsets.
+//
+// For every shell pair and every primitive pair (zeta_a, zeta_b) it writes
+//   zeta_p, P (Sec. 2.1, after Eq. (8)) and the Hermite-to-AO matrix
+//   H_ab^p = sum_{a,b} C^a C^b E_ab^p   (Eq. (19); C = identity for Cartesian)
+// with E from the recursion of Eqs. (10)-(11) bootstrapped by Eq. (14), and
+// all primitive prefactors folded in:
+//   bra: 2 pi^{5/2} K_AB c_a c_b / zeta_p        (from [0]^(m), Eq. (27))
+//   ket: (-1)^{l_q} K_CD c_c c_d / zeta_q         (sign of Eq. (25))
+// A single-function solid side (3-/2-centre, Sec. 2.2.3) keeps only the
+// terminal Hermites p = a, whose coefficient is (2 zeta_a)^{-l_a} (Eq. (16));
+// its H is the bare C and the primitive weight goes to [0]^(m) instead.
+// A single-function Cartesian side uses the 2-centre recursion with a unit
+// partner (zeta_b = 0, b = 0).
+#include "kernels.h"
+
+namespace mdx {
+
+constexpr int PD_LMAX = 7;
+constexpr int PD_ED = PD_LMAX + 1;
+constexpr int PD_ET = 2 * PD_LMAX + 1;
+
+__device__ __forceinline__ void cart_of(int l, int idx, int &ax, int &ay, int &az)
+{
+    // inverse of the Cartesian order (l,0,0),(l-1,1,0),(l-1,0,1),...
+    int s = 0;
+    while ((s + 1) * (s + 2) / 2 <= idx) ++s;
+    az = idx - s * (s + 1) / 2;
+    ay = s - az;
+    ax = l - s;
+}
+
+__global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
+{
+    const SideGeom &g = a.g;
+    const int kblk = g.grouped ? 1 : g.kmax;
+    const int pair = blockIdx.x / kblk;
+    const int k = blockIdx.x % kblk;
+    const PairRec pr = a.pairs[pair];
+    const int np = pr.ka * pr.kb;
+    const int la = g.la;
+    const int lb = g.lb < 0 ? 0 : g.lb;
+    __shared__ double E[3][PD_ED][PD_ED][PD_ET];
+    __shared__ double sh_pref;
+
+    if (threadIdx.x == 0 && k == 0) a.nprim[pair] = np;
+
+    const double A0 = a.center[3 * pr.sa], A1 = a.center[3 * pr.sa + 1], A2 = a.center[3 * pr.sa + 2];
+    double B[3] = {A0, A1, A2};
+    if (g.lb >= 0) {
+        B[0] = a.center[3 * pr.sb]; B[1] = a.center[3 * pr.sb + 1]; B[2] = a.center[3 * pr.sb + 2];
+    }
+    const double Av[3] = {A0, A1, A2};
+
+    if (g.grouped) {
+        // single-function solid side: primitive records carry the weights
+        for (int kk = threadIdx.x; kk < g.kmax; kk += blockDim.x) {
+            PrimRec r{};
+            if (kk < np) {
+                const double z = a.expo[pr.offa + kk], c = a.coef[pr.offa + kk];
+                const double w = c * pow(2.0 * z, -(double)la) / z;
+                r.p = z; r.Px = A0; r.Py = A1; r.Pz = A2;
+                r.ws = (g.role == 0 ? 2.0 * 17.493418327624862 : 1.0) * w;   // 2 pi^{5/2}
+                r.wt = (g.role == 1 && (la & 1)) ? -1.0 : 1.0;
+            } else {
+                r.p = 1.0; r.Px = A0; r.Py = A1; r.Pz = A2; r.ws = 0.0; r.wt = 0.0;
+            }
+            a.prim[pair * g.kmax + kk] = r;
+        }
+        const double sgn = (g.role == 1 && (la & 1)) ? -1.0 : 1.0;
+        double *Hp = a.H + (int64_t)pair * g.pair_stride;
+        const int nrows = g.rows_per_block;
+        for (int e = threadIdx.x; e < nrows * g.ncolp; e += blockDim.x) {
+            const int row = e / g.ncolp, col = e % g.ncolp;
+            double v = 0.0;
+            if (row < g.nterm && col < g.ncol) v = sgn * (g.cart ? (row == col ? 1.0 : 0.0) : a.Ca[col * ncart(la) + row]);
+            Hp[e] = v;
+        }
+        // bra role pads rows to 16
+        if (g.role == 0)
+            for (int e = nrows * g.ncolp + threadIdx.x; e < g.pair_stride; e += blockDim.x) Hp[e] = 0.0;
+        return;
+    }
+
+    const bool valid = k < np;
+    double za = 1.0, zb = 0.0, ca = 0.0, cb = 1.0;
+    if (valid) {
+        const int ka = k / pr.kb, kb = k % pr.kb;
+        za = a.expo[pr.offa + ka];
+        ca = a.coef[pr.offa + ka];
+        if (g.lb >= 0) {
+            zb = a.expo[pr.offb + kb];
+            cb = a.coef[pr.offb + kb];
+        }
+    }
+    const double p = za + zb;
+    const double i2p = 0.5 / p;
+    if (threadIdx.x < 3) {
+        const int ax = threadIdx.x;
+        const double P = (za * Av[ax] + zb * B[ax]) / p;
+        const double XPA = P - Av[ax], XPB = P - B[ax];
+        // Eqs. (10), (11) with E^0_00 = 1 (the exponential is applied below)
+        E[ax][0][0][0] = 1.0;
+        for (int i = 0; i <= la; ++i) {
+            if (i > 0)
+                for (int t = 0; t <= i; ++t) {
+                    double v = XPA * (t <= i - 1 ? E[ax][i - 1][0][t] : 0.0);
+                    if (t > 0) v += i2p * E[ax][i - 1][0][t - 1];
+                    if (t + 1 <= i - 1) v += (t + 1) * E[ax][i - 1][0][t + 1];
+                    E[ax][i][0][t] = v;
+                }
+            for (int j = 1; j <= lb; ++j)
+                for (int t = 0; t <= i + j; ++t) {
+                    double v = XPB * (t <= i + j - 1 ? E[ax][i][j - 1][t] : 0.0);
+                    if (t > 0) v += i2p * E[ax][i][j - 1][t - 1];
+                    if (t + 1 <= i + j - 1) v += (t + 1) * E[ax][i][j - 1][t + 1];
+                    E[ax][i][j][t] = v;
+                }
+        }
+    }
+    if (threadIdx.x == 0) {
+        const double dx = Av[0] - B[0], dy = Av[1] - B[1], dz = Av[2] - B[2];
+        const double K = valid ? exp(-za * zb / p * (dx * dx + dy * dy + dz * dz)) * ca * cb : 0.0;
+        const double pref = K / p;   // + 2 pi^{5/2} on the bra
+        sh_pref = g.role == 0 ? 2.0 * 17.493418327624862 * pref : pref;
+        PrimRec r{};
+        r.p = valid ? p : 1.0;
+        r.Px = (za * Av[0] + zb * B[0]) / p;
+        r.Py = (za * Av[1] + zb * B[1]) / p;
+        r.Pz = (za * Av[2] + zb * B[2]) / p;
+        r.ws = valid ? 1.0 : 0.0;
+        // terminal weight (-1)^L K c c / (zeta_q (2 zeta_q)^L), Eqs. (17), (40)
+        r.wt = valid ? ((g.L & 1) ? -1.0 : 1.0) * pref * pow(2.0 * p, -(double)g.L) : 0.0;
+        a.prim[pair * g.kmax + k] = r;
+    }
+    __syncthreads();
+    const double pref = sh_pref;
+
+    // rows of this primitive block
+    int row0, nrows;
+    double *Hp;
+    if (g.role == 0) {
+        row0 = k * g.nh;
+        nrows = g.nh;
+        if (k == g.kmax - 1) nrows = g.rows_per_block - row0;   // include zero padding
+        Hp = a.H + (int64_t)pair * g.pair_stride;
+    } else {
+        row0 = 0;
+        nrows = g.rows_per_block;
+        Hp = a.H + (int64_t)pair * g.pair_stride + (int64_t)k * g.rows_per_block * g.ncolp;
+    }
+    const int nb_cart = g.lb >= 0 ? ncart(lb) : 1;
+    const int nb_out = g.lb >= 0 ? nfunc(lb, g.cart) : 1;
+    for (int e = threadIdx.x; e < nrows * g.ncolp; e += blockDim.x) {
+        const int row = row0 + e / g.ncolp, col = e % g.ncolp;
+        // Hermite triple of this row
+        int h = -1;
+        if (g.role == 0) {
+            const int rk = row - k * g.nh;
+            if (rk < g.nh && valid) h = rk;
+        } else if (valid) {
+            const int nnt = nherm(g.L - 1);
+            if (row < nnt) h = row;
+            else if (row >= g.ntpad && row < g.ntpad + g.nterm) h = nnt + (row - g.ntpad);
+        }
+        double v = 0.0;
+        if (h >= 0 && col < g.ncol) {
+            const Tuv r = herm_tuv(h);
+            const int ma = col / nb_out, mb = col % nb_out;
+            double s = 0.0;
+            const int a0 = g.cart ? ma : 0, a1 = g.cart ? ma + 1 : ncart(la);
+            const int b0 = g.cart ? mb : 0, b1 = g.cart ? mb + 1 : nb_cart;
+            for (int ia = a0; ia < a1; ++ia) {
+                const double cfa = g.cart ? 1.0 : a.Ca[ma * ncart(la) + ia];
+                if (cfa == 0.0) continue;
+                int ax, ay, az;
+                cart_of(la, ia, ax, ay, az);
+                for (int ib = b0; ib < b1; ++ib) {
+                    const double cfb = (g.cart || g.lb < 0) ? 1.0 : a.Cb[mb * ncart(lb) + ib];
+                    if (cfb == 0.0) continue;
+                    int bx = 0, by = 0, bz = 0;
+                    if (g.lb >= 0) cart_of(lb, ib, bx, by, bz);
+                    if (r.t > ax + bx || r.u > ay + by || r.v > az + bz) continue;
+                    s += cfa * cfb * E[0][ax][bx][r.t] * E[1][ay][by][r.u] * E[2][az][bz][r.v];
+                }
+            }
+            v = pref * s;
+            if (g.role == 1 && ((r.t + r.u + r.v) & 1)) v = -v;
+        }
+        Hp[(int64_t)row * g.ncolp + col] = v;
+    }
+}
+
+void launch_pairdata(const PairDataArgs &a, hipStream_t s)
+{
+    const int kblk = a.g.grouped ? 1 : a.g.kmax;
+    const int nblk = a.g.npair * kblk;
+    if (nblk > 0) hipLaunchKernelGGL(pairdata_kernel, dim3(nblk), dim3(128), 0, s, a);
+}
+
+}  // namespace mdx

@@ -1,0 +1,83 @@
+// runtime.h -- host-side state and planning helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdarg>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/mdx.h"
+#include "kernels.h"
+#include "mdx_internal.h"
+
+struct mdx_ctx {
+    int device = 0;
+    int ncu = 0;
+    double *boys = nullptr;      // Boys table
+    double *solid = nullptr;     // Cartesian->solid coefficients, l <= 8
+    size_t solid_off[9] = {};
+    std::vector<std::vector<double>> solid_host;
+    double *tket = nullptr;      // terminal ket matrices
+    size_t tket_off[2][5][5] = {};
+    size_t tket1_off[2][7] = {};
+    std::map<std::tuple<int, int, int, int, int, int>, int> variant;   // autotuner overrides
+};
+
+#define HIP_TRY2(expr)                                                                        \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess) return mdx::fail(MDX_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+namespace mdx {
+
+mdx_status fail(mdx_status s, const char *fmt, ...);
+void build_tket(mdx_ctx *c, int lc, int ld, bool cart, std::vector<double> &T);
+
+// One side of a class in kernel orientation, with its pair list.
+struct SidePlan {
+    SideGeom g{};
+    std::vector<PairRec> pairs;
+};
+
+// kernel families
+enum KernelKind { K_VALU = 0, K_MFMA = 1 };
+
+// A planned class batch (kernel orientation).
+struct ClassPlan {
+    int ncentre = 4;
+    int cart = 0;
+    int la = 0, lb = 0, lc = 0, ld = 0;   // caller's
+    bool swapped = false;                 // kernel bra = caller ket
+    SidePlan bra, ket;
+    EriKey key{};
+    KernelKind kind = K_VALU;
+    int variant = 0;
+    OutMap om{};
+    // ragged output (plans): per kernel-ket bra counts and bases
+    std::vector<int32_t> count;
+    std::vector<int64_t> obase;
+    int64_t out_doubles = 0;
+    // tiles for ragged launches: (J, I0)
+    std::vector<int2> tiles;
+    const double *tket = nullptr;
+};
+
+// workspace layout of one class
+struct WsLayout {
+    size_t pairs_bra, pairs_ket, np_bra, np_ket, prim_bra, prim_ket, H_bra, H_ket;
+    size_t count, obase, tiles;
+    size_t total;
+};
+
+mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
+                      int32_t nket, const int32_t *ket, const int32_t *bra_count, int flags, ClassPlan &cp);
+WsLayout ws_layout(const ClassPlan &cp, size_t base);
+mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
+                         double *out, hipStream_t s, bool upload);
+
+}  // namespace mdx

@@ -1,0 +1,232 @@
+"""ctypes binding of libmdx.so (include/mdx.h).  Argument marshalling only:
+every step of the integral evaluation runs in the library's HIP kernels.
+PyTorch provides device memory and the current stream.
+
+The library is loaded on first use; if it is missing the call raises -- there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmdx.so")
+
+MDX_OK, MDX_EINVAL, MDX_EUNSUPPORTED, MDX_EWORKSPACE, MDX_ENOMEM, MDX_EDEVICE = range(6)
+MDX_SPHERICAL, MDX_CARTESIAN, MDX_FUSED = 0, 1, 2
+
+_p = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_pi32 = ctypes.POINTER(ctypes.c_int32)
+
+
+class MdxShells(ctypes.Structure):
+    _fields_ = [("nshell", _i32), ("center", _p), ("exponent", _p), ("coef", _p),
+                ("l", _pi32), ("nprim", _pi32), ("prim_offset", _pi32)]
+
+
+class MdxBatchDesc(ctypes.Structure):
+    _fields_ = [("ncentre", ctypes.c_int), ("nbra", _i32), ("bra", _pi32), ("nket", _i32),
+                ("ket", _pi32), ("bra_count", _pi32), ("out_offset", ctypes.c_int64)]
+
+
+class MdxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+_lib = None
+_lock = threading.Lock()
+
+EXPORTS = {
+    "mdx_create": (ctypes.c_int, [ctypes.c_int, ctypes.POINTER(_p)]),
+    "mdx_destroy": (None, [_p]),
+    "mdx_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "mdx_last_error": (ctypes.c_char_p, []),
+    "mdx_boys": (ctypes.c_int, [_p, _i32, _p, ctypes.c_int, _p, _p]),
+    "mdx_eri_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32,
+                                                 _i32, _pi32, ctypes.c_int]),
+    "mdx_eri_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32, _pi32,
+                                     ctypes.c_int, _p, _p, ctypes.c_size_t, _p]),
+    "mdx_eri_grad_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32,
+                                                      _pi32, _i32, _pi32, ctypes.c_int]),
+    "mdx_eri_grad_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32,
+                                          _pi32, ctypes.c_int, _p, _p, _p, ctypes.c_size_t, _p]),
+    "mdx_plan_create": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int,
+                                       ctypes.POINTER(MdxBatchDesc), ctypes.c_int, ctypes.POINTER(_p)]),
+    "mdx_plan_workspace_size": (ctypes.c_size_t, [_p]),
+    "mdx_plan_output_size": (ctypes.c_int64, [_p]),
+    "mdx_plan_execute": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _p, _p, ctypes.c_size_t, _p]),
+    "mdx_plan_destroy": (None, [_p]),
+    "mdx_set_variant": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, ctypes.c_int]),
+}
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIBPATH):
+                raise RuntimeError(f"{LIBPATH} is not built (run paper_2506_12501_amd/build.py); "
+                                   "there is no fallback implementation")
+            L = ctypes.CDLL(LIBPATH)
+            for name, (res, args) in EXPORTS.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def check(status: int, what: str):
+    if status != MDX_OK:
+        L = lib()
+        raise MdxError(status, f"{what}: {L.mdx_status_string(status).decode()}: {L.mdx_last_error().decode()}")
+
+
+def _ptr(t) -> int:
+    return t.data_ptr() if t is not None else 0
+
+
+def _i32p(a: np.ndarray):
+    return a.ctypes.data_as(_pi32)
+
+
+def _stream(torch):
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One mdx_ctx for a device (Boys and solid-harmonic tables resident)."""
+    _cache: dict = {}
+
+    def __init__(self, device: int = 0):
+        self.device = device
+        h = _p()
+        check(lib().mdx_create(device, ctypes.byref(h)), "mdx_create")
+        self.handle = h
+
+    @classmethod
+    def get(cls, device: int = 0) -> "Context":
+        if device not in cls._cache:
+            cls._cache[device] = Context(device)
+        return cls._cache[device]
+
+    def set_variant(self, ncentre, la, lb, lc, ld, cartesian, variant):
+        check(lib().mdx_set_variant(self.handle, ncentre, la, lb, lc, ld, int(cartesian), variant),
+              "mdx_set_variant")
+
+
+class DeviceShells:
+    """Shell table: numeric arrays on the device, metadata on the host."""
+
+    def __init__(self, basis, device="cuda", center=None):
+        import torch
+        self.l = np.ascontiguousarray(basis.l, dtype=np.int32)
+        self.nprim = np.ascontiguousarray(basis.nprim, dtype=np.int32)
+        self.poff = np.ascontiguousarray(basis.poff, dtype=np.int32)
+        if center is None:
+            center = torch.as_tensor(np.ascontiguousarray(basis.xyz, dtype=np.float64).reshape(-1), device=device)
+        self.center = center.reshape(-1).contiguous()
+        self.exps = torch.as_tensor(np.ascontiguousarray(basis.exps, dtype=np.float64), device=device)
+        self.coefs = torch.as_tensor(np.ascontiguousarray(basis.coefs, dtype=np.float64), device=device)
+        self.struct = MdxShells(int(self.l.size), _ptr(self.center), _ptr(self.exps), _ptr(self.coefs),
+                                _i32p(self.l), _i32p(self.nprim), _i32p(self.poff))
+
+    def with_center(self, center):
+        new = object.__new__(DeviceShells)
+        new.__dict__.update(self.__dict__)
+        new.center = center.reshape(-1).contiguous()
+        new.struct = MdxShells(int(self.l.size), _ptr(new.center), _ptr(self.exps), _ptr(self.coefs),
+                               _i32p(self.l), _i32p(self.nprim), _i32p(self.poff))
+        return new
+
+
+def nfunc(l: int, cartesian: bool) -> int:
+    return (l + 1) * (l + 2) // 2 if cartesian else 2 * l + 1
+
+
+def _pairs(a) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1, 2))
+    return a
+
+
+def _class_sizes(shells: DeviceShells, ncentre, bra, ket, cartesian):
+    la = int(shells.l[bra[0, 0]])
+    lb = int(shells.l[bra[0, 1]]) if ncentre == 4 else -1
+    lc = int(shells.l[ket[0, 0]])
+    ld = int(shells.l[ket[0, 1]]) if ncentre >= 3 else -1
+    nab = nfunc(la, cartesian) * (nfunc(lb, cartesian) if lb >= 0 else 1)
+    ncd = nfunc(lc, cartesian) * (nfunc(ld, cartesian) if ld >= 0 else 1)
+    return nab, ncd
+
+
+def boys(x, mmax: int, ctx: Context | None = None):
+    """F[m, i] = F_m(x[i]) on the device."""
+    import torch
+    ctx = ctx or Context.get(x.device.index or 0)
+    x = x.contiguous().to(torch.float64)
+    F = torch.empty((mmax + 1, x.numel()), dtype=torch.float64, device=x.device)
+    check(lib().mdx_boys(ctx.handle, x.numel(), _ptr(x), mmax, _ptr(F), _stream(torch)), "mdx_boys")
+    return F
+
+
+def eri(shells: DeviceShells, ncentre: int, bra, ket, cartesian: bool = False, ctx: Context | None = None,
+        out=None):
+    """Dense batch; returns a view of shape [nbra, nab, ncd, nket] over the
+    library's [ij,ab,cd,kl] column-major buffer."""
+    import torch
+    dev = shells.center.device
+    ctx = ctx or Context.get(dev.index or 0)
+    bra = _pairs(bra)
+    ket = _pairs(ket)
+    nbra, nket = bra.shape[0], ket.shape[0]
+    nab, ncd = _class_sizes(shells, ncentre, bra, ket, cartesian)
+    flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
+    L = lib()
+    wsz = L.mdx_eri_workspace_size(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket,
+                                   _i32p(ket), flags)
+    if wsz == 0:
+        check(MDX_EINVAL if not L.mdx_last_error() else MDX_EINVAL, "mdx_eri_workspace_size")
+    ws = torch.empty(wsz // 8 + 32, dtype=torch.float64, device=dev)
+    base = _ptr(ws)
+    aligned = (base + 255) // 256 * 256
+    if out is None:
+        out = torch.empty(nbra * nab * ncd * nket, dtype=torch.float64, device=dev)
+    check(L.mdx_eri_batch(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket, _i32p(ket),
+                          flags, _ptr(out), ctypes.c_void_p(aligned), wsz, _stream(torch)), "mdx_eri_batch")
+    return out.view(nket, ncd, nab, nbra).permute(3, 2, 1, 0)
+
+
+def eri_grad(shells: DeviceShells, ncentre: int, bra, ket, adjoint, cartesian: bool = False,
+             ctx: Context | None = None):
+    """grad[ij, 12, kl] = sum W d(ab|cd)/dX_i; adjoint in the [ij,ab,cd,kl]
+    column-major layout (flat tensor or the [nbra,nab,ncd,nket] view)."""
+    import torch
+    dev = shells.center.device
+    ctx = ctx or Context.get(dev.index or 0)
+    bra = _pairs(bra)
+    ket = _pairs(ket)
+    nbra, nket = bra.shape[0], ket.shape[0]
+    flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
+    L = lib()
+    wsz = L.mdx_eri_grad_workspace_size(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra),
+                                        nket, _i32p(ket), flags)
+    if wsz == 0:
+        check(MDX_EINVAL, "mdx_eri_grad_workspace_size")
+    ws = torch.empty(wsz // 8 + 32, dtype=torch.float64, device=dev)
+    aligned = (_ptr(ws) + 255) // 256 * 256
+    if adjoint.dim() == 4:
+        adjoint = adjoint.permute(3, 2, 1, 0)
+    W = adjoint.contiguous().reshape(-1)
+    grad = torch.empty(nbra * 12 * nket, dtype=torch.float64, device=dev)
+    check(L.mdx_eri_grad_batch(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket,
+                               _i32p(ket), flags, _ptr(W), _ptr(grad), ctypes.c_void_p(aligned), wsz,
+                               _stream(torch)), "mdx_eri_grad_batch")
+    return grad.view(nket, 12, nbra).permute(2, 1, 0)

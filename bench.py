@@ -1,0 +1,235 @@
+#!/usr/bin/env python
+"""Benchmark: FP64 McMurchie-Davidson ERIs on one MI355X.
+
+One step = the whole hot path for the contracted workload (bra/ket pair data
++ Boys + Hermite recursion + ket and bra transforms + store) over both classes
+(dd|dd) and (pd|dd), 256 x 256 shell pairs each (65,536 shellsets per class),
+K = 3 per shell, exponents log-uniform in [0.05, 50], coefficients uniform in
+[0.1, 1], centres uniform in a 10 A cube (seed 0).  Inputs are resident in HBM
+before the timed region; outputs are written to HBM every step.
+
+Prints one JSON line (see the keys at the end of main()).
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X published dense FP64 (vector and matrix)
+PEAK_HBM_GBS = 8000.0
+METRIC = "FP64 ERI shellsets/s + % FP64 peak per L-class; fused-batch vs per-class speedup"
+
+
+class HipEvents:
+    """Raw hipEvent_t handles for the library's profiling hook."""
+
+    def __init__(self, n):
+        self.hip = ctypes.CDLL("libamdhip64.so")
+        self.ev = (ctypes.c_void_p * n)()
+        for i in range(n):
+            h = ctypes.c_void_p()
+            assert self.hip.hipEventCreate(ctypes.byref(h)) == 0
+            self.ev[i] = h
+        self.n = n
+
+    def elapsed_ms(self, i):
+        ms = ctypes.c_float()
+        assert self.hip.hipEventSynchronize(ctypes.c_void_p(self.ev[2 * i + 1])) == 0
+        r = self.hip.hipEventElapsedTime(ctypes.byref(ms), ctypes.c_void_p(self.ev[2 * i]),
+                                         ctypes.c_void_p(self.ev[2 * i + 1]))
+        assert r == 0, r
+        return ms.value
+
+
+class ClassRun:
+    """Preallocated buffers for repeated mdx_eri_batch calls on one class."""
+
+    def __init__(self, native, batch, ctx, torch):
+        self.native, self.batch, self.ctx, self.torch = native, batch, ctx, torch
+        self.sh = native.DeviceShells(batch.basis)
+        self.bra = native._pairs(batch.bra)
+        self.ket = native._pairs(batch.ket)
+        self.nab, self.ncd = native._class_sizes(self.sh, batch.ncentre, self.bra, self.ket, False)
+        L = native.lib()
+        self.wsz = L.mdx_eri_workspace_size(ctx.handle, ctypes.byref(self.sh.struct), batch.ncentre,
+                                            self.bra.shape[0], native._i32p(self.bra), self.ket.shape[0],
+                                            native._i32p(self.ket), 0)
+        if self.wsz == 0:
+            native.check(native.MDX_EINVAL, "workspace size")
+        self.ws = torch.empty(self.wsz // 8 + 64, dtype=torch.float64, device="cuda")
+        self.wsp = (self.ws.data_ptr() + 255) // 256 * 256
+        self.n = self.bra.shape[0] * self.ket.shape[0]
+        self.out = torch.empty(self.n * self.nab * self.ncd, dtype=torch.float64, device="cuda")
+
+    def __call__(self):
+        n = self.native
+        n.check(n.lib().mdx_eri_batch(self.ctx.handle, ctypes.byref(self.sh.struct), self.batch.ncentre,
+                                      self.bra.shape[0], n._i32p(self.bra), self.ket.shape[0], n._i32p(self.ket),
+                                      0, ctypes.c_void_p(self.out.data_ptr()), ctypes.c_void_p(self.wsp),
+                                      self.wsz, n._stream(self.torch)), "mdx_eri_batch")
+
+    def view(self):
+        nb, nk = self.bra.shape[0], self.ket.shape[0]
+        return self.out.view(nk, self.ncd, self.nab, nb).permute(3, 2, 1, 0)
+
+
+def class_flops(batch):
+    from paper_2506_12501_amd import flops as F, workloads as W
+    la, lb, lc, ld = W.parse_class(batch.name)
+    K = int(batch.basis.nprim[0])
+    return F.shellset_flops(la, lb, lc, ld, K, K if lb >= 0 else 1, K, K if ld >= 0 else 1)
+
+
+def cpu_baseline(runs, sample_pairs):
+    """The oracle, as it stands, on the first sample_pairs x sample_pairs shellsets
+    of each class; all host threads (OpenMP).  Also returns its parity against
+    the GPU output of the same shellsets."""
+    import numpy as np
+    from oracle import oracle as O
+    from tests.gpu_util import ATOL, RTOL
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    total_t, total_n = 0.0, 0
+    worst_abs, worst_rel, nbad, nchk = 0.0, 0.0, 0, 0
+    for r in runs:
+        b = r.batch
+        bra, ket = b.bra[:sample_pairs], b.ket[:sample_pairs]
+        t0 = time.perf_counter()
+        ref = O.eri(b.basis, b.ncentre, bra, ket)
+        total_t += time.perf_counter() - t0
+        total_n += bra.shape[0] * ket.shape[0]
+        got = r.view()[:sample_pairs, :, :, :sample_pairs].cpu().numpy()
+        err = np.abs(got - ref)
+        ok = (err <= ATOL) | (err <= RTOL * np.abs(ref))
+        nbad += int(np.count_nonzero(~ok))
+        nchk += ok.size
+        worst_abs = max(worst_abs, float(err.max()))
+        worst_rel = max(worst_rel, float(np.max(err / np.maximum(np.abs(ref), 1e-300) * (err > ATOL))))
+    return {"value": total_n / total_t, "unit": "shellsets/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{sample_pairs}x{sample_pairs} shellsets of each class (first pairs of the workload), "
+                      f"{total_n} shellsets, {total_t:.1f} s"}, \
+           {"checked": nchk, "failed": nbad, "max_abs_err": worst_abs, "max_rel_err_above_atol": worst_rel,
+            "tolerance": "per element |gpu-oracle| <= 1e-12 or <= 1e-10 |oracle|"}
+
+
+def load_traffic(kernel_tag):
+    """HBM bytes per launch from profiles/<tag>_traffic.json, if it was
+    measured on the current kernel source."""
+    import hashlib
+    p = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    src = os.path.join(ROOT, "paper_2506_12501_amd", "csrc", "eri_mfma.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if d.get("source_sha256_16") != h:
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--npair", type=int, default=256)
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the integral batches shard "
+                                   "across GPUs by ket-pair blocks (see DESIGN.md), but no multi-GPU "
+                                   "run is part of this build", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    from paper_2506_12501_amd import native, workloads as W
+
+    ctx = native.Context.get(0)
+    runs = [ClassRun(native, W.config2(name, npair=args.npair, seed=0), ctx, torch) for name in W.C2_CLASSES]
+    nshell = sum(r.n for r in runs)
+
+    def step():
+        for r in runs:
+            r()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # integral-kernel events through the library hook: launch i of the timed
+    # region uses pair i; classes alternate in call order
+    ev = HipEvents(2 * len(runs) * args.steps)
+    native.check(native.lib().mdx_set_profile_events(ctx.handle, ev.ev, ev.n), "profile hook")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    t1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    native.check(native.lib().mdx_set_profile_events(ctx.handle, None, 0), "profile hook off")
+    ms_step = t0.elapsed_time(t1) / args.steps
+
+    per_class = {}
+    for ci, r in enumerate(runs):
+        ks = [ev.elapsed_ms(s * len(runs) + ci) for s in range(args.steps)]
+        kms = sum(ks) / len(ks)
+        fl = class_flops(r.batch) * r.n
+        per_class[r.batch.name] = {
+            "shellsets": r.n, "kernel_ms": kms, "algorithmic_gflop": fl / 1e9,
+            "kernel_tflops": fl / (kms * 1e-3) / 1e12,
+            "pct_fp64_peak": 100.0 * fl / (kms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "shellsets_per_s_kernel": r.n / (kms * 1e-3),
+        }
+    dom = runs[0].batch.name
+    pc = per_class[dom]
+    traffic = load_traffic("eri_mfma_dddd_k3")
+    roofline = {"bound": "mfma", "achieved": pc["kernel_tflops"], "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": pc["kernel_tflops"] / PEAK_FP64_TFLOPS, "traffic": traffic,
+                "kernel": "eri_mfma_kernel (dd|dd) K=3, 65,536 shellsets per launch",
+                "flops_per_launch": pc["algorithmic_gflop"] * 1e9}
+
+    cpu, parity = (None, None)
+    if not args.no_cpu:
+        cpu, parity = cpu_baseline(runs, args.cpu_sample)
+
+    total_flops = sum(class_flops(r.batch) * r.n for r in runs)
+    rec = {
+        "metric": METRIC,
+        "value": nshell / (ms_step * 1e-3),
+        "unit": "shellsets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "contracted (dd|dd) + (pd|dd), K=3 per shell, 256x256 shell pairs per class "
+                               "(65,536 shellsets each), zeta log-U[0.05,50], c U[0.1,1], 10 A box, seed 0",
+                   "classes": [r.batch.name for r in runs], "shellsets_per_step": nshell},
+        "step_tflops_algorithmic": total_flops / (ms_step * 1e-3) / 1e12,
+        "step_pct_fp64_peak": 100.0 * total_flops / (ms_step * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+        "per_class": per_class,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_sample": parity,
+        "wall_s_timed": wall,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

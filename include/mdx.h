@@ -189,6 +189,17 @@ mdx_status mdx_plan_execute(mdx_plan *plan, const mdx_shells *shells, double *ou
                             size_t ws_bytes, mdx_stream_t stream);
 void mdx_plan_destroy(mdx_plan *plan);
 
+/*
+ * Profiling hook.  With nevents >= 2, every integral-kernel launch made
+ * through this context records hipEventRecord(events[2i]) just before and
+ * hipEventRecord(events[2i+1]) just after the kernel on the call's stream,
+ * i = (launch count since this call) mod (nevents/2).  The events are
+ * hipEvent_t handles created and owned by the caller.  nevents = 0 (or a null
+ * array) switches the hook off.  Returns MDX_EINVAL for a null context or an
+ * odd/negative count.
+ */
+mdx_status mdx_set_profile_events(mdx_ctx *ctx, void *const *events, int nevents);
+
 /* Tile-shape override used by the autotuner: kernel variant for one class
  * key; see the Python autotuner for the meaning of `variant`.  Returns
  * MDX_EINVAL for an unknown class/variant.  Affects later plans/calls. */

@@ -243,6 +243,8 @@ mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, 
     a.nket = (int)nk;
     a.boys = c->boys;
     a.Tket = cp.tket;
+    a.nab = cp.bra.g.ncol;
+    a.ncd = cp.ket.g.ncol;
     a.om = cp.om;
     a.om.out = out;
     int nblocks;
@@ -259,8 +261,16 @@ mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, 
     }
     a.ntile_total = nblocks;
     if (nblocks == 0) return MDX_OK;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (c->prof_events.size() >= 2) {
+        const size_t np = c->prof_events.size() / 2, i = c->prof_count++ % np;
+        ev0 = c->prof_events[2 * i];
+        ev1 = c->prof_events[2 * i + 1];
+        HIP_TRY2(hipEventRecord(ev0, s));
+    }
     bool ok = cp.kind == K_VALU ? eri_valu_launch(cp.key, a, nblocks, s)
                                 : eri_mfma_launch(cp.key, a, nblocks, cp.variant, s);
+    if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
     if (!ok) return fail(MDX_EUNSUPPORTED, "kernel instance missing");
     HIP_TRY2(hipGetLastError());
     return MDX_OK;

@@ -22,6 +22,8 @@ struct EriArgs {
     const double *boys;       // Boys table
     const double *Tket;       // terminal ket matrix [ncart(LK) pad 4][ncolp] (MFMA kernel)
     int ntile_total;          // number of tiles (persistent kernels)
+    int nqmax;                // MFMA kernel: primitive quartets held in LDS at once
+    int nab, ncd;             // functions per bra / ket pair (kernel orientation)
     int *counter;             // work counter (persistent kernels)
     OutMap om;
 };

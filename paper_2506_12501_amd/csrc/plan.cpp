@@ -23,3 +23,14 @@ extern "C" mdx_status mdx_set_variant(mdx_ctx *c, int ncentre, int la, int lb, i
     c->variant[std::make_tuple(ncentre, la, lb, lc, ld, (flags & MDX_CARTESIAN) ? 1 : 0)] = variant;
     return MDX_OK;
 }
+
+extern "C" mdx_status mdx_set_profile_events(mdx_ctx *c, void *const *events, int nevents)
+{
+    if (!c) return mdx::fail(MDX_EINVAL, "null context");
+    if (nevents < 0 || (nevents & 1)) return mdx::fail(MDX_EINVAL, "nevents = %d must be even and >= 0", nevents);
+    c->prof_events.clear();
+    c->prof_count = 0;
+    if (events)
+        for (int i = 0; i < nevents; ++i) c->prof_events.push_back((hipEvent_t)events[i]);
+    return MDX_OK;
+}

@@ -25,6 +25,8 @@ struct mdx_ctx {
     size_t tket_off[2][5][5] = {};
     size_t tket1_off[2][7] = {};
     std::map<std::tuple<int, int, int, int, int, int>, int> variant;   // autotuner overrides
+    std::vector<hipEvent_t> prof_events;   // profiling hook (pairs)
+    size_t prof_count = 0;
 };
 
 #define HIP_TRY2(expr)                                                                        \

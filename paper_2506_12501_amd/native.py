@@ -63,6 +63,7 @@ EXPORTS = {
     "mdx_plan_output_size": (ctypes.c_int64, [_p]),
     "mdx_plan_execute": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _p, _p, ctypes.c_size_t, _p]),
     "mdx_plan_destroy": (None, [_p]),
+    "mdx_set_profile_events": (ctypes.c_int, [_p, ctypes.POINTER(_p), ctypes.c_int]),
     "mdx_set_variant": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, ctypes.c_int]),
 }

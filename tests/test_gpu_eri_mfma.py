@@ -1,0 +1,83 @@
+"""Integral parity, GPU vs CPU oracle: classes on the matrix-core kernel."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2506_12501_amd import workloads as W
+from tests.gpu_util import assert_close
+
+pytestmark = pytest.mark.gpu
+
+
+def run(batch, cartesian=False):
+    from paper_2506_12501_amd import native
+    sh = native.DeviceShells(batch.basis)
+    got = native.eri(sh, batch.ncentre, batch.bra, batch.ket, cartesian=cartesian).cpu().numpy()
+    ref = O.eri(batch.basis, batch.ncentre, batch.bra, batch.ket, cartesian=cartesian)
+    return got, ref
+
+
+@pytest.mark.parametrize("name", ["(dd|dd)", "(pd|dd)", "(dp|dd)", "(dd|pd)"])
+def test_config2_classes_contracted(name):
+    # config-2 distributions (K=3, zeta in [0.05, 50], 10 A box) on a few pairs
+    b = W.make_class_batch(name, 5, 3, 3, 10.0, 0.05, 50.0, 0.1, 1.0, seed=21)
+    got, ref = run(b)
+    assert_close(got, ref, name)
+
+
+@pytest.mark.parametrize("name", ["(dd|pp)", "(dd|ds)", "(dp|dp)", "(dp|pp)", "(dp|ds)", "(pp|dd)"])
+def test_mid_classes(name):
+    b = W.make_class_batch(name, 4, 3, 2, 6.0, 0.1, 30.0, 0.1, 1.0, seed=22)
+    got, ref = run(b)
+    assert_close(got, ref, name)
+
+
+def test_dddd_cartesian():
+    b = W.make_class_batch("(dd|dd)", 3, 2, 2, 6.0, 0.1, 30.0, 0.1, 1.0, seed=23)
+    got, ref = run(b, cartesian=True)
+    assert_close(got, ref, "(dd|dd) cart")
+
+
+@pytest.mark.parametrize("name", ["(ff|ff)", "(gg|gg)"])
+def test_config4_high_l(name):
+    b = W.config4(name, nbra=4, nket=3, seed=24)
+    got, ref = run(b)
+    assert_close(got, ref, name)
+
+
+@pytest.mark.parametrize("name", ["(d|dd)", "(f|dd)", "(g|dd)", "(h|dd)", "(i|dd)"])
+def test_config4_three_centre(name):
+    b = W.config4(name, nbra=6, nket=5, seed=25)
+    got, ref = run(b)
+    assert_close(got, ref, name)
+
+
+def test_contracted_three_centre_aux():
+    # contracted aux shell: primitives summed into [0]^(m) before the recursion
+    b = W.make_class_batch("(f|dd)", 5, 3, 4, 5.0, 0.1, 20.0, 0.1, 1.0, seed=26)
+    got, ref = run(b)
+    assert_close(got, ref, "(f|dd) K=4")
+
+
+def test_mixed_contraction_degrees():
+    # pairs of one class with different K in one batch (padding rows)
+    rng = np.random.default_rng(27)
+    sb = W.ShellBuilder()
+    bra, ket = [], []
+    for i in range(4):
+        ids = []
+        for _ in range(2):
+            K = int(rng.integers(1, 4))
+            z = np.exp(rng.uniform(np.log(0.1), np.log(20), K))
+            ids.append(sb.add(rng.uniform(0, 8, 3), 2, z, rng.uniform(0.2, 1, K) * W.prim_norm(z, 2)))
+        bra.append(ids)
+    for i in range(3):
+        ids = []
+        for _ in range(2):
+            K = int(rng.integers(1, 4))
+            z = np.exp(rng.uniform(np.log(0.1), np.log(20), K))
+            ids.append(sb.add(rng.uniform(0, 8, 3), 2, z, rng.uniform(0.2, 1, K) * W.prim_norm(z, 2)))
+        ket.append(ids)
+    b = W.ClassBatch("(dd|dd)", 4, sb.basis(), np.array(bra, dtype=np.int32), np.array(ket, dtype=np.int32))
+    got, ref = run(b)
+    assert_close(got, ref, "(dd|dd) mixed K")

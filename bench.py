@@ -141,7 +141,21 @@ def main():
     ap.add_argument("--npair", type=int, default=256)
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only copy this many MiB device-to-device (HBM counter calibration)")
+    ap.add_argument("--classes", default=None, help="comma-separated subset of the workload's classes")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n * 8}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the integral batches shard "
                                    "across GPUs by ket-pair blocks (see DESIGN.md), but no multi-GPU "
@@ -152,8 +166,17 @@ def main():
     from paper_2506_12501_amd import native, workloads as W
 
     ctx = native.Context.get(0)
-    runs = [ClassRun(native, W.config2(name, npair=args.npair, seed=0), ctx, torch) for name in W.C2_CLASSES]
+    names = args.classes.split(",") if args.classes else W.C2_CLASSES
+    runs = [ClassRun(native, W.config2(name, npair=args.npair, seed=0), ctx, torch) for name in names]
     nshell = sum(r.n for r in runs)
+
+    # autotuner (untimed): fastest kernel variant per class on this workload
+    tuning = {}
+    if not args.no_tune:
+        from paper_2506_12501_amd import autotune
+        for r in runs:
+            best, times = autotune.tune(ctx, r.sh, r.batch.ncentre, r.bra, r.ket, r, reps=2, cache=False)
+            tuning[r.batch.name] = {"variant": best, "ms": {str(k): v for k, v in times.items()}}
 
     def step():
         for r in runs:
@@ -223,6 +246,7 @@ def main():
         "step_tflops_algorithmic": total_flops / (ms_step * 1e-3) / 1e12,
         "step_pct_fp64_peak": 100.0 * total_flops / (ms_step * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
         "per_class": per_class,
+        "tuning": tuning,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,

@@ -200,9 +200,14 @@ void mdx_plan_destroy(mdx_plan *plan);
  */
 mdx_status mdx_set_profile_events(mdx_ctx *ctx, void *const *events, int nevents);
 
-/* Tile-shape override used by the autotuner: kernel variant for one class
- * key; see the Python autotuner for the meaning of `variant`.  Returns
- * MDX_EINVAL for an unknown class/variant.  Affects later plans/calls. */
+/*
+ * Kernel variant for one class (used by the autotuner).  The class is given
+ * by ncentre and the caller's l values (lb / ld ignored for a single-function
+ * side) plus MDX_CARTESIAN in flags.  variant 0 = register (one lane per
+ * shellset) kernel; 1, 2, ... = matrix-core kernel tile shapes; -1 = back to
+ * the default choice.  Returns MDX_EINVAL if the class has no such variant.
+ * Affects calls and plans made afterwards through this context.
+ */
 mdx_status mdx_set_variant(mdx_ctx *ctx, int ncentre, int la, int lb, int lc, int ld, int flags,
                            int variant);
 

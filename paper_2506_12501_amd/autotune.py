@@ -1,0 +1,112 @@
+"""Autotuner: per class, time every compiled kernel variant on the caller's
+batch and keep the fastest (replaces the paper's compile-time tile choice,
+Sec. 3.1).  Results are cached as JSON keyed by device architecture, class
+and contraction degrees, and applied through mdx_set_variant.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+from . import native
+
+CACHE = os.environ.get("MDX_TUNE_CACHE", os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json"))
+
+
+def _class_of(shells: "native.DeviceShells", ncentre, bra, ket):
+    la = int(shells.l[bra[0, 0]])
+    lb = int(shells.l[bra[0, 1]]) if ncentre == 4 else -1
+    lc = int(shells.l[ket[0, 0]])
+    ld = int(shells.l[ket[0, 1]]) if ncentre >= 3 else -1
+    Kb = int(shells.nprim[bra[0, 0]]) * (int(shells.nprim[bra[0, 1]]) if ncentre == 4 else 1)
+    Kk = int(shells.nprim[ket[0, 0]]) * (int(shells.nprim[ket[0, 1]]) if ncentre >= 3 else 1)
+    return la, lb, lc, ld, Kb, Kk
+
+
+def key_string(arch, ncentre, la, lb, lc, ld, cartesian, Kb, Kk):
+    return f"{arch}|{ncentre}|{la},{lb},{lc},{ld}|{'cart' if cartesian else 'sph'}|K{Kb}x{Kk}"
+
+
+def variants(ctx: "native.Context", ncentre, la, lb, lc, ld, cartesian) -> list:
+    """Variant ids the library has for this class (probing mdx_set_variant)."""
+    L = native.lib()
+    out = []
+    for v in range(0, 32):
+        st = L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), int(cartesian), v)
+        if st == native.MDX_OK:
+            out.append(v)
+        elif v > 0:
+            break
+    L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), int(cartesian), -1)
+    return out
+
+
+def time_call(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    best = float("inf")
+    for _ in range(reps):
+        t0.record()
+        fn()
+        t1.record()
+        torch.cuda.synchronize()
+        best = min(best, t0.elapsed_time(t1))
+    return best
+
+
+def tune(ctx, shells, ncentre, bra, ket, call, cartesian=False, reps=3, cache=True):
+    """call(): runs the batch once with the context's current variant.
+    Returns (best_variant, {variant: ms})."""
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    arch = getattr(props, "gcnArchName", "gfx950")
+    la, lb, lc, ld, Kb, Kk = _class_of(shells, ncentre, bra, ket)
+    key = key_string(arch, ncentre, la, lb, lc, ld, cartesian, Kb, Kk)
+    L = native.lib()
+    times = {}
+    for v in variants(ctx, ncentre, la, lb, lc, ld, cartesian):
+        native.check(L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), int(cartesian), v),
+                     "mdx_set_variant")
+        times[v] = time_call(call, reps)
+    best = min(times, key=times.get)
+    native.check(L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), int(cartesian), best),
+                 "mdx_set_variant")
+    if cache:
+        data = load_cache()
+        data[key] = {"variant": best, "ms": times}
+        save_cache(data)
+    return best, times
+
+
+def load_cache(path: str = CACHE) -> dict:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(data: dict, path: str = CACHE) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply_cache(ctx, path: str = CACHE) -> int:
+    """Apply every cached choice for this device; returns how many."""
+    import torch
+    arch = getattr(torch.cuda.get_device_properties(0), "gcnArchName", "gfx950")
+    n = 0
+    for key, rec in load_cache(path).items():
+        a, nc, ls, kind, _ = key.split("|")
+        if a != arch:
+            continue
+        la, lb, lc, ld = (int(x) for x in ls.split(","))
+        st = native.lib().mdx_set_variant(ctx.handle, int(nc), la, max(lb, 0), lc, max(ld, 0),
+                                          int(kind == "cart"), int(rec["variant"]))
+        n += st == native.MDX_OK
+    return n

@@ -128,7 +128,7 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
     const int var = it != c->variant.end() ? it->second : -1;
     const bool has_valu = eri_valu_has(cp.key), has_mfma = eri_mfma_has(cp.key);
     if (var == 0 && has_valu) cp.kind = K_VALU;
-    else if (var >= 1 && has_mfma) { cp.kind = K_MFMA; cp.variant = var; }
+    else if (var >= 1 && var <= eri_mfma_variants(cp.key)) { cp.kind = K_MFMA; cp.variant = var; }
     else if (has_valu) cp.kind = K_VALU;
     else if (has_mfma) cp.kind = K_MFMA;
     else

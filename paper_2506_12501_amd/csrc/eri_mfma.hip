@@ -18,13 +18,13 @@
 //  lane (c, g) holds X[row 4r+g][col c], which is B[k=g][n=c] of k-step r, so
 //  the K order of the bra GEMM is permuted to match (no data movement).
 //
-// [r]^(0) follows the recursion of Eq. (31) in three one-index sweeps, each in
-// registers: per (quartet, v) a lane raises z then y, writing the columns
-// [0 u v]^(m) into the table; per (quartet, u, v) a lane then raises x along
-// its own column and overwrites it with [t u v]^(0).  The table is a dense
-// (L+1)^3 cube indexed (t,u,v), so [p+q] sits at offset(p) + offset(q):
-// per-lane row offsets plus compile-time ket offsets.
+// [r]^(0) follows the recursion of Eq. (31) in three one-axis sweeps (z, then
+// y per column v, then x per column (u, v)), each of compile-time length and
+// unrolled in registers.  The table is a dense (L+1)^3 cube indexed (t,u,v),
+// so [p+q] sits at offset(p) + offset(q): per-lane row offsets plus
+// compile-time ket offsets.
 #include <algorithm>
+#include <utility>
 
 #include "eri_common.h"
 #include "kernels.h"
@@ -70,25 +70,130 @@ __device__ __forceinline__ int pick4(const int (&v)[N], int base, int g)
     return (g & 2) ? ((g & 1) ? a3 : a2) : ((g & 1) ? a1 : a0);
 }
 
-// one-index Hermite recursion along a column (Eq. (31) for one axis): c holds
-// the column of index r, p that of r-1; column 0 has entries m <= M, column r
-// has m <= M-r.  Produces column r+1:  n[m] = r p[m+1] + X c[m+1],  m <= M-r-1
+// [r]^(0) of one primitive quartet, Eq. (31), as three one-axis sweeps over
+// the table cube[(t*D + u)*D + v] (D = L+1).  Each sweep handles columns of a
+// compile-time length, so it is fully unrolled: no predication, no wasted
+// work on short columns, recursion state in registers.
+//   z sweep:  [0 0 v]^(m) for v <= L, m <= L-v   -> cube position (m, 0, v)
+//   y sweep:  per v, [0 u v]^(m), m <= M-u (M = L-v) -> (m, u, v)
+//   x sweep:  per (u, v), [t u v]^(0), t <= M (M = L-u-v) -> (t, u, v)
+// Intermediate columns are stored at (m, u, v) and overwritten in place by
+// the lane that owns them.
 template <int D>
-__device__ __forceinline__ void rstep(double (&c)[D], double (&p)[D], int r, int M, double X)
+__device__ __forceinline__ void zsweep(double *__restrict__ cq, const double *__restrict__ S, double Z)
 {
-    // in place, ascending m: c[m+1] and p[m+1] are still the old values at step m
+    constexpr int L = D - 1;
+    double c[D], p[D];
 #pragma unroll
-    for (int m = 0; m + 1 < D; ++m) {
-        const double old = c[m];
-        c[m] = (m <= M - r - 1) ? fma((double)r, p[m + 1], X * c[m + 1]) : 0.0;
-        p[m] = old;
+    for (int m = 0; m < D; ++m) {
+        c[m] = S[m];
+        p[m] = 0.0;
     }
-    p[D - 1] = c[D - 1];
-    c[D - 1] = 0.0;
+#pragma unroll
+    for (int v = 0; v <= L; ++v) {
+#pragma unroll
+        for (int m = 0; m <= L - v; ++m) cq[(m * D) * D + v] = c[m];
+        if (v < L) {
+            double n[D];
+#pragma unroll
+            for (int m = 0; m <= L - v - 1; ++m) n[m] = v > 0 ? fma((double)v, p[m + 1], Z * c[m + 1]) : Z * c[m + 1];
+#pragma unroll
+            for (int m = 0; m <= L - v - 1; ++m) {
+                p[m] = c[m];
+                c[m] = n[m];
+            }
+            p[L - v] = c[L - v];
+        }
+    }
 }
 
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB>
-__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(2)))
+template <int D, int M>
+__device__ __forceinline__ void ysweep(double *__restrict__ cv /* cube + v */, double Y)
+{
+    double c[M + 1], p[M + 1];
+#pragma unroll
+    for (int m = 0; m <= M; ++m) {
+        c[m] = cv[(m * D) * D];
+        p[m] = 0.0;
+    }
+#pragma unroll
+    for (int u = 1; u <= M; ++u) {
+        double n[M + 1];
+#pragma unroll
+        for (int m = 0; m <= M - u; ++m) n[m] = u > 1 ? fma((double)(u - 1), p[m + 1], Y * c[m + 1]) : Y * c[m + 1];
+#pragma unroll
+        for (int m = 0; m <= M - u; ++m) cv[(m * D + u) * D] = n[m];
+#pragma unroll
+        for (int m = 0; m <= M - u; ++m) {
+            p[m] = c[m];
+            c[m] = n[m];
+        }
+        p[M - u + 1] = c[M - u + 1];
+    }
+}
+
+template <int D, int M>
+__device__ __forceinline__ void xsweep(double *__restrict__ cuv /* cube + u*D + v */, double X)
+{
+    double c[M + 1], p[M + 1];
+#pragma unroll
+    for (int m = 0; m <= M; ++m) {
+        c[m] = cuv[(m * D) * D];
+        p[m] = 0.0;
+    }
+#pragma unroll
+    for (int t = 1; t <= M; ++t) {
+        double n[M + 1];
+#pragma unroll
+        for (int m = 0; m <= M - t; ++m) n[m] = t > 1 ? fma((double)(t - 1), p[m + 1], X * c[m + 1]) : X * c[m + 1];
+        cuv[(t * D) * D] = n[0];
+#pragma unroll
+        for (int m = 0; m <= M - t; ++m) {
+            p[m] = c[m];
+            c[m] = n[m];
+        }
+        p[M - t + 1] = c[M - t + 1];
+    }
+}
+
+// y sweep for column v = L - M, executed by wave (v % NW); lanes over quartets
+template <int D, int NW, int M>
+__device__ __forceinline__ void ypass(double *cube, const double *PQ, int NQ, int w, int lane)
+{
+    constexpr int L = D - 1, v = L - M, CUBE = D * D * D;
+    if (w == v % NW)
+        for (int q = lane; q < NQ; q += 64) ysweep<D, M>(cube + q * CUBE + v, PQ[q * 4 + 1]);
+}
+
+// x sweep for all columns (u, v) with u + v = L - M, executed by wave
+// (M % NW); lanes over (quartet, column)
+template <int D, int NW, int M>
+__device__ __forceinline__ void xpass(double *cube, const double *PQ, int NQ, int w, int lane)
+{
+    constexpr int L = D - 1, s = L - M, CUBE = D * D * D;
+    if (w == (L - M) % NW)
+        for (int e = lane; e < NQ * (s + 1); e += 64) {
+            const int q = e / (s + 1), v = e - q * (s + 1), u = s - v;
+            xsweep<D, M>(cube + q * CUBE + u * D + v, PQ[q * 4]);
+        }
+}
+
+template <int D, int NW, int... Ms>
+__device__ __forceinline__ void ypasses(double *cube, const double *PQ, int NQ, int w, int lane,
+                                        std::integer_sequence<int, Ms...>)
+{
+    (ypass<D, NW, Ms>(cube, PQ, NQ, w, lane), ...);
+}
+
+template <int D, int NW, int... Ms>
+__device__ __forceinline__ void xpasses(double *cube, const double *PQ, int NQ, int w, int lane,
+                                        std::integer_sequence<int, Ms...>)
+{
+    (xpass<D, NW, Ms>(cube, PQ, NQ, w, lane), ...);
+}
+
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE>
+__global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 eri_mfma_kernel(EriArgs a)
 {
     constexpr int L = LB + LK;
@@ -165,12 +270,6 @@ eri_mfma_kernel(EriArgs a)
     const int64_t omult = a.om.count ? (int64_t)nI : a.om.mult;
 
     for (int grp = 0; grp < NG; ++grp) {
-        d4 O[NTAB][NTG];
-#pragma unroll
-        for (int mm = 0; mm < NTAB; ++mm)
-#pragma unroll
-            for (int n = 0; n < NTG; ++n) O[mm][n] = d4{0.0, 0.0, 0.0, 0.0};
-
         for (int ch = 0; ch < nch; ++ch) {
             const int tile0 = ch * NW * MTW + w * MTW;
             const int row_lo = ch * NW * MTW * 16;
@@ -250,50 +349,12 @@ eri_mfma_kernel(EriArgs a)
                 }
                 if (fresh) {
                     __syncthreads();
-                    // sweep 1 (lane per quartet q and z-index v): raise z to v, then y,
-                    // writing the columns [0 u v]^(m) at cube positions (m, u, v)
-                    if (tid < NQ * D) {
-                        const int q = tid / D, v = tid - q * D;
-                        double cc[D], pp[D];
-#pragma unroll
-                        for (int m = 0; m < D; ++m) {
-                            cc[m] = S[q * D + m];
-                            pp[m] = 0.0;
-                        }
-                        const double Z = PQ[q * 4 + 2], Yv = PQ[q * 4 + 1];
-                        for (int r = 0; r < v; ++r) rstep<D>(cc, pp, r, L, Z);
-#pragma unroll
-                        for (int m = 0; m < D; ++m) pp[m] = 0.0;
-                        double *col = cube + q * CUBE + v;
-                        const int M = L - v;
-                        for (int u = 0; u <= M; ++u) {
-#pragma unroll
-                            for (int m = 0; m < D; ++m)
-                                if (m <= M - u) col[(m * D + u) * D] = cc[m];
-                            if (u < M) rstep<D>(cc, pp, u, M, Yv);
-                        }
-                    }
+                    // three one-axis sweeps, Eq. (31)
+                    if (tid < NQ) zsweep<D>(cube + tid * CUBE, S + tid * D, PQ[tid * 4 + 2]);
                     __syncthreads();
-                    // sweep 2 (lane per quartet q and (u, v)): raise x along the column
-                    for (int e = tid; e < NQ * NUV; e += NT) {
-                        const int q = e / NUV;
-                        int r2 = e - q * NUV, s = 0;
-                        while ((s + 1) * (s + 2) / 2 <= r2) ++s;
-                        const int v = r2 - s * (s + 1) / 2, u = s - v;
-                        const int M = L - s;
-                        double *col = cube + q * CUBE + u * D + v;
-                        double cc[D], pp[D];
-#pragma unroll
-                        for (int m = 0; m < D; ++m) {
-                            cc[m] = (m <= M) ? col[m * D * D] : 0.0;
-                            pp[m] = 0.0;
-                        }
-                        const double X = PQ[q * 4];
-                        for (int t = 0; t <= M; ++t) {
-                            col[t * D * D] = cc[0];
-                            if (t < M) rstep<D>(cc, pp, t, M, X);
-                        }
-                    }
+                    ypasses<D, NW>(cube, PQ, NQ, w, lane, std::make_integer_sequence<int, D>{});
+                    __syncthreads();
+                    xpasses<D, NW>(cube, PQ, NQ, w, lane, std::make_integer_sequence<int, D>{});
                 }
 #pragma unroll
                 for (int i = 0; i < HKR; ++i) {
@@ -318,7 +379,7 @@ eri_mfma_kernel(EriArgs a)
                 }
                 // terminal Hermites: early contraction over ket primitives
                 const double wt = kp[kk].wt;
-#pragma unroll 2
+#pragma unroll
                 for (int s = 0; s < KT; ++s) {
                     const int to = kt[4 * s + g];
 #pragma unroll
@@ -338,6 +399,11 @@ eri_mfma_kernel(EriArgs a)
                     for (int n = 0; n < NTG; ++n) acc[tt][n] = mfma(Y[tt][s], bv[n], acc[tt][n]);
             }
 
+            d4 O[NTAB][NTG];
+#pragma unroll
+            for (int mm = 0; mm < NTAB; ++mm)
+#pragma unroll
+                for (int n = 0; n < NTG; ++n) O[mm][n] = d4{0.0, 0.0, 0.0, 0.0};
             // bra transform: O += H_bra X, K order permuted to the accumulator layout;
             // the next tile's H_bra values are fetched while this tile multiplies
             double hb[2][4][NTAB];
@@ -368,31 +434,35 @@ eri_mfma_kernel(EriArgs a)
                             for (int n = 0; n < NTG; ++n) O[mm][n] = mfma(hb[cur][r][mm], acc[tt][n][r], O[mm][n]);
                 }
             }
-        }
 
-        // sum the waves' partial bra transforms and store this column group
+            // sum the waves' partial bra transforms and store this column group
+            // (a shellset with several row chunks accumulates through the output)
 #pragma unroll
-        for (int mm = 0; mm < NTAB; ++mm) {
-            __syncthreads();
-            if (w > 0) {
+            for (int mm = 0; mm < NTAB; ++mm) {
+                __syncthreads();
+                if (w > 0) {
 #pragma unroll
-                for (int n = 0; n < NTG; ++n)
+                    for (int n = 0; n < NTG; ++n)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) red[(((w - 1) * NTG + n) * 4 + r) * 64 + lane] = O[mm][n][r];
-            }
-            __syncthreads();
-            if (w == 0) {
+                        for (int r = 0; r < 4; ++r) red[(((w - 1) * NTG + n) * 4 + r) * 64 + lane] = O[mm][n][r];
+                }
+                __syncthreads();
+                if (w == 0) {
 #pragma unroll
-                for (int n = 0; n < NTG; ++n)
+                    for (int n = 0; n < NTG; ++n)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        double v = O[mm][n][r];
-                        for (int ww = 1; ww < NW; ++ww) v += red[(((ww - 1) * NTG + n) * 4 + r) * 64 + lane];
-                        const int ab = 16 * mm + 4 * r + g;
-                        const int cd = grp * GW + 16 * n + c;
-                        if (ab < a.nab && cd < a.ncd)
-                            a.om.out[obase + (int64_t)I * a.om.sI + omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd])] = v;
-                    }
+                        for (int r = 0; r < 4; ++r) {
+                            double v = O[mm][n][r];
+                            for (int ww = 1; ww < NW; ++ww) v += red[(((ww - 1) * NTG + n) * 4 + r) * 64 + lane];
+                            const int ab = 16 * mm + 4 * r + g;
+                            const int cd = grp * GW + 16 * n + c;
+                            if (ab < a.nab && cd < a.ncd) {
+                                double *dst = a.om.out + obase + (int64_t)I * a.om.sI +
+                                              omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd]);
+                                *dst = ch == 0 ? v : *dst + v;
+                            }
+                        }
+                }
             }
         }
     }
@@ -418,7 +488,7 @@ static size_t mfma_lds_bytes(int nqmax)
            (size_t)(NH + NTPAD + 4 * KT) * 4;
 }
 
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB>
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE>
 static bool launch_mfma(const EriArgs &a0, int nblocks, hipStream_t s)
 {
     EriArgs a = a0;
@@ -426,48 +496,75 @@ static bool launch_mfma(const EriArgs &a0, int nblocks, hipStream_t s)
     a.nqmax = GB ? 1 : std::min(a.bra.kmax, (NW * MTW * 16) / NHB + 2);
     const size_t lds = mfma_lds_bytes<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB>(a.nqmax);
     if (lds > 160 * 1024) return false;
-    auto kern = eri_mfma_kernel<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB>;
-    if (lds > 64 * 1024) hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    auto kern = eri_mfma_kernel<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB, WPE>;
+    static size_t lds_set = 0;   // largest dynamic LDS granted to this instance so far
+    if (lds > 64 * 1024 && lds > lds_set) {
+        if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+            return false;
+        lds_set = lds;
+    }
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(64 * NW), lds, s, a);
     return true;
 }
 
-// key (LB, LK, NAB, NCD, GB) -> shape
-#define MDX_MFMA_INSTANCES(X)                                                     \
-    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4)   /* (dd|dd)                    */      \
-    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4)   /* (dd|dp), (pd|dd) swapped   */      \
-    X(4, 2, 25, 9, false, 2, 1, 1, 5, 4)    /* (dd|pp)                    */      \
-    X(4, 2, 25, 5, false, 2, 1, 1, 5, 4)    /* (dd|ds)                    */      \
-    X(3, 3, 15, 15, false, 1, 1, 1, 5, 4)   /* (dp|dp)                    */      \
-    X(3, 2, 15, 9, false, 1, 1, 1, 5, 4)    /* (dp|pp)                    */      \
-    X(3, 2, 15, 5, false, 1, 1, 1, 5, 4)    /* (dp|ds)                    */      \
-    X(2, 2, 9, 9, false, 1, 1, 1, 5, 4)     /* (pp|pp)                    */      \
-    X(4, 4, 36, 36, false, 3, 3, 3, 5, 4)   /* (dd|dd) Cartesian          */      \
-    X(4, 3, 36, 18, false, 3, 2, 2, 5, 4)   /* (dd|dp) Cartesian          */      \
-    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3)   /* (ff|ff)                    */      \
-    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4)   /* (gg|gg)                    */      \
-    X(2, 4, 5, 25, true, 1, 2, 2, 1, 1)     /* (d|dd)                     */      \
-    X(3, 4, 7, 25, true, 1, 2, 2, 1, 1)     /* (f|dd)                     */      \
-    X(4, 4, 9, 25, true, 1, 2, 2, 1, 1)     /* (g|dd)                     */      \
-    X(5, 4, 11, 25, true, 1, 2, 2, 2, 1)    /* (h|dd)                     */      \
-    X(6, 4, 13, 25, true, 1, 2, 2, 2, 1)    /* (i|dd)                     */      \
-    X(0, 4, 1, 25, true, 1, 2, 2, 1, 1)     /* (s|dd)                     */      \
-    X(1, 4, 3, 25, true, 1, 2, 2, 1, 1)     /* (p|dd)                     */
+// Instances: class key (LB, LK, NAB, NCD, GB) and tile shape
+// (NTAB, NTCD, NTG, MTW, NW, WPE).  Several shapes per key are variants 1, 2, ...
+// in listing order; the autotuner picks one per class.
+#define MDX_MFMA_INSTANCES(X)                                                         \
+    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 2)   /* (dd|dd)                    */       \
+    X(4, 4, 25, 25, false, 2, 2, 2, 3, 4, 2)                                          \
+    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 1)                                          \
+    X(4, 4, 25, 25, false, 2, 2, 1, 5, 4, 2)                                          \
+    X(4, 4, 25, 25, false, 2, 2, 2, 3, 2, 3)                                          \
+    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2)   /* (dd|dp), (pd|dd) swapped   */       \
+    X(4, 3, 25, 15, false, 2, 1, 1, 3, 4, 2)                                          \
+    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 1)                                          \
+    X(4, 3, 25, 15, false, 2, 1, 1, 3, 2, 3)                                          \
+    X(4, 2, 25, 9, false, 2, 1, 1, 5, 4, 2)    /* (dd|pp)                    */       \
+    X(4, 2, 25, 5, false, 2, 1, 1, 5, 4, 2)    /* (dd|ds)                    */       \
+    X(3, 3, 15, 15, false, 1, 1, 1, 5, 4, 2)   /* (dp|dp)                    */       \
+    X(3, 2, 15, 9, false, 1, 1, 1, 5, 4, 2)    /* (dp|pp)                    */       \
+    X(3, 2, 15, 5, false, 1, 1, 1, 5, 4, 2)    /* (dp|ds)                    */       \
+    X(2, 2, 9, 9, false, 1, 1, 1, 5, 4, 2)     /* (pp|pp)                    */       \
+    X(4, 4, 36, 36, false, 3, 3, 3, 5, 4, 2)   /* (dd|dd) Cartesian          */       \
+    X(4, 3, 36, 18, false, 3, 2, 2, 5, 4, 2)   /* (dd|dp) Cartesian          */       \
+    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 2)   /* (ff|ff)                    */       \
+    X(6, 6, 49, 49, false, 4, 4, 1, 2, 3, 2)                                          \
+    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 1)                                          \
+    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 2)   /* (gg|gg)                    */       \
+    X(8, 8, 81, 81, false, 6, 6, 1, 3, 4, 2)                                          \
+    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 1)                                          \
+    X(2, 4, 5, 25, true, 1, 2, 2, 1, 1, 2)     /* (d|dd)                     */       \
+    X(3, 4, 7, 25, true, 1, 2, 2, 1, 1, 2)     /* (f|dd)                     */       \
+    X(4, 4, 9, 25, true, 1, 2, 2, 1, 1, 2)     /* (g|dd)                     */       \
+    X(5, 4, 11, 25, true, 1, 2, 2, 2, 1, 2)    /* (h|dd)                     */       \
+    X(6, 4, 13, 25, true, 1, 2, 2, 2, 1, 2)    /* (i|dd)                     */       \
+    X(0, 4, 1, 25, true, 1, 2, 2, 1, 1, 2)     /* (s|dd)                     */       \
+    X(1, 4, 3, 25, true, 1, 2, 2, 1, 1, 2)     /* (p|dd)                     */
 
-bool eri_mfma_has(const EriKey &k)
+static bool key_is(const EriKey &k, int lb, int lk, int nab, int ncd, bool gb)
 {
-#define MDX_HAS(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw) \
-    if (!k.GK && k.LB == lb && k.LK == lk && k.NAB == nab && k.NCD == ncd && k.GB == gb) return true;
-    MDX_MFMA_INSTANCES(MDX_HAS)
-#undef MDX_HAS
-    return false;
+    return !k.GK && k.LB == lb && k.LK == lk && k.NAB == nab && k.NCD == ncd && k.GB == gb;
 }
 
-bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int /*variant*/, hipStream_t s)
+int eri_mfma_variants(const EriKey &k)
 {
-#define MDX_TRY(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw)                                  \
-    if (!k.GK && k.LB == lb && k.LK == lk && k.NAB == nab && k.NCD == ncd && k.GB == gb)       \
-        return launch_mfma<lb, lk, ntab, ntcd, ntg, mtw, nw, gb>(a, nblocks, s);
+    int n = 0;
+#define MDX_COUNT(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe) \
+    if (key_is(k, lb, lk, nab, ncd, gb)) ++n;
+    MDX_MFMA_INSTANCES(MDX_COUNT)
+#undef MDX_COUNT
+    return n;
+}
+
+bool eri_mfma_has(const EriKey &k) { return eri_mfma_variants(k) > 0; }
+
+bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s)
+{
+    int n = 0;
+#define MDX_TRY(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe)                     \
+    if (key_is(k, lb, lk, nab, ncd, gb) && ++n == variant)                             \
+        return launch_mfma<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe>(a, nblocks, s);
     MDX_MFMA_INSTANCES(MDX_TRY)
 #undef MDX_TRY
     return false;

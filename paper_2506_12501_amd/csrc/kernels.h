@@ -42,6 +42,7 @@ void launch_pairdata(const PairDataArgs &a, hipStream_t s);
 bool eri_valu_has(const EriKey &k);
 bool eri_valu_launch(const EriKey &k, const EriArgs &a, int nblocks, hipStream_t s);
 bool eri_mfma_has(const EriKey &k);
+int eri_mfma_variants(const EriKey &k);
 bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
 
 void launch_boys(const double *x, int n, int mmax, double *F, const double *tab, hipStream_t s);

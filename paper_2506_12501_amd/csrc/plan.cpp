@@ -20,7 +20,29 @@ extern "C" void mdx_plan_destroy(mdx_plan *) {}
 extern "C" mdx_status mdx_set_variant(mdx_ctx *c, int ncentre, int la, int lb, int lc, int ld, int flags, int variant)
 {
     if (!c) return mdx::fail(MDX_EINVAL, "null context");
-    c->variant[std::make_tuple(ncentre, la, lb, lc, ld, (flags & MDX_CARTESIAN) ? 1 : 0)] = variant;
+    if (ncentre < 2 || ncentre > 4 || la < 0 || lc < 0 || (ncentre == 4 && lb < 0) || (ncentre >= 3 && ld < 0) ||
+        la > 8 || lb > 8 || lc > 8 || ld > 8)
+        return mdx::fail(MDX_EINVAL, "mdx_set_variant: bad class");
+    const bool cart = (flags & MDX_CARTESIAN) != 0;
+    const auto key_t = std::make_tuple(ncentre, la, ncentre == 4 ? lb : -1, lc, ncentre >= 3 ? ld : -1, cart ? 1 : 0);
+    if (variant < 0) {
+        c->variant.erase(key_t);
+        return MDX_OK;
+    }
+    // class key in kernel orientation, as plan_class derives it
+    const bool bra2 = ncentre == 4, ket2 = ncentre >= 3;
+    int Lb = la + (bra2 ? lb : 0), Lk = lc + (ket2 ? ld : 0);
+    int nab = mdx::nfunc(la, cart) * (bra2 ? mdx::nfunc(lb, cart) : 1);
+    int ncd = mdx::nfunc(lc, cart) * (ket2 ? mdx::nfunc(ld, cart) : 1);
+    bool gb = !bra2 && !cart, gk = !ket2 && !cart;
+    if (ncentre == 4 && Lb < Lk) {
+        std::swap(Lb, Lk);
+        std::swap(nab, ncd);
+    }
+    const mdx::EriKey k{Lb, Lk, nab, ncd, gb, gk};
+    const bool ok = variant == 0 ? mdx::eri_valu_has(k) : variant <= mdx::eri_mfma_variants(k);
+    if (!ok) return mdx::fail(MDX_EINVAL, "mdx_set_variant: class has no variant %d", variant);
+    c->variant[key_t] = variant;
     return MDX_OK;
 }
 

@@ -1,0 +1,40 @@
+"""Every compiled kernel variant of a class must match the oracle (the
+autotuner may pick any of them)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2506_12501_amd import workloads as W
+from tests.gpu_util import assert_close
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("(dd|dd)", 3), ("(pd|dd)", 3), ("(ff|ff)", 1), ("(gg|gg)", 1), ("(pp|pp)", 1), ("(dd|ps)", 2),
+         ("(f|dd)", 2)]
+
+
+@pytest.mark.parametrize("name,K", CASES)
+def test_all_variants_match_oracle(name, K):
+    from paper_2506_12501_amd import autotune, native
+    b = W.make_class_batch(name, 5, 3, K, 6.0, 0.05, 30.0, 0.1, 1.0, seed=31)
+    ref = O.eri(b.basis, b.ncentre, b.bra, b.ket)
+    ctx = native.Context.get(0)
+    la, lb, lc, ld = W.parse_class(name)
+    vs = autotune.variants(ctx, b.ncentre, la, lb, lc, ld, False)
+    assert vs, name
+    sh = native.DeviceShells(b.basis)
+    L = native.lib()
+    try:
+        for v in vs:
+            native.check(L.mdx_set_variant(ctx.handle, b.ncentre, la, max(lb, 0), lc, max(ld, 0), 0, v), "variant")
+            got = native.eri(sh, b.ncentre, b.bra, b.ket).cpu().numpy()
+            assert_close(got, ref, f"{name} variant {v}")
+    finally:
+        L.mdx_set_variant(ctx.handle, b.ncentre, la, max(lb, 0), lc, max(ld, 0), 0, -1)
+
+
+def test_unknown_variant_rejected():
+    from paper_2506_12501_amd import native
+    ctx = native.Context.get(0)
+    st = native.lib().mdx_set_variant(ctx.handle, 4, 0, 0, 0, 0, 0, 17)
+    assert st == native.MDX_EINVAL

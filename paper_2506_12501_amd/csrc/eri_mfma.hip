@@ -74,15 +74,17 @@ __device__ __forceinline__ int pick4(const int (&v)[N], int base, int g)
 // the table cube[(t*D + u)*D + v] (D = L+1).  Each sweep handles columns of a
 // compile-time length, so it is fully unrolled: no predication, no wasted
 // work on short columns, recursion state in registers.
-//   z sweep:  [0 0 v]^(m) for v <= L, m <= L-v   -> cube position (m, 0, v)
-//   y sweep:  per v, [0 u v]^(m), m <= M-u (M = L-v) -> (m, u, v)
+//   z, y sweep: per v, raise z to v in registers, then y:
+//               [0 u v]^(m), m <= M-u (M = L-v) -> cube position (m, u, v)
 //   x sweep:  per (u, v), [t u v]^(0), t <= M (M = L-u-v) -> (t, u, v)
 // Intermediate columns are stored at (m, u, v) and overwritten in place by
 // the lane that owns them.
-template <int D>
-__device__ __forceinline__ void zsweep(double *__restrict__ cq, const double *__restrict__ S, double Z)
+template <int D, int M>
+__device__ __forceinline__ void ysweep(double *__restrict__ cv /* cube + v */, const double *__restrict__ S, double Y,
+                                       double Z)
 {
-    constexpr int L = D - 1;
+    // z first: [0 0 v]^(m), m <= M, for v = L - M, from [0]^(m) (registers only)
+    constexpr int L = D - 1, V = L - M;
     double c[D], p[D];
 #pragma unroll
     for (int m = 0; m < D; ++m) {
@@ -90,30 +92,21 @@ __device__ __forceinline__ void zsweep(double *__restrict__ cq, const double *__
         p[m] = 0.0;
     }
 #pragma unroll
-    for (int v = 0; v <= L; ++v) {
+    for (int v = 1; v <= V; ++v) {
+        double n[D];
 #pragma unroll
-        for (int m = 0; m <= L - v; ++m) cq[(m * D) * D + v] = c[m];
-        if (v < L) {
-            double n[D];
+        for (int m = 0; m <= L - v; ++m) n[m] = v > 1 ? fma((double)(v - 1), p[m + 1], Z * c[m + 1]) : Z * c[m + 1];
 #pragma unroll
-            for (int m = 0; m <= L - v - 1; ++m) n[m] = v > 0 ? fma((double)v, p[m + 1], Z * c[m + 1]) : Z * c[m + 1];
-#pragma unroll
-            for (int m = 0; m <= L - v - 1; ++m) {
-                p[m] = c[m];
-                c[m] = n[m];
-            }
-            p[L - v] = c[L - v];
+        for (int m = 0; m <= L - v; ++m) {
+            p[m] = c[m];
+            c[m] = n[m];
         }
+        p[L - v + 1] = c[L - v + 1];
     }
-}
-
-template <int D, int M>
-__device__ __forceinline__ void ysweep(double *__restrict__ cv /* cube + v */, double Y)
-{
-    double c[M + 1], p[M + 1];
+    // then y: [0 u v]^(m), m <= M - u
 #pragma unroll
     for (int m = 0; m <= M; ++m) {
-        c[m] = cv[(m * D) * D];
+        cv[(m * D) * D] = c[m];
         p[m] = 0.0;
     }
 #pragma unroll
@@ -156,13 +149,13 @@ __device__ __forceinline__ void xsweep(double *__restrict__ cuv /* cube + u*D + 
     }
 }
 
-// y sweep for column v = L - M, executed by wave (v % NW); lanes over quartets
+// z/y sweep for column v = L - M, executed by wave (v % NW); lanes over quartets
 template <int D, int NW, int M>
-__device__ __forceinline__ void ypass(double *cube, const double *PQ, int NQ, int w, int lane)
+__device__ __forceinline__ void ypass(double *cube, const double *S, const double *PQ, int NQ, int w, int lane)
 {
     constexpr int L = D - 1, v = L - M, CUBE = D * D * D;
     if (w == v % NW)
-        for (int q = lane; q < NQ; q += 64) ysweep<D, M>(cube + q * CUBE + v, PQ[q * 4 + 1]);
+        for (int q = lane; q < NQ; q += 64) ysweep<D, M>(cube + q * CUBE + v, S + q * D, PQ[q * 4 + 1], PQ[q * 4 + 2]);
 }
 
 // x sweep for all columns (u, v) with u + v = L - M, executed by wave
@@ -179,10 +172,10 @@ __device__ __forceinline__ void xpass(double *cube, const double *PQ, int NQ, in
 }
 
 template <int D, int NW, int... Ms>
-__device__ __forceinline__ void ypasses(double *cube, const double *PQ, int NQ, int w, int lane,
+__device__ __forceinline__ void ypasses(double *cube, const double *S, const double *PQ, int NQ, int w, int lane,
                                         std::integer_sequence<int, Ms...>)
 {
-    (ypass<D, NW, Ms>(cube, PQ, NQ, w, lane), ...);
+    (ypass<D, NW, Ms>(cube, S, PQ, NQ, w, lane), ...);
 }
 
 template <int D, int NW, int... Ms>
@@ -223,8 +216,9 @@ eri_mfma_kernel(EriArgs a)
         J = t.x;
         I = t.y;
     } else {
-        J = blockIdx.x / a.tiles_per_J;
-        I = blockIdx.x % a.tiles_per_J;
+        const int t = xcd_tile(blockIdx.x, gridDim.x);
+        J = t / a.tiles_per_J;
+        I = t % a.tiles_per_J;
     }
     const int nI = a.om.count ? a.om.count[J] : a.nbra;
     if (I >= nI) return;   // whole workgroup
@@ -245,9 +239,11 @@ eri_mfma_kernel(EriArgs a)
     double *cube = smem;
     const int cube_words = (SEPRED || nqmax * CUBE > RED) ? nqmax * CUBE : RED;
     double *red = SEPRED ? smem + cube_words : cube;
-    double *S = smem + cube_words + (SEPRED ? RED : 0);   // [nqmax][D]
-    double *PQ = S + nqmax * D;                          // [nqmax][4]
-    double *Hk = PQ + nqmax * 4;                         // [NTPAD][GW]
+    const int kkmax = a.ket.kmax;
+    double *S = smem + cube_words + (SEPRED ? RED : 0);   // [kkmax][nqmax][D]
+    double *PQ = S + kkmax * nqmax * D;                  // [kkmax][nqmax][4]
+    double *Wt = PQ + kkmax * nqmax * 4;                 // [kkmax] terminal weights
+    double *Hk = Wt + kkmax;                             // [NTPAD][GW]
     double *Tk = Hk + NTPAD * GW;                        // [4*KT][GW]
     int *tuvt = (int *)(Tk + 4 * KT * GW);               // [NH] packed t | u<<8 | v<<16
     int *kq = tuvt + NH;                                 // [NTPAD] cube offsets, non-terminal ket
@@ -303,27 +299,18 @@ eri_mfma_kernel(EriArgs a)
                 for (int s = 0; s < KT; ++s) Y[tt][s] = 0.0;
             }
 
-            for (int kk = 0; kk < nkk; ++kk) {
-                const bool fresh = !(resident && grp > 0);
-                __syncthreads();   // previous k-loop reads of the table / Hk are complete
-                // ket block of this primitive: global loads now, LDS store after the recursion
-                double hv[HKR];
-                {
-                    const double *src = HkG + (int64_t)kk * RPB * NCDP + grp * GW;
-#pragma unroll
-                    for (int i = 0; i < HKR; ++i) {
-                        const int e = tid + i * NT;
-                        hv[i] = e < NTPAD * GW ? src[(e / GW) * NCDP + (e % GW)] : 0.0;
-                    }
-                }
-                if (fresh && tid < NQ) {
-                    // [0]^(m), Eq. (27), times the primitive weights
+            const bool fresh = !(resident && grp > 0);
+            if (fresh) {
+                // [0]^(m) of every primitive quartet of the chunk, Eq. (27), times the
+                // primitive weights; a single-function solid bra sums its primitives here
+                for (int e = tid; e < NQ * nkk; e += NT) {
+                    const int kk = e / NQ, q = e - kk * NQ;
                     double Sm[D];
 #pragma unroll
                     for (int m = 0; m <= L; ++m) Sm[m] = 0.0;
                     const PrimRec K = kp[kk];
                     double X = 0.0, Yv = 0.0, Z = 0.0;
-                    const int b0 = GB ? 0 : kb_lo + tid, b1 = GB ? npb : kb_lo + tid + 1;
+                    const int b0 = GB ? 0 : kb_lo + q, b1 = GB ? npb : kb_lo + q + 1;
                     for (int ib = b0; ib < b1; ++ib) {
                         const PrimRec B = bp[ib];
                         const double pq = B.p + K.p;
@@ -341,20 +328,35 @@ eri_mfma_kernel(EriArgs a)
                             f *= m2r;
                         }
                     }
+                    double *Sq = S + (kk * nqmax + q) * D;
 #pragma unroll
-                    for (int m = 0; m <= L; ++m) S[tid * D + m] = Sm[m];
-                    PQ[tid * 4 + 0] = X;
-                    PQ[tid * 4 + 1] = Yv;
-                    PQ[tid * 4 + 2] = Z;
+                    for (int m = 0; m <= L; ++m) Sq[m] = Sm[m];
+                    double *pq4 = PQ + (kk * nqmax + q) * 4;
+                    pq4[0] = X;
+                    pq4[1] = Yv;
+                    pq4[2] = Z;
+                    if (q == 0) Wt[kk] = K.wt;
+                }
+            }
+
+            for (int kk = 0; kk < nkk; ++kk) {
+                __syncthreads();   // previous k-loop reads of the table / Hk are complete
+                // ket block of this primitive: global loads now, LDS store after the recursion
+                double hv[HKR];
+                {
+                    const double *src = HkG + (int64_t)kk * RPB * NCDP + grp * GW;
+#pragma unroll
+                    for (int i = 0; i < HKR; ++i) {
+                        const int e = tid + i * NT;
+                        hv[i] = e < NTPAD * GW ? src[(e / GW) * NCDP + (e % GW)] : 0.0;
+                    }
                 }
                 if (fresh) {
+                    // one-axis sweeps of Eq. (31): z and y per column v, then x per (u, v)
+                    const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
+                    ypasses<D, NW>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, D>{});
                     __syncthreads();
-                    // three one-axis sweeps, Eq. (31)
-                    if (tid < NQ) zsweep<D>(cube + tid * CUBE, S + tid * D, PQ[tid * 4 + 2]);
-                    __syncthreads();
-                    ypasses<D, NW>(cube, PQ, NQ, w, lane, std::make_integer_sequence<int, D>{});
-                    __syncthreads();
-                    xpasses<D, NW>(cube, PQ, NQ, w, lane, std::make_integer_sequence<int, D>{});
+                    xpasses<D, NW>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, D>{});
                 }
 #pragma unroll
                 for (int i = 0; i < HKR; ++i) {
@@ -378,7 +380,7 @@ eri_mfma_kernel(EriArgs a)
                     }
                 }
                 // terminal Hermites: early contraction over ket primitives
-                const double wt = kp[kk].wt;
+                const double wt = Wt[kk];
 #pragma unroll
                 for (int s = 0; s < KT; ++s) {
                     const int to = kt[4 * s + g];
@@ -476,7 +478,7 @@ struct MfmaShape {
 };
 
 template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB>
-static size_t mfma_lds_bytes(int nqmax)
+static size_t mfma_lds_bytes(int nqmax, int kkmax)
 {
     constexpr int L = LB + LK, D = L + 1, CUBE = D * D * D, NH = nherm(L);
     constexpr int NTPAD = round_up(nherm(LK - 1), 4);
@@ -484,7 +486,7 @@ static size_t mfma_lds_bytes(int nqmax)
     constexpr bool SEPRED = NTCD / NTG > 1;
     constexpr size_t RED = (size_t)(NW - 1) * NTG * 256;
     const size_t cube_words = SEPRED ? (size_t)nqmax * CUBE + RED : std::max((size_t)nqmax * CUBE, RED);
-    return (cube_words + (size_t)nqmax * (D + 4) + (size_t)(NTPAD + 4 * KT) * NTG * 16) * 8 +
+    return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(NTPAD + 4 * KT) * NTG * 16) * 8 +
            (size_t)(NH + NTPAD + 4 * KT) * 4;
 }
 
@@ -494,7 +496,7 @@ static bool launch_mfma(const EriArgs &a0, int nblocks, hipStream_t s)
     EriArgs a = a0;
     constexpr int NHB = GB ? ncart(LB) : nherm(LB);
     a.nqmax = GB ? 1 : std::min(a.bra.kmax, (NW * MTW * 16) / NHB + 2);
-    const size_t lds = mfma_lds_bytes<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB>(a.nqmax);
+    const size_t lds = mfma_lds_bytes<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB>(a.nqmax, a.ket.kmax);
     if (lds > 160 * 1024) return false;
     auto kern = eri_mfma_kernel<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB, WPE>;
     static size_t lds_set = 0;   // largest dynamic LDS granted to this instance so far

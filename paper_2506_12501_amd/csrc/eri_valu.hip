@@ -35,8 +35,9 @@ __global__ void __launch_bounds__(64) eri_valu_kernel(EriArgs a)
         J = t.x;
         I = t.y + (int)threadIdx.x;
     } else {
-        J = blockIdx.x / a.tiles_per_J;
-        I = (blockIdx.x % a.tiles_per_J) * 64 + (int)threadIdx.x;
+        const int t = xcd_tile(blockIdx.x, gridDim.x);
+        J = t / a.tiles_per_J;
+        I = (t % a.tiles_per_J) * 64 + (int)threadIdx.x;
     }
     const int nI = a.om.count ? a.om.count[J] : a.nbra;
     if (I >= nI) return;

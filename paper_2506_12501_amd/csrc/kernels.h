@@ -7,6 +7,15 @@ namespace mdx {
 
 __device__ __forceinline__ double rsqrt_d(double x) { return 1.0 / sqrt(x); }
 
+// Blocks are dealt to the 8 XCDs round-robin.  Renumber them so that each XCD
+// receives a contiguous range of work items (consecutive bra pairs of a ket
+// pair share that XCD's L2 and its output cache lines).
+__device__ __forceinline__ int xcd_tile(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7, k = b >> 3;
+    return x * q + min(x, r) + k;
+}
+
 // class key of an integral kernel (kernel orientation)
 struct EriKey {
     int LB, LK;     // total Hermite order of bra and ket

@@ -149,8 +149,35 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         nrows = g.rows_per_block;
         Hp = a.H + (int64_t)pair * g.pair_stride + (int64_t)k * g.rows_per_block * g.ncolp;
     }
-    const int nb_cart = g.lb >= 0 ? ncart(lb) : 1;
     const int nb_out = g.lb >= 0 ? nfunc(lb, g.cart) : 1;
+    const int na_out = nfunc(la, g.cart);
+    // nonzero Cartesian->solid terms of every output function, both centres
+    // (at most 10 nonzero terms per real solid harmonic for l <= 7; one per Cartesian)
+    constexpr int NF = PD_ED * (PD_ED + 1) / 2, NTM = 10;
+    __shared__ int ta_n[NF], tb_n[NF];
+    __shared__ int ta_c[NF][NTM][3], tb_c[NF][NTM][3];
+    __shared__ double ta_w[NF][NTM], tb_w[NF][NTM];
+    for (int side = 0; side < 2; ++side) {
+        const int l = side == 0 ? la : lb, nout = side == 0 ? na_out : nb_out;
+        const double *C = side == 0 ? a.Ca : a.Cb;
+        const bool unit = side == 1 && g.lb < 0;
+        for (int mo = threadIdx.x; mo < nout; mo += blockDim.x) {
+            int n = 0;
+            for (int ic = 0; ic < ncart(l); ++ic) {
+                const double w = unit ? 1.0 : (g.cart ? (ic == mo ? 1.0 : 0.0) : C[mo * ncart(l) + ic]);
+                if (w == 0.0 || n == NTM) continue;
+                int x, y, z;
+                cart_of(l, ic, x, y, z);
+                (side == 0 ? ta_c : tb_c)[mo][n][0] = x;
+                (side == 0 ? ta_c : tb_c)[mo][n][1] = y;
+                (side == 0 ? ta_c : tb_c)[mo][n][2] = z;
+                (side == 0 ? ta_w : tb_w)[mo][n] = w;
+                ++n;
+            }
+            (side == 0 ? ta_n : tb_n)[mo] = n;
+        }
+    }
+    __syncthreads();
     for (int e = threadIdx.x; e < nrows * g.ncolp; e += blockDim.x) {
         const int row = row0 + e / g.ncolp, col = e % g.ncolp;
         // Hermite triple of this row
@@ -168,20 +195,12 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
             const Tuv r = herm_tuv(h);
             const int ma = col / nb_out, mb = col % nb_out;
             double s = 0.0;
-            const int a0 = g.cart ? ma : 0, a1 = g.cart ? ma + 1 : ncart(la);
-            const int b0 = g.cart ? mb : 0, b1 = g.cart ? mb + 1 : nb_cart;
-            for (int ia = a0; ia < a1; ++ia) {
-                const double cfa = g.cart ? 1.0 : a.Ca[ma * ncart(la) + ia];
-                if (cfa == 0.0) continue;
-                int ax, ay, az;
-                cart_of(la, ia, ax, ay, az);
-                for (int ib = b0; ib < b1; ++ib) {
-                    const double cfb = (g.cart || g.lb < 0) ? 1.0 : a.Cb[mb * ncart(lb) + ib];
-                    if (cfb == 0.0) continue;
-                    int bx = 0, by = 0, bz = 0;
-                    if (g.lb >= 0) cart_of(lb, ib, bx, by, bz);
+            for (int i = 0; i < ta_n[ma]; ++i) {
+                const int ax = ta_c[ma][i][0], ay = ta_c[ma][i][1], az = ta_c[ma][i][2];
+                for (int j = 0; j < tb_n[mb]; ++j) {
+                    const int bx = tb_c[mb][j][0], by = tb_c[mb][j][1], bz = tb_c[mb][j][2];
                     if (r.t > ax + bx || r.u > ay + by || r.v > az + bz) continue;
-                    s += cfa * cfb * E[0][ax][bx][r.t] * E[1][ay][by][r.u] * E[2][az][bz][r.v];
+                    s += ta_w[ma][i] * tb_w[mb][j] * E[0][ax][bx][r.t] * E[1][ay][by][r.u] * E[2][az][bz][r.v];
                 }
             }
             v = pref * s;

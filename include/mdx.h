@@ -57,6 +57,7 @@ typedef enum {
 #define MDX_SPHERICAL 0    /* real solid harmonics (default)             */
 #define MDX_CARTESIAN 1    /* Cartesian components                       */
 #define MDX_FUSED 2        /* plans: one graph launch, persistent kernels */
+#define MDX_GRADIENT 4     /* mdx_set_variant: choose the backward kernel */
 
 typedef struct mdx_ctx mdx_ctx;
 
@@ -205,8 +206,11 @@ mdx_status mdx_set_profile_events(mdx_ctx *ctx, void *const *events, int nevents
  * by ncentre and the caller's l values (lb / ld ignored for a single-function
  * side) plus MDX_CARTESIAN in flags.  variant 0 = register (one lane per
  * shellset) kernel; 1, 2, ... = matrix-core kernel tile shapes; -1 = back to
- * the default choice.  Returns MDX_EINVAL if the class has no such variant.
- * Affects calls and plans made afterwards through this context.
+ * the default choice.  With MDX_GRADIENT in flags the choice applies to the
+ * backward kernel of mdx_eri_grad_batch instead (tile shapes 1, 2, ...; a
+ * pass whose kernel has fewer shapes uses shape 1).  Returns MDX_EINVAL if
+ * the class has no such variant.  Affects calls and plans made afterwards
+ * through this context.
  */
 mdx_status mdx_set_variant(mdx_ctx *ctx, int ncentre, int la, int lb, int lc, int ld, int flags,
                            int variant);

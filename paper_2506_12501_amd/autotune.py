@@ -24,21 +24,28 @@ def _class_of(shells: "native.DeviceShells", ncentre, bra, ket):
     return la, lb, lc, ld, Kb, Kk
 
 
-def key_string(arch, ncentre, la, lb, lc, ld, cartesian, Kb, Kk):
-    return f"{arch}|{ncentre}|{la},{lb},{lc},{ld}|{'cart' if cartesian else 'sph'}|K{Kb}x{Kk}"
+def key_string(arch, ncentre, la, lb, lc, ld, cartesian, Kb, Kk, gradient=False):
+    kind = ("cart" if cartesian else "sph") + ("+grad" if gradient else "")
+    return f"{arch}|{ncentre}|{la},{lb},{lc},{ld}|{kind}|K{Kb}x{Kk}"
 
 
-def variants(ctx: "native.Context", ncentre, la, lb, lc, ld, cartesian) -> list:
-    """Variant ids the library has for this class (probing mdx_set_variant)."""
+def _flags(cartesian, gradient):
+    return (native.MDX_CARTESIAN if cartesian else 0) | (native.MDX_GRADIENT if gradient else 0)
+
+
+def variants(ctx: "native.Context", ncentre, la, lb, lc, ld, cartesian, gradient=False) -> list:
+    """Variant ids the library has for this class (probing mdx_set_variant);
+    gradient=True: the backward kernel's tile shapes."""
     L = native.lib()
+    fl = _flags(cartesian, gradient)
     out = []
     for v in range(0, 32):
-        st = L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), int(cartesian), v)
+        st = L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), fl, v)
         if st == native.MDX_OK:
             out.append(v)
         elif v > 0:
             break
-    L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), int(cartesian), -1)
+    L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), fl, -1)
     return out
 
 
@@ -58,22 +65,24 @@ def time_call(fn, reps=3):
     return best
 
 
-def tune(ctx, shells, ncentre, bra, ket, call, cartesian=False, reps=3, cache=True):
-    """call(): runs the batch once with the context's current variant.
+def tune(ctx, shells, ncentre, bra, ket, call, cartesian=False, reps=3, cache=True, gradient=False):
+    """call(): runs the batch once with the context's current variant
+    (gradient=True: the backward call, tuning the backward kernel).
     Returns (best_variant, {variant: ms})."""
     import torch
     props = torch.cuda.get_device_properties(0)
     arch = getattr(props, "gcnArchName", "gfx950")
     la, lb, lc, ld, Kb, Kk = _class_of(shells, ncentre, bra, ket)
-    key = key_string(arch, ncentre, la, lb, lc, ld, cartesian, Kb, Kk)
+    key = key_string(arch, ncentre, la, lb, lc, ld, cartesian, Kb, Kk, gradient)
     L = native.lib()
+    fl = _flags(cartesian, gradient)
     times = {}
-    for v in variants(ctx, ncentre, la, lb, lc, ld, cartesian):
-        native.check(L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), int(cartesian), v),
+    for v in variants(ctx, ncentre, la, lb, lc, ld, cartesian, gradient):
+        native.check(L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), fl, v),
                      "mdx_set_variant")
         times[v] = time_call(call, reps)
     best = min(times, key=times.get)
-    native.check(L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), int(cartesian), best),
+    native.check(L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), fl, best),
                  "mdx_set_variant")
     if cache:
         data = load_cache()
@@ -106,7 +115,8 @@ def apply_cache(ctx, path: str = CACHE) -> int:
         if a != arch:
             continue
         la, lb, lc, ld = (int(x) for x in ls.split(","))
-        st = native.lib().mdx_set_variant(ctx.handle, int(nc), la, max(lb, 0), lc, max(ld, 0),
-                                          int(kind == "cart"), int(rec["variant"]))
+        fl = _flags(kind.startswith("cart"), kind.endswith("+grad"))
+        st = native.lib().mdx_set_variant(ctx.handle, int(nc), la, max(lb, 0), lc, max(ld, 0), fl,
+                                          int(rec["variant"]))
         n += st == native.MDX_OK
     return n

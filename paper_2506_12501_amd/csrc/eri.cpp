@@ -10,14 +10,14 @@ namespace mdx {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-static SideGeom make_geom(int la, int lb, bool cart, int role, int npair, int kmax)
+SideGeom make_geom(int la, int lb, bool cart, int role, int npair, int kmax, bool allow_grouped)
 {
     SideGeom g{};
     g.la = la;
     g.lb = lb;
     g.L = la + std::max(lb, 0);
     g.cart = cart ? 1 : 0;
-    g.grouped = (lb < 0 && !cart) ? 1 : 0;
+    g.grouped = (lb < 0 && !cart && allow_grouped && role != 2) ? 1 : 0;
     g.role = role;
     g.npair = npair;
     g.kmax = kmax;
@@ -29,6 +29,13 @@ static SideGeom make_geom(int la, int lb, bool cart, int role, int npair, int km
         g.ntpad = 0;
         g.rows_per_block = role == 0 ? round_up(g.nterm, 16) : g.nterm;
         g.nblocks = 1;
+    } else if (role == 2) {
+        // derivative bra: six blocks of rows up to order L + 1
+        g.nh = nherm(g.L + 1);
+        g.nterm = 0;
+        g.ntpad = 0;
+        g.rows_per_block = round_up(kmax * g.nh, 16);
+        g.nblocks = 6;
     } else if (role == 0) {
         g.nh = nherm(g.L);
         g.nterm = 0;
@@ -46,9 +53,10 @@ static SideGeom make_geom(int la, int lb, bool cart, int role, int npair, int km
     return g;
 }
 
-mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
-                      int32_t nket, const int32_t *ket, const int32_t *bra_count, int flags, ClassPlan &cp)
+mdx_status check_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
+                       int32_t nket, const int32_t *ket, int flags, int l[4])
 {
+    l[0] = l[1] = l[2] = l[3] = -1;
     if (!c) return fail(MDX_EINVAL, "null context");
     if (!sh) return fail(MDX_EINVAL, "null shell table");
     if (ncentre < 2 || ncentre > 4) return fail(MDX_EINVAL, "ncentre = %d (must be 2, 3 or 4)", ncentre);
@@ -58,10 +66,6 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
     if (sh->nshell < 0 || (sh->nshell > 0 && (!sh->l || !sh->nprim || !sh->prim_offset || !sh->center ||
                                                !sh->exponent || !sh->coef)))
         return fail(MDX_EINVAL, "incomplete shell table");
-    const bool cart = (flags & MDX_CARTESIAN) != 0;
-    cp = ClassPlan{};
-    cp.ncentre = ncentre;
-    cp.cart = cart;
     if (nbra == 0 || nket == 0) return MDX_OK;
     const bool bra2 = ncentre == 4, ket2 = ncentre >= 3;
     auto check_shell = [&](int32_t s) -> bool { return s >= 0 && s < sh->nshell && sh->nprim[s] >= 1; };
@@ -80,41 +84,62 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
             if (sh->l[s0] != l0 || (two && sh->l[s1] != l1))
                 return fail(MDX_EINVAL, "%s pair %d: mixed classes in one batch", side ? "ket" : "bra", i);
         }
-        if (side == 0) { cp.la = l0; cp.lb = l1; }
-        else { cp.lc = l0; cp.ld = l1; }
+        l[2 * side] = l0;
+        l[2 * side + 1] = l1;
     }
     const int lmax_pair = MDX_LMAX_4C, lmax_single = MDX_LMAX_3C;
-    auto lok = [&](int l, bool single) { return l >= 0 && l <= (single ? lmax_single : lmax_pair); };
-    if (cp.la < 0 || cp.lc < 0) return fail(MDX_EINVAL, "negative angular momentum");
-    if (!lok(cp.la, !bra2) || (bra2 && !lok(cp.lb, false)) || !lok(cp.lc, !ket2) || (ket2 && !lok(cp.ld, false)))
+    auto lok = [&](int lv, bool single) { return lv >= 0 && lv <= (single ? lmax_single : lmax_pair); };
+    if (l[0] < 0 || l[2] < 0) return fail(MDX_EINVAL, "negative angular momentum");
+    if (!lok(l[0], !bra2) || (bra2 && !lok(l[1], false)) || !lok(l[2], !ket2) || (ket2 && !lok(l[3], false)))
         return fail(MDX_EUNSUPPORTED, "angular momentum beyond the compiled limits (l <= %d per pair shell, %d single)",
                     lmax_pair, lmax_single);
-    if (ncentre == 2 && (cp.lc > lmax_single)) return fail(MDX_EUNSUPPORTED, "2-centre l beyond limit");
+    return MDX_OK;
+}
+
+SidePlan make_side(const mdx_shells *sh, const int32_t *lst, int32_t n, bool two, int l0, int l1, bool cart,
+                   int role, bool allow_grouped)
+{
+    SidePlan sp;
+    sp.pairs.resize(n);
+    int kmax = 1;
+    for (int32_t i = 0; i < n; ++i) {
+        PairRec r{};
+        r.sa = lst[2 * i];
+        r.sb = two ? lst[2 * i + 1] : -1;
+        r.ka = sh->nprim[r.sa];
+        r.kb = two ? sh->nprim[r.sb] : 1;
+        r.offa = sh->prim_offset[r.sa];
+        r.offb = two ? sh->prim_offset[r.sb] : 0;
+        sp.pairs[i] = r;
+        kmax = std::max(kmax, r.ka * r.kb);
+    }
+    sp.g = make_geom(l0, two ? l1 : -1, cart, role, n, kmax, allow_grouped);
+    return sp;
+}
+
+mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
+                      int32_t nket, const int32_t *ket, const int32_t *bra_count, int flags, ClassPlan &cp)
+{
+    int lv[4];
+    mdx_status st = check_class(c, sh, ncentre, nbra, bra, nket, ket, flags, lv);
+    if (st != MDX_OK) return st;
+    const bool cart = (flags & MDX_CARTESIAN) != 0;
+    cp = ClassPlan{};
+    cp.ncentre = ncentre;
+    cp.cart = cart;
+    if (nbra == 0 || nket == 0) return MDX_OK;
+    const bool bra2 = ncentre == 4, ket2 = ncentre >= 3;
+    cp.la = lv[0]; cp.lb = lv[1]; cp.lc = lv[2]; cp.ld = lv[3];
+    if (ncentre == 2 && (cp.lc > MDX_LMAX_3C)) return fail(MDX_EUNSUPPORTED, "2-centre l beyond limit");
 
     const int Lb = cp.la + std::max(cp.lb, 0), Lk = cp.lc + std::max(cp.ld, 0);
     cp.swapped = (ncentre == 4 && Lb < Lk && !bra_count);
     // kernel sides
     for (int side = 0; side < 2; ++side) {
         const bool from_bra = (side == 0) != cp.swapped;
-        const int32_t n = from_bra ? nbra : nket;
-        const int32_t *lst = from_bra ? bra : ket;
-        const bool two = from_bra ? bra2 : ket2;
-        SidePlan &sp = side == 0 ? cp.bra : cp.ket;
-        sp.pairs.resize(n);
-        int kmax = 1;
-        for (int32_t i = 0; i < n; ++i) {
-            PairRec r{};
-            r.sa = lst[2 * i];
-            r.sb = two ? lst[2 * i + 1] : -1;
-            r.ka = sh->nprim[r.sa];
-            r.kb = two ? sh->nprim[r.sb] : 1;
-            r.offa = sh->prim_offset[r.sa];
-            r.offb = two ? sh->prim_offset[r.sb] : 0;
-            sp.pairs[i] = r;
-            kmax = std::max(kmax, r.ka * r.kb);
-        }
         const int l0 = from_bra ? cp.la : cp.lc, l1 = from_bra ? cp.lb : cp.ld;
-        sp.g = make_geom(l0, two ? l1 : -1, cart, side, n, kmax);
+        (side == 0 ? cp.bra : cp.ket) = make_side(sh, from_bra ? bra : ket, from_bra ? nbra : nket,
+                                                  from_bra ? bra2 : ket2, l0, l1, cart, side, true);
     }
     cp.key.LB = cp.bra.g.L;
     cp.key.LK = cp.ket.g.L;

@@ -54,6 +54,36 @@ bool eri_mfma_has(const EriKey &k);
 int eri_mfma_variants(const EriKey &k);
 bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
 
+// Backward kernel arguments.  The derivative side (pair data in the
+// derivative-bra role) supplies the rows; the other side (ket role) is
+// contracted with the adjoint W inside the kernel.
+//   W[I*wsI + J*wsJ + i*wsd + j*wsw]   i: derivative-side function, j: other side
+//   G[I*gsI + J*gsJ + slot*gss] = sum_k M[slot][k] g_k   for slots in wmask,
+//   g_k (k = 0..5) = sum_ij W d(ij)/d{A_x, A_y, A_z, B_x, B_y, B_z} of the
+//   derivative side's two centres.
+struct GradArgs {
+    SideDev dside, wside;
+    int nI, nJ;               // pairs on the derivative / other side
+    const double *boys;
+    const double *Tw;         // terminal matrix of the other side [ncart(LW) pad 4][nwp]
+    int nqmax;
+    int nd, nw, nwp;          // functions per pair (derivative side, other side), other side's column stride
+    const double *W;
+    int64_t wsI, wsJ, wsd, wsw;
+    double *G;
+    int64_t gsI, gsJ, gss;
+    int wmask;
+    signed char M[12][6];
+};
+
+// class key of a backward kernel: Hermite orders of the two sides and
+// 16-column tiles of the derivative side's functions
+struct GradKey {
+    int LD, LW, NTN;
+};
+int eri_grad_variants(const GradKey &k);
+bool eri_grad_launch(const GradKey &k, const GradArgs &a, int nblocks, int variant, hipStream_t s);
+
 void launch_boys(const double *x, int n, int mmax, double *F, const double *tab, hipStream_t s);
 
 }  // namespace mdx

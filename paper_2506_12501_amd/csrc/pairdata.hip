@@ -101,7 +101,9 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         const double XPA = P - Av[ax], XPB = P - B[ax];
         // Eqs. (10), (11) with E^0_00 = 1 (the exponential is applied below)
         E[ax][0][0][0] = 1.0;
-        for (int i = 0; i <= la; ++i) {
+        // the derivative-bra role also needs a+1 and b+1 (d/dA of Eq. (1))
+        const int la_e = la + (g.role == 2), lb_e = lb + (g.role == 2);
+        for (int i = 0; i <= la_e; ++i) {
             if (i > 0)
                 for (int t = 0; t <= i; ++t) {
                     double v = XPA * (t <= i - 1 ? E[ax][i - 1][0][t] : 0.0);
@@ -109,7 +111,7 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
                     if (t + 1 <= i - 1) v += (t + 1) * E[ax][i - 1][0][t + 1];
                     E[ax][i][0][t] = v;
                 }
-            for (int j = 1; j <= lb; ++j)
+            for (int j = 1; j <= lb_e; ++j)
                 for (int t = 0; t <= i + j; ++t) {
                     double v = XPB * (t <= i + j - 1 ? E[ax][i][j - 1][t] : 0.0);
                     if (t > 0) v += i2p * E[ax][i][j - 1][t - 1];
@@ -122,7 +124,7 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         const double dx = Av[0] - B[0], dy = Av[1] - B[1], dz = Av[2] - B[2];
         const double K = valid ? exp(-za * zb / p * (dx * dx + dy * dy + dz * dz)) * ca * cb : 0.0;
         const double pref = K / p;   // + 2 pi^{5/2} on the bra
-        sh_pref = g.role == 0 ? 2.0 * 17.493418327624862 * pref : pref;
+        sh_pref = g.role != 1 ? 2.0 * 17.493418327624862 * pref : pref;
         PrimRec r{};
         r.p = valid ? p : 1.0;
         r.Px = (za * Av[0] + zb * B[0]) / p;
@@ -139,7 +141,7 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
     // rows of this primitive block
     int row0, nrows;
     double *Hp;
-    if (g.role == 0) {
+    if (g.role != 1) {
         row0 = k * g.nh;
         nrows = g.nh;
         if (k == g.kmax - 1) nrows = g.rows_per_block - row0;   // include zero padding
@@ -178,6 +180,45 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         }
     }
     __syncthreads();
+    if (g.role == 2) {
+        // derivative bra: d/dA_i of x_A^a exp(-zeta_a r_A^2) is 2 zeta_a (a+1_i) - a_i (a-1_i)
+        // (likewise for B), so along axis i the Hermite coefficient of the derivative is
+        // 2 zeta_a E^{a+1,b}_t - a_i E^{a-1,b}_t, expanded about the same P up to order L+1.
+        auto e1 = [&](int ax, int i, int j, int t) -> double {
+            return (i >= 0 && j >= 0 && t <= i + j) ? E[ax][i][j][t] : 0.0;
+        };
+        const int64_t dstride = (int64_t)g.rows_per_block * g.ncolp;
+        for (int e = threadIdx.x; e < 6 * nrows * g.ncolp; e += blockDim.x) {
+            const int d = e / (nrows * g.ncolp), rem = e - d * nrows * g.ncolp;
+            const int row = row0 + rem / g.ncolp, col = rem % g.ncolp;
+            const int rk = row - k * g.nh;
+            double v = 0.0;
+            if (valid && rk < g.nh && col < g.ncol) {
+                const Tuv r = herm_tuv(rk);
+                const int tv[3] = {r.t, r.u, r.v};
+                const int dax = d % 3;
+                const bool onA = d < 3;
+                const int ma = col / nb_out, mb = col % nb_out;
+                double s = 0.0;
+                for (int i = 0; i < ta_n[ma]; ++i)
+                    for (int j = 0; j < tb_n[mb]; ++j) {
+                        double f = ta_w[ma][i] * tb_w[mb][j];
+                        for (int ax = 0; ax < 3 && f != 0.0; ++ax) {
+                            const int ai = ta_c[ma][i][ax], bi = tb_c[mb][j][ax], t = tv[ax];
+                            double c;
+                            if (ax != dax) c = e1(ax, ai, bi, t);
+                            else if (onA) c = 2.0 * za * e1(ax, ai + 1, bi, t) - ai * e1(ax, ai - 1, bi, t);
+                            else c = 2.0 * zb * e1(ax, ai, bi + 1, t) - bi * e1(ax, ai, bi - 1, t);
+                            f *= c;
+                        }
+                        s += f;
+                    }
+                v = pref * s;
+            }
+            Hp[d * dstride + (int64_t)row * g.ncolp + col] = v;
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < nrows * g.ncolp; e += blockDim.x) {
         const int row = row0 + e / g.ncolp, col = e % g.ncolp;
         // Hermite triple of this row

@@ -23,8 +23,19 @@ extern "C" mdx_status mdx_set_variant(mdx_ctx *c, int ncentre, int la, int lb, i
     if (ncentre < 2 || ncentre > 4 || la < 0 || lc < 0 || (ncentre == 4 && lb < 0) || (ncentre >= 3 && ld < 0) ||
         la > 8 || lb > 8 || lc > 8 || ld > 8)
         return mdx::fail(MDX_EINVAL, "mdx_set_variant: bad class");
+    if (flags & ~(MDX_CARTESIAN | MDX_GRADIENT)) return mdx::fail(MDX_EINVAL, "mdx_set_variant: unknown flags 0x%x", flags);
     const bool cart = (flags & MDX_CARTESIAN) != 0;
     const auto key_t = std::make_tuple(ncentre, la, ncentre == 4 ? lb : -1, lc, ncentre >= 3 ? ld : -1, cart ? 1 : 0);
+    if (flags & MDX_GRADIENT) {
+        if (variant < 0) {
+            c->grad_variant.erase(key_t);
+            return MDX_OK;
+        }
+        if (variant < 1 || variant > mdx::grad_class_variants(ncentre, la, lb, lc, ld, cart))
+            return mdx::fail(MDX_EINVAL, "mdx_set_variant: class has no backward variant %d", variant);
+        c->grad_variant[key_t] = variant;
+        return MDX_OK;
+    }
     if (variant < 0) {
         c->variant.erase(key_t);
         return MDX_OK;

@@ -24,7 +24,8 @@ struct mdx_ctx {
     double *tket = nullptr;      // terminal ket matrices
     size_t tket_off[2][5][5] = {};
     size_t tket1_off[2][7] = {};
-    std::map<std::tuple<int, int, int, int, int, int>, int> variant;   // autotuner overrides
+    std::map<std::tuple<int, int, int, int, int, int>, int> variant;        // autotuner overrides
+    std::map<std::tuple<int, int, int, int, int, int>, int> grad_variant;   // same, backward kernel
     std::vector<hipEvent_t> prof_events;   // profiling hook (pairs)
     size_t prof_count = 0;
 };
@@ -76,6 +77,15 @@ struct WsLayout {
     size_t total;
 };
 
+SideGeom make_geom(int la, int lb, bool cart, int role, int npair, int kmax, bool allow_grouped);
+SidePlan make_side(const mdx_shells *sh, const int32_t *lst, int32_t n, bool two, int l0, int l1, bool cart,
+                   int role, bool allow_grouped);
+// validates a class batch; l = (l_a, l_b, l_c, l_d), -1 for absent functions
+// (all -1 when the batch is empty)
+mdx_status check_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
+                       int32_t nket, const int32_t *ket, int flags, int l[4]);
+// largest backward-kernel variant count over the passes of a class (0: none)
+int grad_class_variants(int ncentre, int la, int lb, int lc, int ld, bool cart);
 mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
                       int32_t nket, const int32_t *ket, const int32_t *bra_count, int flags, ClassPlan &cp);
 WsLayout ws_layout(const ClassPlan &cp, size_t base);

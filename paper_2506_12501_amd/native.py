@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmdx.so")
 
 MDX_OK, MDX_EINVAL, MDX_EUNSUPPORTED, MDX_EWORKSPACE, MDX_ENOMEM, MDX_EDEVICE = range(6)
-MDX_SPHERICAL, MDX_CARTESIAN, MDX_FUSED = 0, 1, 2
+MDX_SPHERICAL, MDX_CARTESIAN, MDX_FUSED, MDX_GRADIENT = 0, 1, 2, 4
 
 _p = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -194,7 +194,9 @@ def eri(shells: DeviceShells, ncentre: int, bra, ket, cartesian: bool = False, c
     wsz = L.mdx_eri_workspace_size(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket,
                                    _i32p(ket), flags)
     if wsz == 0:
-        check(MDX_EINVAL if not L.mdx_last_error() else MDX_EINVAL, "mdx_eri_workspace_size")
+        # planning failed: the batch call reports the planning status
+        check(L.mdx_eri_batch(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket,
+                              _i32p(ket), flags, None, None, 0, _stream(torch)), "mdx_eri_batch")
     ws = torch.empty(wsz // 8 + 32, dtype=torch.float64, device=dev)
     base = _ptr(ws)
     aligned = (base + 255) // 256 * 256
@@ -220,7 +222,8 @@ def eri_grad(shells: DeviceShells, ncentre: int, bra, ket, adjoint, cartesian: b
     wsz = L.mdx_eri_grad_workspace_size(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra),
                                         nket, _i32p(ket), flags)
     if wsz == 0:
-        check(MDX_EINVAL, "mdx_eri_grad_workspace_size")
+        check(L.mdx_eri_grad_batch(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket,
+                                   _i32p(ket), flags, None, None, None, 0, _stream(torch)), "mdx_eri_grad_batch")
     ws = torch.empty(wsz // 8 + 32, dtype=torch.float64, device=dev)
     aligned = (_ptr(ws) + 255) // 256 * 256
     if adjoint.dim() == 4:

@@ -27,6 +27,11 @@ PEAK_HBM_GBS = 8000.0
 METRIC = "FP64 ERI shellsets/s + % FP64 peak per L-class; fused-batch vs per-class speedup"
 
 
+def log(msg):
+    """progress on stderr; stdout carries only the JSON result line"""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 class HipEvents:
     """Raw hipEvent_t handles for the library's profiling hook."""
 
@@ -80,6 +85,111 @@ class ClassRun:
         return self.out.view(nk, self.ncd, self.nab, nb).permute(3, 2, 1, 0)
 
 
+class GradRun:
+    """Preallocated buffers for repeated mdx_eri_grad_batch calls on one class."""
+
+    def __init__(self, native, batch, ctx, torch, seed=1):
+        from paper_2506_12501_amd import workloads as W
+        self.native, self.batch, self.ctx, self.torch = native, batch, ctx, torch
+        self.sh = native.DeviceShells(batch.basis)
+        self.bra = native._pairs(batch.bra)
+        self.ket = native._pairs(batch.ket)
+        nab, ncd = native._class_sizes(self.sh, batch.ncentre, self.bra, self.ket, False)
+        L = native.lib()
+        self.wsz = L.mdx_eri_grad_workspace_size(ctx.handle, ctypes.byref(self.sh.struct), batch.ncentre,
+                                                 self.bra.shape[0], native._i32p(self.bra), self.ket.shape[0],
+                                                 native._i32p(self.ket), 0)
+        if self.wsz == 0:
+            native.check(native.MDX_EINVAL, "gradient workspace size")
+        self.ws = torch.empty(self.wsz // 8 + 64, dtype=torch.float64, device="cuda")
+        self.wsp = (self.ws.data_ptr() + 255) // 256 * 256
+        self.n = self.bra.shape[0] * self.ket.shape[0]
+        self.W = torch.as_tensor(W.adjoint(batch, nab, ncd, seed=seed), device="cuda")
+        self.grad = torch.empty(self.n * 12, dtype=torch.float64, device="cuda")
+
+    def __call__(self):
+        n = self.native
+        n.check(n.lib().mdx_eri_grad_batch(self.ctx.handle, ctypes.byref(self.sh.struct), self.batch.ncentre,
+                                           self.bra.shape[0], n._i32p(self.bra), self.ket.shape[0],
+                                           n._i32p(self.ket), 0, ctypes.c_void_p(self.W.data_ptr()),
+                                           ctypes.c_void_p(self.grad.data_ptr()), ctypes.c_void_p(self.wsp),
+                                           self.wsz, n._stream(self.torch)), "mdx_eri_grad_batch")
+
+
+def measure(fn, nlaunch, reps, native, ctx, torch):
+    """(ms per call, [mean kernel ms of launch j of a call]) over reps calls;
+    kernel times come from the library's profiling hook."""
+    for _ in range(2):
+        fn()
+    torch.cuda.synchronize()
+    ev = HipEvents(2 * nlaunch * reps)
+    native.check(native.lib().mdx_set_profile_events(ctx.handle, ev.ev, ev.n), "profile hook")
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(reps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    native.check(native.lib().mdx_set_profile_events(ctx.handle, None, 0), "profile hook off")
+    ks = [ev.elapsed_ms(i) for i in range(nlaunch * reps)]
+    return t0.elapsed_time(t1) / reps, [sum(ks[j::nlaunch]) / reps for j in range(nlaunch)]
+
+
+def extra_legs(native, ctx, torch, tune, reps):
+    """The other measured workloads (not part of the headline step)."""
+    from paper_2506_12501_amd import autotune, flops as F, workloads as W
+    out = {}
+
+    def kfl(batch, grad=False):
+        la, lb, lc, ld = W.parse_class(batch.name)
+        Ks = [int(batch.basis.nprim[batch.bra[0, 0]]), int(batch.basis.nprim[batch.bra[0, 1]]) if lb >= 0 else 1,
+              int(batch.basis.nprim[batch.ket[0, 0]]), int(batch.basis.nprim[batch.ket[0, 1]]) if ld >= 0 else 1]
+        return (F.grad_shellset_flops if grad else F.shellset_flops)(la, lb, lc, ld, *Ks)
+
+    # backward kernel: (dd|dd) K=3, 256 x 256 pairs, adjoint N(0,1) seed 1
+    g = GradRun(native, W.config2("(dd|dd)"), ctx, torch, seed=1)
+    variant = None
+    if tune:
+        variant, _ = autotune.tune(ctx, g.sh, 4, g.bra, g.ket, g, reps=2, cache=False, gradient=True)
+    ms, kms = measure(g, 2, reps, native, ctx, torch)
+    fl = kfl(g.batch, grad=True) * g.n
+    log("gradient leg done")
+    out["gradient"] = {
+        "workload": "(dd|dd) backward, K=3, 256x256 pairs (65,536 shellsets), adjoint N(0,1) seed 1, "
+                    "12 centre derivatives per shellset",
+        "ms_per_call": ms, "shellsets_per_s": g.n / (ms * 1e-3), "kernel_ms_per_pass": kms,
+        "algorithmic_gflop": fl / 1e9, "kernel_tflops": fl / (sum(kms) * 1e-3) / 1e12,
+        "pct_fp64_peak": 100 * fl / (sum(kms) * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": variant,
+        "flop_model": "flops.grad_shellset_flops"}
+    del g
+
+    # high-L primitive classes: (ff|ff), (gg|gg) 128 x 128; (X|dd) 256 x 256
+    hl = {}
+    for name in W.C4_CLASSES_4C + W.C4_CLASSES_3C:
+        r = ClassRun(native, W.config4(name, seed=0), ctx, torch)
+        v = None
+        if tune:
+            v, _ = autotune.tune(ctx, r.sh, r.batch.ncentre, r.bra, r.ket, r, reps=2, cache=False)
+        ms, kms = measure(r, 1, reps, native, ctx, torch)
+        fl = kfl(r.batch) * r.n
+        hl[name] = {"shellsets": r.n, "ms_per_call": ms, "kernel_ms": kms[0],
+                    "shellsets_per_s": r.n / (ms * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
+                    "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": v}
+        del r
+    out["high_l"] = hl
+
+    # plain s/p primitive classes: 16 x 16 pairs (256 shellsets) per class
+    sp = {}
+    for name in W.C1_CLASSES:
+        r = ClassRun(native, W.config1(name, seed=0), ctx, torch)
+        ms, kms = measure(r, 1, max(reps, 20), native, ctx, torch)
+        sp[name] = {"shellsets": r.n, "us_per_call": ms * 1e3, "kernel_us": kms[0] * 1e3,
+                    "shellsets_per_s": r.n / (ms * 1e-3)}
+    out["sp_classes"] = sp
+    return out
+
+
 def class_flops(batch):
     from paper_2506_12501_amd import flops as F, workloads as W
     la, lb, lc, ld = W.parse_class(batch.name)
@@ -121,16 +231,26 @@ def cpu_baseline(runs, sample_pairs):
 def load_traffic(kernel_tag):
     """HBM bytes per launch from profiles/<tag>_traffic.json, if it was
     measured on the current kernel source."""
-    import hashlib
     p = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
     if not os.path.exists(p):
         return None
     d = json.load(open(p))
-    src = os.path.join(ROOT, "paper_2506_12501_amd", "csrc", "eri_mfma.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if d.get("source_sha256_16") != h:
+    if d.get("source_sha256_16") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+KERNEL_SOURCES = ["eri_mfma.hip", "mfma_common.h", "eri_common.h", "kernels.h", "mdx_internal.h", "boys_device.h",
+                  "eri.cpp"]
+
+
+def kernel_source_hash():
+    """sha256 (16 hex digits) over the sources of the forward matrix-core kernel and its launch"""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2506_12501_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -139,7 +259,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--npair", type=int, default=256)
-    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--cpu-sample", type=int, default=224)
+    ap.add_argument("--no-extras", action="store_true", help="skip the gradient / high-L / s-p legs")
+    ap.add_argument("--extra-reps", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -168,6 +290,7 @@ def main():
     ctx = native.Context.get(0)
     names = args.classes.split(",") if args.classes else W.C2_CLASSES
     runs = [ClassRun(native, W.config2(name, npair=args.npair, seed=0), ctx, torch) for name in names]
+    log("workload built")
     nshell = sum(r.n for r in runs)
 
     # autotuner (untimed): fastest kernel variant per class on this workload
@@ -177,6 +300,8 @@ def main():
         for r in runs:
             best, times = autotune.tune(ctx, r.sh, r.batch.ncentre, r.bra, r.ket, r, reps=2, cache=False)
             tuning[r.batch.name] = {"variant": best, "ms": {str(k): v for k, v in times.items()}}
+
+    log(f"tuning done: {tuning}")
 
     def step():
         for r in runs:
@@ -202,6 +327,7 @@ def main():
     wall = time.perf_counter() - wall0
     native.check(native.lib().mdx_set_profile_events(ctx.handle, None, 0), "profile hook off")
     ms_step = t0.elapsed_time(t1) / args.steps
+    log(f"timed region done: {ms_step:.3f} ms per step")
 
     per_class = {}
     for ci, r in enumerate(runs):
@@ -222,9 +348,15 @@ def main():
                 "kernel": "eri_mfma_kernel (dd|dd) K=3, 65,536 shellsets per launch",
                 "flops_per_launch": pc["algorithmic_gflop"] * 1e9}
 
+    extras = None
+    if not args.no_extras:
+        extras = extra_legs(native, ctx, torch, not args.no_tune, args.extra_reps)
+        log("extra legs done")
+
     cpu, parity = (None, None)
     if not args.no_cpu:
         cpu, parity = cpu_baseline(runs, args.cpu_sample)
+        log("cpu baseline done")
 
     total_flops = sum(class_flops(r.batch) * r.n for r in runs)
     rec = {
@@ -250,6 +382,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_sample": parity,
+        "extras": extras,
         "wall_s_timed": wall,
     }
     print(json.dumps(rec), flush=True)

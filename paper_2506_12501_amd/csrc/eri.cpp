@@ -273,11 +273,18 @@ mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, 
     a.om = cp.om;
     a.om.out = out;
     int nblocks;
-    const int tile = cp.kind == K_VALU ? 64 : 1;
     if (cp.count.empty()) {
         a.tiles = nullptr;
-        a.tiles_per_J = (int)((nb + tile - 1) / tile);
-        nblocks = a.tiles_per_J * (int)nk;
+        int64_t nbl;
+        if (cp.kind == K_VALU) {   // 64 bra pairs (one per lane) per ket pair
+            a.tiles_per_J = (int)((nb + 63) / 64);
+            nbl = (int64_t)a.tiles_per_J * (int64_t)nk;
+        } else {                   // blocks of 8 bra x 16 ket pairs
+            a.tiles_per_J = (int)((nb + 7) / 8);
+            nbl = (int64_t)a.tiles_per_J * (int64_t)((nk + 15) / 16) * 128;
+        }
+        if (nbl > INT32_MAX) return fail(MDX_EUNSUPPORTED, "%lld workgroups in one launch (split the batch)", (long long)nbl);
+        nblocks = (int)nbl;
     } else {
         a.om.count = (const int32_t *)(ws + L.count);
         a.om.obase = (const int64_t *)(ws + L.obase);

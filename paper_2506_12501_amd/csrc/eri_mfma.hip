@@ -60,9 +60,15 @@ eri_mfma_kernel(EriArgs a)
         J = t.x;
         I = t.y;
     } else {
+        // blocks of 8 bra x 16 ket pairs, dealt to the XCDs in contiguous
+        // ranges: the workgroups resident on an XCD share 8 bra and 16 ket H
+        // blocks in its L2 (bra blocks run fastest, so the ket H stays), and 8
+        // consecutive bra pairs fill output lines
         const int t = xcd_tile(blockIdx.x, gridDim.x);
-        J = t / a.tiles_per_J;
-        I = t % a.tiles_per_J;
+        const int blk = t >> 7, e = t & 127;
+        I = (blk % a.tiles_per_J) * 8 + (e & 7);
+        J = (blk / a.tiles_per_J) * 16 + (e >> 3);
+        if (J >= a.nket) return;   // whole workgroup
     }
     const int nI = a.om.count ? a.om.count[J] : a.nbra;
     if (I >= nI) return;   // whole workgroup

@@ -48,3 +48,36 @@ def output_bytes(la, lb, lc, ld, cartesian=False) -> int:
     n_ab = nfunc(la, cartesian) * (nfunc(lb, cartesian) if lb >= 0 else 1)
     n_cd = nfunc(lc, cartesian) * (nfunc(ld, cartesian) if ld >= 0 else 1)
     return 8 * n_ab * n_cd
+
+
+def grad_shellset_flops(la: int, lb: int, lc: int, ld: int, Ka: int = 1, Kb: int = 1, Kc: int = 1, Kd: int = 1,
+                        cartesian: bool = False) -> float:
+    """FLOPs of the backward schedule per shellset (twelve centre derivatives
+    contracted with an adjoint).  One pass per derivative side d against the
+    other side w (4-centre: both pairs; 3-centre: the ket pair; 2-centre: the
+    lower-l function), each with L' = l_d + l_w + 1:
+      K_d K_w [B(L') + R(L') + 2 NH(l_d+1) NH(l_w-1) n_d + 2 NH(l_d+1) nc(l_w)]
+      + K_d [2 NH(l_d+1) nc(l_w) n_d + 12 NH(l_d+1) n_d]      (terminal block, six dots)
+      + K_w 2 NH(l_w-1) n_w n_d + 2 nc(l_w) n_w n_d           (adjoint folded into w)
+    A single function counts as a pair with a unit s partner."""
+    nfn = lambda l: nfunc(l, cartesian) if l >= 0 else 1
+    sides = [(la + max(lb, 0), nfn(la) * nfn(lb), Ka * max(Kb, 1)),
+             (lc + max(ld, 0), nfn(lc) * nfn(ld), Kc * max(Kd, 1))]
+    if lb >= 0 and ld >= 0:
+        passes = [(0, 1), (1, 0)]
+    elif ld >= 0:
+        passes = [(1, 0)]
+    else:
+        passes = [(0, 1)] if la <= lc else [(1, 0)]
+    total = 0.0
+    for d, w in passes:
+        (ldd, nd, Kd_), (lw, nw, Kw) = sides[d], sides[w]
+        L = ldd + lw + 1
+        B = 20 + 3 * (L + 1)
+        R = 3 * sum(nh(j) - 1 for j in range(1, L + 1))
+        h = nh(ldd + 1)
+        per_q = B + R + 2 * h * nh(lw - 1) * nd + 2 * h * nc(lw)
+        per_d = 2 * h * nc(lw) * nd + 12 * h * nd
+        per_w = 2 * nh(lw - 1) * nw * nd
+        total += Kd_ * Kw * per_q + Kd_ * per_d + Kw * per_w + 2 * nc(lw) * nw * nd
+    return float(total)

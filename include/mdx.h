@@ -150,6 +150,22 @@ mdx_status mdx_eri_grad_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentr
                               mdx_stream_t stream);
 
 /*
+ * Schwarz factors Q_ij = sqrt(max_ab |(ab|ab)|) of npair shell pairs of one
+ * class (pairs[2i], pairs[2i+1], same (l_a, l_b) for all), from the diagonal
+ * 4-centre shellsets (ab|ab) computed by the integral kernels.  |(ab|cd)| <=
+ * Q_ab Q_cd (Cauchy-Schwarz for the Coulomb metric), so a quartet with
+ * Q_ab Q_cd below a threshold can be skipped -- the screening of batches by
+ * sorted factors that Sec. 3.1 describes.
+ *   Q DEVICE double[npair]; ws DEVICE, at least mdx_schwarz_workspace_size
+ *   bytes, 256-byte aligned.  flags: MDX_SPHERICAL or MDX_CARTESIAN.
+ * Errors as mdx_eri_batch.
+ */
+size_t mdx_schwarz_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
+                                  int flags);
+mdx_status mdx_schwarz(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs, int flags,
+                       double *Q, void *ws, size_t ws_bytes, mdx_stream_t stream);
+
+/*
  * Multi-class plans (batch-level screening of Sec. 3.1; mixed classes in one
  * launch).  A plan holds host-side planning and device-side index tables; it
  * is built once and executed many times.
@@ -175,17 +191,28 @@ typedef struct {
 typedef struct mdx_plan mdx_plan;
 
 /* flags: MDX_SPHERICAL/MDX_CARTESIAN | MDX_FUSED.  Without MDX_FUSED the plan
- * issues one plain launch per class (and per pair-data side); with it, the
- * whole plan is one captured graph with persistent work-queue kernels. */
+ * issues one plain launch per batch (and two pair-data launches per batch);
+ * with it, execution is one captured graph: the pair data of all batches,
+ * then one persistent work-queue launch per kernel instance, each serving
+ * every batch that uses that instance.
+ * Batches are taken in kernel orientation as given (no bra/ket swap): give
+ * the pair with the larger total angular momentum as the bra (l_a + l_b >=
+ * l_c + l_d); other orientations can fail with MDX_EUNSUPPORTED.
+ * mdx_plan_create allocates the plan's device index tables (the only
+ * allocation of the library outside mdx_create; freed by mdx_plan_destroy);
+ * with MDX_FUSED it also creates the streams and events used to capture the
+ * graph.  Executions of one plan must not overlap in time (they share its
+ * work counters). */
 mdx_status mdx_plan_create(mdx_ctx *ctx, const mdx_shells *shells, int nbatch,
                            const mdx_batch_desc *batches, int flags, mdx_plan **out);
 size_t mdx_plan_workspace_size(const mdx_plan *plan);
 /* total number of doubles the plan writes (max over batches of offset+size) */
 int64_t mdx_plan_output_size(const mdx_plan *plan);
-/* shells must describe the same basis (same metadata) as at creation; its
- * device arrays may hold new values.  With MDX_FUSED the device pointers,
- * out, ws and stream must stay the same across executions (the graph keeps
- * them); changing any of them rebuilds the graph. */
+/* shells must describe the same basis (same metadata) as at creation, else
+ * MDX_EINVAL; its device arrays may hold new values.  out: DEVICE double of at
+ * least mdx_plan_output_size doubles.  With MDX_FUSED the graph keeps the
+ * device pointers of shells, out and ws: changing any of them rebuilds the
+ * graph (which synchronises the stream once); the stream may change freely. */
 mdx_status mdx_plan_execute(mdx_plan *plan, const mdx_shells *shells, double *out, void *ws,
                             size_t ws_bytes, mdx_stream_t stream);
 void mdx_plan_destroy(mdx_plan *plan);

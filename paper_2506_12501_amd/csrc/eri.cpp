@@ -189,15 +189,20 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
     } else {
         cp.count.resize(nket);
         cp.obase.resize(nket);
-        int64_t off = 0;
+        cp.tile_off.resize(nket + 1);
+        const int rows = cp.kind == K_VALU ? 64 : 1;   // bra pairs per tile
+        int64_t off = 0, ntile = 0;
         for (int32_t k = 0; k < nket; ++k) {
             const int32_t n = bra_count[k];
             if (n < 0 || n > nbra) return fail(MDX_EINVAL, "bra_count[%d] = %d outside [0, %d]", k, n, nbra);
             cp.count[k] = n;
             cp.obase[k] = off;
             off += (int64_t)n * nab_c * ncd_c;
-            for (int32_t i0 = 0; i0 < n; i0 += 64) cp.tiles.push_back(make_int2(k, i0));
+            cp.tile_off[k] = (int32_t)ntile;
+            ntile += (n + rows - 1) / rows;
+            if (ntile > INT32_MAX) return fail(MDX_EUNSUPPORTED, "more than 2^31 tiles in one batch");
         }
+        cp.tile_off[nket] = (int32_t)ntile;
         om.sI = 1;
         om.sJ = 0;
         om.mult = 0;
@@ -224,46 +229,67 @@ WsLayout ws_layout(const ClassPlan &cp, size_t base)
     L.H_ket = take(nk * (size_t)cp.ket.g.pair_stride * sizeof(double));
     L.count = take(cp.count.size() * sizeof(int32_t));
     L.obase = take(cp.obase.size() * sizeof(int64_t));
-    L.tiles = take(cp.tiles.size() * sizeof(int2));
+    L.tile_off = take(cp.tile_off.size() * sizeof(int32_t));
     L.total = o - base;
     return L;
 }
 
-mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
-                         double *out, hipStream_t s, bool upload)
+ClassDev class_dev(const WsLayout &L, char *ws)
+{
+    ClassDev d{};
+    d.pairs_bra = (const PairRec *)(ws + L.pairs_bra);
+    d.pairs_ket = (const PairRec *)(ws + L.pairs_ket);
+    d.count = (const int32_t *)(ws + L.count);
+    d.obase = (const int64_t *)(ws + L.obase);
+    d.tile_off = (const int32_t *)(ws + L.tile_off);
+    d.prim_bra = (PrimRec *)(ws + L.prim_bra);
+    d.prim_ket = (PrimRec *)(ws + L.prim_ket);
+    d.np_bra = (int32_t *)(ws + L.np_bra);
+    d.np_ket = (int32_t *)(ws + L.np_ket);
+    d.H_bra = (double *)(ws + L.H_bra);
+    d.H_ket = (double *)(ws + L.H_ket);
+    return d;
+}
+
+mdx_status upload_tables(const ClassPlan &cp, const ClassDev &d, hipStream_t s)
 {
     const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
-    if (nb == 0 || nk == 0) return MDX_OK;
-    if (upload) {
-        HIP_TRY2(hipMemcpyAsync(ws + L.pairs_bra, cp.bra.pairs.data(), nb * sizeof(PairRec), hipMemcpyHostToDevice, s));
-        HIP_TRY2(hipMemcpyAsync(ws + L.pairs_ket, cp.ket.pairs.data(), nk * sizeof(PairRec), hipMemcpyHostToDevice, s));
-        if (!cp.count.empty()) {
-            HIP_TRY2(hipMemcpyAsync(ws + L.count, cp.count.data(), cp.count.size() * 4, hipMemcpyHostToDevice, s));
-            HIP_TRY2(hipMemcpyAsync(ws + L.obase, cp.obase.data(), cp.obase.size() * 8, hipMemcpyHostToDevice, s));
-        }
-        if (!cp.tiles.empty())
-            HIP_TRY2(hipMemcpyAsync(ws + L.tiles, cp.tiles.data(), cp.tiles.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    HIP_TRY2(hipMemcpyAsync((void *)d.pairs_bra, cp.bra.pairs.data(), nb * sizeof(PairRec), hipMemcpyHostToDevice, s));
+    HIP_TRY2(hipMemcpyAsync((void *)d.pairs_ket, cp.ket.pairs.data(), nk * sizeof(PairRec), hipMemcpyHostToDevice, s));
+    if (!cp.count.empty()) {
+        HIP_TRY2(hipMemcpyAsync((void *)d.count, cp.count.data(), cp.count.size() * 4, hipMemcpyHostToDevice, s));
+        HIP_TRY2(hipMemcpyAsync((void *)d.obase, cp.obase.data(), cp.obase.size() * 8, hipMemcpyHostToDevice, s));
     }
-    for (int side = 0; side < 2; ++side) {
-        const SidePlan &sp = side == 0 ? cp.bra : cp.ket;
-        PairDataArgs pa{};
-        pa.g = sp.g;
-        pa.pairs = (const PairRec *)(ws + (side == 0 ? L.pairs_bra : L.pairs_ket));
-        pa.center = sh->center;
-        pa.expo = sh->exponent;
-        pa.coef = sh->coef;
-        pa.Ca = c->solid + c->solid_off[sp.g.la];
-        pa.Cb = sp.g.lb >= 0 ? c->solid + c->solid_off[sp.g.lb] : nullptr;
-        pa.prim = (PrimRec *)(ws + (side == 0 ? L.prim_bra : L.prim_ket));
-        pa.H = (double *)(ws + (side == 0 ? L.H_bra : L.H_ket));
-        pa.nprim = (int32_t *)(ws + (side == 0 ? L.np_bra : L.np_ket));
-        launch_pairdata(pa, s);
-    }
-    EriArgs a{};
-    a.bra = SideDev{(const PrimRec *)(ws + L.prim_bra), (const double *)(ws + L.H_bra),
-                    (const int32_t *)(ws + L.np_bra), cp.bra.g.kmax, cp.bra.g.pair_stride};
-    a.ket = SideDev{(const PrimRec *)(ws + L.prim_ket), (const double *)(ws + L.H_ket),
-                    (const int32_t *)(ws + L.np_ket), cp.ket.g.kmax, cp.ket.g.pair_stride};
+    if (!cp.tile_off.empty())
+        HIP_TRY2(hipMemcpyAsync((void *)d.tile_off, cp.tile_off.data(), cp.tile_off.size() * sizeof(int32_t),
+                                hipMemcpyHostToDevice, s));
+    return MDX_OK;
+}
+
+void enqueue_pairdata(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const ClassDev &d, int side,
+                      hipStream_t s)
+{
+    const SidePlan &sp = side == 0 ? cp.bra : cp.ket;
+    PairDataArgs pa{};
+    pa.g = sp.g;
+    pa.pairs = side == 0 ? d.pairs_bra : d.pairs_ket;
+    pa.center = sh->center;
+    pa.expo = sh->exponent;
+    pa.coef = sh->coef;
+    pa.Ca = c->solid + c->solid_off[sp.g.la];
+    pa.Cb = sp.g.lb >= 0 ? c->solid + c->solid_off[sp.g.lb] : nullptr;
+    pa.prim = side == 0 ? d.prim_bra : d.prim_ket;
+    pa.H = side == 0 ? d.H_bra : d.H_ket;
+    pa.nprim = side == 0 ? d.np_bra : d.np_ket;
+    launch_pairdata(pa, s);
+}
+
+mdx_status class_args(mdx_ctx *c, const ClassPlan &cp, const ClassDev &d, double *out, EriArgs &a, int &nblocks)
+{
+    const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
+    a = EriArgs{};
+    a.bra = SideDev{d.prim_bra, d.H_bra, d.np_bra, cp.bra.g.kmax, cp.bra.g.pair_stride};
+    a.ket = SideDev{d.prim_ket, d.H_ket, d.np_ket, cp.ket.g.kmax, cp.ket.g.pair_stride};
     a.nbra = (int)nb;
     a.nket = (int)nk;
     a.boys = c->boys;
@@ -272,9 +298,10 @@ mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, 
     a.ncd = cp.ket.g.ncol;
     a.om = cp.om;
     a.om.out = out;
-    int nblocks;
-    if (cp.count.empty()) {
-        a.tiles = nullptr;
+    if (cp.diag) {
+        a.diag = 1;
+        nblocks = (int)nk;
+    } else if (cp.count.empty()) {
         int64_t nbl;
         if (cp.kind == K_VALU) {   // 64 bra pairs (one per lane) per ket pair
             a.tiles_per_J = (int)((nb + 63) / 64);
@@ -286,26 +313,46 @@ mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, 
         if (nbl > INT32_MAX) return fail(MDX_EUNSUPPORTED, "%lld workgroups in one launch (split the batch)", (long long)nbl);
         nblocks = (int)nbl;
     } else {
-        a.om.count = (const int32_t *)(ws + L.count);
-        a.om.obase = (const int64_t *)(ws + L.obase);
-        a.tiles = (const int2 *)(ws + L.tiles);
-        nblocks = (int)cp.tiles.size();
+        a.om.count = d.count;
+        a.om.obase = d.obase;
+        a.tile_off = d.tile_off;
+        nblocks = cp.tile_off.back();
     }
     a.ntile_total = nblocks;
+    return MDX_OK;
+}
+
+mdx_status launch_class(mdx_ctx *c, const ClassPlan &cp, const EriArgs &a, int nblocks, hipStream_t s)
+{
     if (nblocks == 0) return MDX_OK;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t ev1 = nullptr;
     if (c->prof_events.size() >= 2) {
         const size_t np = c->prof_events.size() / 2, i = c->prof_count++ % np;
-        ev0 = c->prof_events[2 * i];
         ev1 = c->prof_events[2 * i + 1];
-        HIP_TRY2(hipEventRecord(ev0, s));
+        HIP_TRY2(hipEventRecord(c->prof_events[2 * i], s));
     }
-    bool ok = cp.kind == K_VALU ? eri_valu_launch(cp.key, a, nblocks, s)
-                                : eri_mfma_launch(cp.key, a, nblocks, cp.variant, s);
+    const bool ok = cp.kind == K_VALU ? eri_valu_launch(cp.key, a, nblocks, s)
+                                      : eri_mfma_launch(cp.key, a, nblocks, cp.variant, s);
     if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
-    if (!ok) return fail(MDX_EUNSUPPORTED, "kernel instance missing");
+    if (!ok) return fail(MDX_EUNSUPPORTED, "kernel instance missing or its LDS need exceeds the device limit");
     HIP_TRY2(hipGetLastError());
     return MDX_OK;
+}
+
+mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
+                         double *out, hipStream_t s, bool upload)
+{
+    const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
+    if (nb == 0 || nk == 0) return MDX_OK;
+    const ClassDev d = class_dev(L, ws);
+    mdx_status st;
+    if (upload && (st = upload_tables(cp, d, s)) != MDX_OK) return st;
+    enqueue_pairdata(c, sh, cp, d, 0, s);
+    enqueue_pairdata(c, sh, cp, d, 1, s);
+    EriArgs a;
+    int nblocks = 0;
+    if ((st = class_args(c, cp, d, out, a, nblocks)) != MDX_OK) return st;
+    return launch_class(c, cp, a, nblocks, s);
 }
 
 }  // namespace mdx

@@ -1,31 +1,6 @@
-// eri_mfma.hip -- MD integrals on the FP64 matrix cores (V_MFMA_F64_16X16X4_F64).
-//
-// One workgroup of NW waves evaluates one shellset (bra pair I, ket pair J).
-// The Hermite-to-AO transforms of the paper's Eq. (36) chain are dense
-// contractions and run as MFMA GEMMs:
-//
-//  ket transform (Eq. (32), with the partial early contraction of Sec. 2.2.2,
-//  Eqs. (38)-(40)):
-//     X[(kb,p)][cd] = sum_{kk, q non-terminal} [p+q]^(0)_{kb,kk} H_ket[kk][q][cd]
-//                   + sum_{q terminal} Y[(kb,p)][q] T[q][cd],
-//     Y[(kb,p)][q]  = sum_kk w_kk [p+q]^(0)_{kb,kk}          (VALU, registers)
-//  M = rows (bra primitive, bra Hermite), K = (ket primitive, ket Hermite),
-//  N = ket functions.  The A operand is gathered from [r]^(0) held in LDS
-//  (Eq. (25): [p|q] is never stored, the sign lives in H_ket).
-//
-//  bra transform (Eq. (33)):  out[ab][cd] = sum_rows H_bra[ab][row] X[row][cd]
-//  The accumulator tile of X is used directly as the B operand: register r of
-//  lane (c, g) holds X[row 4r+g][col c], which is B[k=g][n=c] of k-step r, so
-//  the K order of the bra GEMM is permuted to match (no data movement).
-//
-// [r]^(0) follows the recursion of Eq. (31) in three one-axis sweeps (z, then
-// y per column v, then x per column (u, v)), each of compile-time length and
-// unrolled in registers.  The table is a dense (L+1)^3 cube indexed (t,u,v),
-// so [p+q] sits at offset(p) + offset(q): per-lane row offsets plus
-// compile-time ket offsets.
-#include <algorithm>
-
-#include "mfma_common.h"
+// eri_mfma.hip -- plain launches of the matrix-core integral kernel: one
+// shellset per workgroup, (I, J) from the block index.
+#include "eri_mfma.h"
 
 namespace mdx {
 
@@ -33,32 +8,12 @@ template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB,
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 eri_mfma_kernel(EriArgs a)
 {
-    constexpr int L = LB + LK;
-    constexpr int D = L + 1, CUBE = D * D * D;
-    constexpr int NH = nherm(L);
-    constexpr int NUV = (L + 1) * (L + 2) / 2;
-    constexpr int NHB = GB ? ncart(LB) : nherm(LB);
-    constexpr int HB0 = GB ? nherm(LB - 1) : 0;
-    constexpr int NKN = nherm(LK - 1);
-    constexpr int NTPAD = round_up(NKN, 4);
-    constexpr int KS = NTPAD / 4;
-    constexpr int NKT = ncart(LK);
-    constexpr int KT = round_up(NKT, 4) / 4;
-    constexpr int RPB = NTPAD + NKT;
-    constexpr int NCDP = NTCD * 16, NABP = NTAB * 16;
-    constexpr int NG = NTCD / NTG;
-    constexpr int GW = NTG * 16;
-    constexpr int NT = 64 * NW;
-    constexpr int HKR = (NTPAD * GW + NT - 1) / NT;   // staged ket values per thread
-    static_assert(NTCD % NTG == 0, "cd tiles must split into groups");
-    const int tid = threadIdx.x;
-    const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
-
     int J, I;
-    if (a.tiles) {
-        const int2 t = a.tiles[blockIdx.x];
-        J = t.x;
-        I = t.y;
+    if (a.diag) {   // diagonal shellsets (I = J) only
+        J = blockIdx.x;
+        I = J;
+    } else if (a.tile_off) {   // ragged batch: one shellset per tile
+        ragged_tile(a.tile_off, a.nket, blockIdx.x, J, I);
     } else {
         // blocks of 8 bra x 16 ket pairs, dealt to the XCDs in contiguous
         // ranges: the workgroups resident on an XCD share 8 bra and 16 ket H
@@ -68,276 +23,11 @@ eri_mfma_kernel(EriArgs a)
         const int blk = t >> 7, e = t & 127;
         I = (blk % a.tiles_per_J) * 8 + (e & 7);
         J = (blk / a.tiles_per_J) * 16 + (e >> 3);
-        if (J >= a.nket) return;   // whole workgroup
     }
-    const int nI = a.om.count ? a.om.count[J] : a.nbra;
-    if (I >= nI) return;   // whole workgroup
-
-    const int npb = a.bra.nprim[I];
-    const int nkk = a.ket.nprim[J];
-    const int nbk = GB ? 1 : npb;
-    const int nrows = nbk * NHB;
-    const int MT = (nrows + 15) >> 4;
-    const int nch = (MT + NW * MTW - 1) / (NW * MTW);
-    const int nqmax = a.nqmax;
-
-    // With several column groups the [r]^(0) table may stay resident across
-    // groups, so the cross-wave reduction gets a region of its own.
-    constexpr bool SEPRED = NG > 1;
-    constexpr int RED = (NW - 1) * NTG * 256;
-    extern __shared__ double smem[];
-    double *cube = smem;
-    const int cube_words = (SEPRED || nqmax * CUBE > RED) ? nqmax * CUBE : RED;
-    double *red = SEPRED ? smem + cube_words : cube;
-    const int kkmax = a.ket.kmax;
-    double *S = smem + cube_words + (SEPRED ? RED : 0);   // [kkmax][nqmax][D]
-    double *PQ = S + kkmax * nqmax * D;                  // [kkmax][nqmax][4]
-    double *Wt = PQ + kkmax * nqmax * 4;                 // [kkmax] terminal weights
-    double *Hk = Wt + kkmax;                             // [NTPAD][GW]
-    double *Tk = Hk + NTPAD * GW;                        // [4*KT][GW]
-    int *tuvt = (int *)(Tk + 4 * KT * GW);               // [NH] packed t | u<<8 | v<<16
-    int *kq = tuvt + NH;                                 // [NTPAD] cube offsets, non-terminal ket
-    int *kt = kq + NTPAD;                                // [4*KT] cube offsets, terminal ket
-
-    for (int k = tid; k < NH; k += NT) {
-        const Tuv r = herm_tuv(k);
-        tuvt[k] = r.t | (r.u << 8) | (r.v << 16);
-    }
-    for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? cube_off<D>(k) : 0;
-    for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? cube_off<D>(NKN + k) : 0;
-
-    const PrimRec *bp = a.bra.prim + (int64_t)I * a.bra.kmax;
-    const PrimRec *kp = a.ket.prim + (int64_t)J * a.ket.kmax;
-    const double *Hb = a.bra.H + (int64_t)I * a.bra.pair_stride;
-    const double *HkG = a.ket.H + (int64_t)J * a.ket.pair_stride;
-
-    const bool resident = (nkk == 1 && nch == 1);
-    const int64_t obase = a.om.count ? a.om.obase[J] : (int64_t)J * a.om.sJ;
-    const int64_t omult = a.om.count ? (int64_t)nI : a.om.mult;
-
-    for (int grp = 0; grp < NG; ++grp) {
-        for (int ch = 0; ch < nch; ++ch) {
-            const int tile0 = ch * NW * MTW + w * MTW;
-            const int row_lo = ch * NW * MTW * 16;
-            const int row_hi = min(nrows, row_lo + NW * MTW * 16);
-            const int kb_lo = GB ? 0 : row_lo / NHB;
-            const int kb_hi = GB ? 0 : (row_hi - 1) / NHB;
-            const int NQ = kb_hi - kb_lo + 1;
-
-            __syncthreads();   // Hermite table visible; previous users of LDS done
-            for (int e = tid; e < 4 * KT * GW; e += NT) Tk[e] = a.Tket[(e / GW) * NCDP + grp * GW + (e % GW)];
-            int abase[MTW];
-#pragma unroll
-            for (int tt = 0; tt < MTW; ++tt) {
-                const int row = 16 * (tile0 + tt) + c;
-                int off = 0;
-                if (row < nrows) {
-                    const int kb = GB ? 0 : row / NHB;
-                    const int h = GB ? row : row - kb * NHB;
-                    const int pk = tuvt[HB0 + h];
-                    off = (kb - kb_lo) * CUBE + ((pk & 255) * D + ((pk >> 8) & 255)) * D + (pk >> 16);
-                }
-                abase[tt] = off;
-            }
-            d4 acc[MTW][NTG];
-            double Y[MTW][KT];
-#pragma unroll
-            for (int tt = 0; tt < MTW; ++tt) {
-#pragma unroll
-                for (int n = 0; n < NTG; ++n) acc[tt][n] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int s = 0; s < KT; ++s) Y[tt][s] = 0.0;
-            }
-
-            const bool fresh = !(resident && grp > 0);
-            if (fresh) {
-                // [0]^(m) of every primitive quartet of the chunk, Eq. (27), times the
-                // primitive weights; a single-function solid bra sums its primitives here
-                for (int e = tid; e < NQ * nkk; e += NT) {
-                    const int kk = e / NQ, q = e - kk * NQ;
-                    double Sm[D];
-#pragma unroll
-                    for (int m = 0; m <= L; ++m) Sm[m] = 0.0;
-                    const PrimRec K = kp[kk];
-                    double X = 0.0, Yv = 0.0, Z = 0.0;
-                    const int b0 = GB ? 0 : kb_lo + q, b1 = GB ? npb : kb_lo + q + 1;
-                    for (int ib = b0; ib < b1; ++ib) {
-                        const PrimRec B = bp[ib];
-                        const double pq = B.p + K.p;
-                        const double rho = B.p * K.p / pq;
-                        X = B.Px - K.Px;
-                        Yv = B.Py - K.Py;
-                        Z = B.Pz - K.Pz;
-                        double F[D];
-                        boys_eval<L>(rho * (X * X + Yv * Yv + Z * Z), F, a.boys);
-                        double f = B.ws * K.ws * rsqrt_d(pq);
-                        const double m2r = -2.0 * rho;
-#pragma unroll
-                        for (int m = 0; m <= L; ++m) {
-                            Sm[m] = fma(f, F[m], Sm[m]);
-                            f *= m2r;
-                        }
-                    }
-                    double *Sq = S + (kk * nqmax + q) * D;
-#pragma unroll
-                    for (int m = 0; m <= L; ++m) Sq[m] = Sm[m];
-                    double *pq4 = PQ + (kk * nqmax + q) * 4;
-                    pq4[0] = X;
-                    pq4[1] = Yv;
-                    pq4[2] = Z;
-                    if (q == 0) Wt[kk] = K.wt;
-                }
-            }
-
-            for (int kk = 0; kk < nkk; ++kk) {
-                __syncthreads();   // previous k-loop reads of the table / Hk are complete
-                // ket block of this primitive: global loads now, LDS store after the recursion
-                double hv[HKR];
-                {
-                    const double *src = HkG + (int64_t)kk * RPB * NCDP + grp * GW;
-#pragma unroll
-                    for (int i = 0; i < HKR; ++i) {
-                        const int e = tid + i * NT;
-                        hv[i] = e < NTPAD * GW ? src[(e / GW) * NCDP + (e % GW)] : 0.0;
-                    }
-                }
-                if (fresh) {
-                    // one-axis sweeps of Eq. (31): z and y per column v, then x per (u, v)
-                    const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
-                    ypasses<D, NW>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, D>{});
-                    __syncthreads();
-                    xpasses<D, NW>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, D>{});
-                }
-#pragma unroll
-                for (int i = 0; i < HKR; ++i) {
-                    const int e = tid + i * NT;
-                    if (e < NTPAD * GW) Hk[e] = hv[i];
-                }
-                __syncthreads();
-
-                // ket transform on MFMA over the non-terminal Hermites
-#pragma unroll 2
-                for (int s = 0; s < KS; ++s) {
-                    const int qo = kq[4 * s + g];
-                    double bv[NTG];
-#pragma unroll
-                    for (int n = 0; n < NTG; ++n) bv[n] = Hk[(4 * s + g) * GW + 16 * n + c];
-#pragma unroll
-                    for (int tt = 0; tt < MTW; ++tt) {
-                        const double av = cube[abase[tt] + qo];
-#pragma unroll
-                        for (int n = 0; n < NTG; ++n) acc[tt][n] = mfma(av, bv[n], acc[tt][n]);
-                    }
-                }
-                // terminal Hermites: early contraction over ket primitives
-                const double wt = Wt[kk];
-#pragma unroll
-                for (int s = 0; s < KT; ++s) {
-                    const int to = kt[4 * s + g];
-#pragma unroll
-                    for (int tt = 0; tt < MTW; ++tt) Y[tt][s] = fma(wt, cube[abase[tt] + to], Y[tt][s]);
-                }
-            }
-
-            // terminal block: X += Y T
-#pragma unroll
-            for (int s = 0; s < KT; ++s) {
-                double bv[NTG];
-#pragma unroll
-                for (int n = 0; n < NTG; ++n) bv[n] = Tk[(4 * s + g) * GW + 16 * n + c];
-#pragma unroll
-                for (int tt = 0; tt < MTW; ++tt)
-#pragma unroll
-                    for (int n = 0; n < NTG; ++n) acc[tt][n] = mfma(Y[tt][s], bv[n], acc[tt][n]);
-            }
-
-            d4 O[NTAB][NTG];
-#pragma unroll
-            for (int mm = 0; mm < NTAB; ++mm)
-#pragma unroll
-                for (int n = 0; n < NTG; ++n) O[mm][n] = d4{0.0, 0.0, 0.0, 0.0};
-            // bra transform: O += H_bra X, K order permuted to the accumulator layout;
-            // the next tile's H_bra values are fetched while this tile multiplies
-            double hb[2][4][NTAB];
-            {
-                const int T = min(tile0, MT - 1);
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-#pragma unroll
-                    for (int mm = 0; mm < NTAB; ++mm) hb[0][r][mm] = Hb[(int64_t)(16 * T + 4 * r + g) * NABP + 16 * mm + c];
-            }
-#pragma unroll
-            for (int tt = 0; tt < MTW; ++tt) {
-                const int cur = tt & 1, nxt = cur ^ 1;
-                if (tt + 1 < MTW) {
-                    const int T = min(tile0 + tt + 1, MT - 1);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int mm = 0; mm < NTAB; ++mm)
-                            hb[nxt][r][mm] = Hb[(int64_t)(16 * T + 4 * r + g) * NABP + 16 * mm + c];
-                }
-                if (tile0 + tt < MT) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int mm = 0; mm < NTAB; ++mm)
-#pragma unroll
-                            for (int n = 0; n < NTG; ++n) O[mm][n] = mfma(hb[cur][r][mm], acc[tt][n][r], O[mm][n]);
-                }
-            }
-
-            // sum the waves' partial bra transforms and store this column group
-            // (a shellset with several row chunks accumulates through the output)
-#pragma unroll
-            for (int mm = 0; mm < NTAB; ++mm) {
-                __syncthreads();
-                if (w > 0) {
-#pragma unroll
-                    for (int n = 0; n < NTG; ++n)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) red[(((w - 1) * NTG + n) * 4 + r) * 64 + lane] = O[mm][n][r];
-                }
-                __syncthreads();
-                if (w == 0) {
-#pragma unroll
-                    for (int n = 0; n < NTG; ++n)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            double v = O[mm][n][r];
-                            for (int ww = 1; ww < NW; ++ww) v += red[(((ww - 1) * NTG + n) * 4 + r) * 64 + lane];
-                            const int ab = 16 * mm + 4 * r + g;
-                            const int cd = grp * GW + 16 * n + c;
-                            if (ab < a.nab && cd < a.ncd) {
-                                double *dst = a.om.out + obase + (int64_t)I * a.om.sI +
-                                              omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd]);
-                                *dst = ch == 0 ? v : *dst + v;
-                            }
-                        }
-                }
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// instances and dispatch
-// ---------------------------------------------------------------------------
-struct MfmaShape {
-    int NTAB, NTCD, NTG, MTW, NW;
-};
-
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB>
-static size_t mfma_lds_bytes(int nqmax, int kkmax)
-{
-    constexpr int L = LB + LK, D = L + 1, CUBE = D * D * D, NH = nherm(L);
-    constexpr int NTPAD = round_up(nherm(LK - 1), 4);
-    constexpr int KT = round_up(ncart(LK), 4) / 4;
-    constexpr bool SEPRED = NTCD / NTG > 1;
-    constexpr size_t RED = (size_t)(NW - 1) * NTG * 256;
-    const size_t cube_words = SEPRED ? (size_t)nqmax * CUBE + RED : std::max((size_t)nqmax * CUBE, RED);
-    return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(NTPAD + 4 * KT) * NTG * 16) * 8 +
-           (size_t)(NH + NTPAD + 4 * KT) * 4;
+    if (J >= a.nket) return;   // whole workgroup
+    const int nI = a.diag ? J + 1 : (a.om.count ? a.om.count[J] : a.nbra);
+    if (I >= nI) return;       // whole workgroup
+    eri_mfma_shellset<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB>(a, I, J, nI);
 }
 
 template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE>
@@ -358,41 +48,6 @@ static bool launch_mfma(const EriArgs &a0, int nblocks, hipStream_t s)
     hipLaunchKernelGGL(kern, dim3(nblocks), dim3(64 * NW), lds, s, a);
     return true;
 }
-
-// Instances: class key (LB, LK, NAB, NCD, GB) and tile shape
-// (NTAB, NTCD, NTG, MTW, NW, WPE).  Several shapes per key are variants 1, 2, ...
-// in listing order; the autotuner picks one per class.
-#define MDX_MFMA_INSTANCES(X)                                                         \
-    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 2)   /* (dd|dd)                    */       \
-    X(4, 4, 25, 25, false, 2, 2, 2, 3, 4, 2)                                          \
-    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 1)                                          \
-    X(4, 4, 25, 25, false, 2, 2, 1, 5, 4, 2)                                          \
-    X(4, 4, 25, 25, false, 2, 2, 2, 3, 2, 3)                                          \
-    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2)   /* (dd|dp), (pd|dd) swapped   */       \
-    X(4, 3, 25, 15, false, 2, 1, 1, 3, 4, 2)                                          \
-    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 1)                                          \
-    X(4, 3, 25, 15, false, 2, 1, 1, 3, 2, 3)                                          \
-    X(4, 2, 25, 9, false, 2, 1, 1, 5, 4, 2)    /* (dd|pp)                    */       \
-    X(4, 2, 25, 5, false, 2, 1, 1, 5, 4, 2)    /* (dd|ds)                    */       \
-    X(3, 3, 15, 15, false, 1, 1, 1, 5, 4, 2)   /* (dp|dp)                    */       \
-    X(3, 2, 15, 9, false, 1, 1, 1, 5, 4, 2)    /* (dp|pp)                    */       \
-    X(3, 2, 15, 5, false, 1, 1, 1, 5, 4, 2)    /* (dp|ds)                    */       \
-    X(2, 2, 9, 9, false, 1, 1, 1, 5, 4, 2)     /* (pp|pp)                    */       \
-    X(4, 4, 36, 36, false, 3, 3, 3, 5, 4, 2)   /* (dd|dd) Cartesian          */       \
-    X(4, 3, 36, 18, false, 3, 2, 2, 5, 4, 2)   /* (dd|dp) Cartesian          */       \
-    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 2)   /* (ff|ff)                    */       \
-    X(6, 6, 49, 49, false, 4, 4, 1, 2, 3, 2)                                          \
-    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 1)                                          \
-    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 2)   /* (gg|gg)                    */       \
-    X(8, 8, 81, 81, false, 6, 6, 1, 3, 4, 2)                                          \
-    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 1)                                          \
-    X(2, 4, 5, 25, true, 1, 2, 2, 1, 1, 2)     /* (d|dd)                     */       \
-    X(3, 4, 7, 25, true, 1, 2, 2, 1, 1, 2)     /* (f|dd)                     */       \
-    X(4, 4, 9, 25, true, 1, 2, 2, 1, 1, 2)     /* (g|dd)                     */       \
-    X(5, 4, 11, 25, true, 1, 2, 2, 2, 1, 2)    /* (h|dd)                     */       \
-    X(6, 4, 13, 25, true, 1, 2, 2, 2, 1, 2)    /* (i|dd)                     */       \
-    X(0, 4, 1, 25, true, 1, 2, 2, 1, 1, 2)     /* (s|dd)                     */       \
-    X(1, 4, 3, 25, true, 1, 2, 2, 1, 1, 2)     /* (p|dd)                     */
 
 static bool key_is(const EriKey &k, int lb, int lk, int nab, int ncd, bool gb)
 {

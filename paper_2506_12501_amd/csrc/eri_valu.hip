@@ -1,138 +1,28 @@
-// eri_valu.hip -- one lane per shellset, everything in registers (small classes).
-//
-// Per primitive quartet the lane follows the MD chain of Eq. (36):
-//   [0]^(m) (Eq. (27), Boys of Eq. (28))  ->  [r]^(0) (Eq. (31))
-//   -> [p|q] = (-1)^{l_q} [p+q]^(0) (Eq. (25); the sign sits in the ket H)
-//   -> ket transform (Eq. (32)), accumulated over ket primitives
-// and, once per bra primitive, the bra transform (Eq. (33)).  Lanes of a wave
-// take consecutive bra pairs of one ket pair, so ket data are wave-uniform
-// (scalar loads) and stores of the [ij,ab,cd,kl] layout are coalesced.
-// A single-function solid side sums its primitives into [0]^(m) before the
-// recursion (Sec. 2.2.3).
-#include "eri_common.h"
-#include "kernels.h"
+// eri_valu.hip -- plain launches of the register integral kernel: one lane
+// per shellset, 64 consecutive bra pairs of one ket pair per wave.
+#include "eri_valu.h"
 
 namespace mdx {
 
 template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
 __global__ void __launch_bounds__(64) eri_valu_kernel(EriArgs a)
 {
-    constexpr int L = LB + LK;
-    constexpr int NH = nherm(L);
-    constexpr int NHB = GB ? ncart(LB) : nherm(LB);           // bra rows per primitive
-    constexpr int HB0 = GB ? nherm(LB - 1) : 0;               // Hermite index of bra row 0
-    constexpr int NKN = GK ? 0 : nherm(LK - 1);               // ket non-terminal rows
-    constexpr int NTPAD = GK ? 0 : round_up(nherm(LK - 1), 4);
-    constexpr int NKT = ncart(LK);                            // ket terminal rows
-    constexpr int RPB = NTPAD + NKT;                          // ket rows per primitive block
-    constexpr int NABP = round_up(NAB, 16);
-    constexpr int NCDP = round_up(NCD, 16);
-    constexpr SumTab<LB, LK> sum{};
-
     int J, I;
-    if (a.tiles) {
-        const int2 t = a.tiles[blockIdx.x];
-        J = t.x;
-        I = t.y + (int)threadIdx.x;
+    if (a.diag) {   // diagonal shellsets (I = J) only: lane 0 of block J
+        J = blockIdx.x;
+        I = J + (int)threadIdx.x;
+    } else if (a.tile_off) {   // ragged batch: tiles of 64 bra pairs
+        int t0;
+        ragged_tile(a.tile_off, a.nket, blockIdx.x, J, t0);
+        I = t0 * 64 + (int)threadIdx.x;
     } else {
         const int t = xcd_tile(blockIdx.x, gridDim.x);
         J = t / a.tiles_per_J;
         I = (t % a.tiles_per_J) * 64 + (int)threadIdx.x;
     }
-    const int nI = a.om.count ? a.om.count[J] : a.nbra;
+    const int nI = a.diag ? J + 1 : (a.om.count ? a.om.count[J] : a.nbra);
     if (I >= nI) return;
-
-    const int npb = a.bra.nprim[I];
-    const int npk = a.ket.nprim[J];
-    const PrimRec *bp = a.bra.prim + (int64_t)I * a.bra.kmax;
-    const PrimRec *kp = a.ket.prim + (int64_t)J * a.ket.kmax;
-    const double *Hb = a.bra.H + (int64_t)I * a.bra.pair_stride;
-    const double *HkP = a.ket.H + (int64_t)J * a.ket.pair_stride;
-
-    double out[NAB][NCD];
-#pragma unroll
-    for (int i = 0; i < NAB; ++i)
-#pragma unroll
-        for (int j = 0; j < NCD; ++j) out[i][j] = 0.0;
-
-    const int nkb = GB ? 1 : npb;
-    const int nkk = GK ? 1 : npk;
-    for (int kb = 0; kb < nkb; ++kb) {
-        double X[NHB][NCD];
-#pragma unroll
-        for (int i = 0; i < NHB; ++i)
-#pragma unroll
-            for (int j = 0; j < NCD; ++j) X[i][j] = 0.0;
-
-        for (int kk = 0; kk < nkk; ++kk) {
-            double S[L + 1];
-#pragma unroll
-            for (int m = 0; m <= L; ++m) S[m] = 0.0;
-            double PQ0 = 0.0, PQ1 = 0.0, PQ2 = 0.0;
-            const int b0 = GB ? 0 : kb, b1 = GB ? npb : kb + 1;
-            const int k0 = GK ? 0 : kk, k1 = GK ? npk : kk + 1;
-            for (int ib = b0; ib < b1; ++ib) {
-                const PrimRec B = bp[ib];
-                for (int ik = k0; ik < k1; ++ik) {
-                    const PrimRec K = kp[ik];
-                    const double pq = B.p + K.p;
-                    const double rho = B.p * K.p / pq;
-                    PQ0 = B.Px - K.Px;
-                    PQ1 = B.Py - K.Py;
-                    PQ2 = B.Pz - K.Pz;
-                    const double T = rho * (PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2);
-                    double F[L + 1];
-                    boys_eval<L>(T, F, a.boys);
-                    double f = B.ws * K.ws * rsqrt_d(pq);
-                    const double m2r = -2.0 * rho;
-#pragma unroll
-                    for (int m = 0; m <= L; ++m) {
-                        S[m] = fma(f, F[m], S[m]);
-                        f *= m2r;
-                    }
-                }
-            }
-            double R[(L + 1) * NH];
-            r_recursion<L>(S, PQ0, PQ1, PQ2, R);
-
-            // ket transform, Eq. (32): X[h][cd] += [h|q] H_ket[q][cd]
-            const double *Hk = HkP + (GK ? 0 : (int64_t)kk * RPB * NCDP);
-#pragma unroll
-            for (int r = 0; r < NKN + NKT; ++r) {
-                const int hrow = r < NKN ? r : NTPAD + (r - NKN);
-                const int qh = r < NKN ? r : nherm(LK - 1) + (r - NKN);
-                double hk[NCD];
-#pragma unroll
-                for (int j = 0; j < NCD; ++j) hk[j] = Hk[hrow * NCDP + j];
-#pragma unroll
-                for (int i = 0; i < NHB; ++i) {
-                    const double v = R[sum.idx[HB0 + i][qh]];
-#pragma unroll
-                    for (int j = 0; j < NCD; ++j) X[i][j] = fma(v, hk[j], X[i][j]);
-                }
-            }
-        }
-        // bra transform, Eq. (33): out[ab][cd] += H_bra[ab][h] X[h][cd]
-        const double *Hbk = Hb + (int64_t)(GB ? 0 : kb * NHB) * NABP;
-#pragma unroll
-        for (int i = 0; i < NHB; ++i) {
-#pragma unroll
-            for (int ab = 0; ab < NAB; ++ab) {
-                const double hb = Hbk[i * NABP + ab];
-#pragma unroll
-                for (int j = 0; j < NCD; ++j) out[ab][j] = fma(hb, X[i][j], out[ab][j]);
-            }
-        }
-    }
-
-    // store, [ij,ab,cd,kl] addressing of the caller
-    const int64_t base = (a.om.count ? a.om.obase[J] : (int64_t)J * a.om.sJ) + (int64_t)I * a.om.sI;
-    const int64_t mult = a.om.count ? (int64_t)nI : a.om.mult;
-#pragma unroll
-    for (int ab = 0; ab < NAB; ++ab)
-#pragma unroll
-        for (int j = 0; j < NCD; ++j)
-            a.om.out[base + mult * (int64_t)(a.om.oab[ab] + a.om.ocd[j])] = out[ab][j];
+    eri_valu_shellset<LB, LK, NAB, NCD, GB, GK>(a, I, J, nI);
 }
 
 template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
@@ -140,36 +30,6 @@ static void launch_valu(const EriArgs &a, int nblocks, hipStream_t s)
 {
     hipLaunchKernelGGL((eri_valu_kernel<LB, LK, NAB, NCD, GB, GK>), dim3(nblocks), dim3(64), 0, s, a);
 }
-
-#define MDX_VALU_INSTANCES(X)                                                                       \
-    /* 4-centre, spherical and Cartesian, l <= 2 per shell, bra order >= ket order */              \
-    X(0, 0, 1, 1, false, false)                                                                     \
-    X(1, 0, 3, 1, false, false) X(1, 1, 3, 3, false, false)                                         \
-    X(2, 0, 9, 1, false, false) X(2, 1, 9, 3, false, false) X(2, 2, 9, 9, false, false)             \
-    X(2, 2, 9, 5, false, false) X(2, 2, 9, 6, false, false)                                         \
-    X(2, 0, 5, 1, false, false) X(2, 1, 5, 3, false, false) X(2, 2, 5, 9, false, false)             \
-    X(2, 2, 5, 5, false, false)                                                                     \
-    X(2, 0, 6, 1, false, false) X(2, 1, 6, 3, false, false) X(2, 2, 6, 9, false, false)             \
-    X(2, 2, 6, 6, false, false)                                                                     \
-    X(3, 0, 15, 1, false, false) X(3, 1, 15, 3, false, false) X(3, 2, 15, 9, false, false)          \
-    X(3, 2, 15, 5, false, false)                                                                    \
-    X(3, 0, 18, 1, false, false) X(3, 1, 18, 3, false, false) X(3, 2, 18, 9, false, false)          \
-    X(3, 2, 18, 6, false, false)                                                                    \
-    X(4, 0, 25, 1, false, false) X(4, 1, 25, 3, false, false) X(4, 2, 25, 5, false, false)          \
-    X(4, 0, 36, 1, false, false) X(4, 1, 36, 3, false, false) X(4, 2, 36, 6, false, false)          \
-    /* 3-centre (X|cd), solid single function (grouped) or Cartesian (unit partner) */             \
-    X(0, 0, 1, 1, true, false) X(0, 1, 1, 3, true, false) X(0, 2, 1, 9, true, false)                \
-    X(0, 2, 1, 5, true, false) X(0, 4, 1, 25, true, false)                                          \
-    X(1, 0, 3, 1, true, false) X(1, 1, 3, 3, true, false) X(1, 2, 3, 9, true, false)                \
-    X(1, 2, 3, 5, true, false) X(1, 4, 3, 25, true, false)                                          \
-    X(2, 2, 5, 5, true, false) X(2, 2, 5, 9, true, false) X(2, 4, 5, 25, true, false)               \
-    X(0, 2, 1, 6, false, false) X(1, 2, 3, 6, false, false) X(2, 2, 6, 6, false, false)             \
-    X(0, 4, 1, 36, false, false) X(1, 4, 3, 36, false, false)                                       \
-    /* 2-centre (a|c) */                                                                            \
-    X(0, 0, 1, 1, true, true) X(1, 1, 3, 3, true, true) X(2, 2, 5, 5, true, true)                   \
-    X(2, 0, 5, 1, true, true) X(2, 1, 5, 3, true, true) X(1, 0, 3, 1, true, true)                   \
-    X(3, 3, 7, 7, true, true) X(4, 4, 9, 9, true, true) X(3, 2, 7, 5, true, true)                   \
-    X(1, 1, 3, 3, false, false) X(2, 2, 6, 6, false, false)
 
 bool eri_valu_launch(const EriKey &k, const EriArgs &a, int nblocks, hipStream_t s)
 {

@@ -16,6 +16,20 @@ __device__ __forceinline__ int xcd_tile(int b, int n)
     return x * q + min(x, r) + k;
 }
 
+// ket pair J and first bra pair of tile t of a ragged batch: tile_off[J] is
+// the number of tiles before ket J (binary search; kets without tiles are skipped)
+__device__ __forceinline__ void ragged_tile(const int32_t *tile_off, int nket, int t, int &J, int &t0)
+{
+    int lo = 0, hi = nket;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (tile_off[mid] <= t) lo = mid;
+        else hi = mid;
+    }
+    J = lo;
+    t0 = t - tile_off[lo];
+}
+
 // class key of an integral kernel (kernel orientation)
 struct EriKey {
     int LB, LK;     // total Hermite order of bra and ket
@@ -26,8 +40,10 @@ struct EriKey {
 struct EriArgs {
     SideDev bra, ket;
     int nbra, nket;
-    int tiles_per_J;          // dense tiling: bra tiles per ket pair
-    const int2 *tiles;        // explicit (J, I0) tile list, or null
+    int tiles_per_J;          // dense tiling: bra tiles (VALU) / 8-pair bra blocks (MFMA)
+    const int32_t *tile_off;  // ragged: [nket+1] tiles before each ket pair (VALU tile: 64 bra
+                              // pairs, MFMA tile: one), or null
+    int diag;                 // 1: only the diagonal shellsets I = J (one per block)
     const double *boys;       // Boys table
     const double *Tket;       // terminal ket matrix [ncart(LK) pad 4][ncolp] (MFMA kernel)
     int ntile_total;          // number of tiles (persistent kernels)
@@ -83,6 +99,22 @@ struct GradKey {
 };
 int eri_grad_variants(const GradKey &k);
 bool eri_grad_launch(const GradKey &k, const GradArgs &a, int nblocks, int variant, hipStream_t s);
+
+// persistent work-queue launch over several ragged batches of one kernel instance
+struct QueueArgs {
+    const EriArgs *desc;   // [nb] kernel arguments of each batch (device memory)
+    const int32_t *base;   // [nb+1] work items (tiles) before each batch
+    int nb;
+    int total;             // base[nb]
+    int *counter;          // zero before the launch
+};
+bool eri_mfma_config(const EriKey &k, int variant, int bra_kmax, int ket_kmax, int &nqmax, size_t &lds, int &nthreads);
+// sets the dynamic-LDS limit of the queue kernel; returns resident workgroups per CU (0: unusable)
+int eri_queue_prepare(const EriKey &k, bool mfma, int variant, size_t lds);
+bool eri_queue_launch(const EriKey &k, bool mfma, int variant, const QueueArgs &q, int nblocks, size_t lds,
+                      hipStream_t s);
+void launch_schwarz(const double *diag, int npair, int nab, double *Q, hipStream_t s);
+void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
 
 void launch_boys(const double *x, int n, int mmax, double *F, const double *tab, hipStream_t s);
 

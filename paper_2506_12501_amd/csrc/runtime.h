@@ -56,6 +56,7 @@ struct ClassPlan {
     int cart = 0;
     int la = 0, lb = 0, lc = 0, ld = 0;   // caller's
     bool swapped = false;                 // kernel bra = caller ket
+    bool diag = false;                    // only the shellsets I = J (Schwarz factors)
     SidePlan bra, ket;
     EriKey key{};
     KernelKind kind = K_VALU;
@@ -65,15 +66,15 @@ struct ClassPlan {
     std::vector<int32_t> count;
     std::vector<int64_t> obase;
     int64_t out_doubles = 0;
-    // tiles for ragged launches: (J, I0)
-    std::vector<int2> tiles;
+    // ragged launches: tiles before each kernel ket pair ([nket+1])
+    std::vector<int32_t> tile_off;
     const double *tket = nullptr;
 };
 
 // workspace layout of one class
 struct WsLayout {
     size_t pairs_bra, pairs_ket, np_bra, np_ket, prim_bra, prim_ket, H_bra, H_ket;
-    size_t count, obase, tiles;
+    size_t count, obase, tile_off;
     size_t total;
 };
 
@@ -89,6 +90,22 @@ int grad_class_variants(int ncentre, int la, int lb, int lc, int ld, bool cart);
 mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
                       int32_t nket, const int32_t *ket, const int32_t *bra_count, int flags, ClassPlan &cp);
 WsLayout ws_layout(const ClassPlan &cp, size_t base);
+// device addresses of one class's tables and pair data
+struct ClassDev {
+    const PairRec *pairs_bra, *pairs_ket;
+    const int32_t *count;
+    const int64_t *obase;
+    const int32_t *tile_off;
+    PrimRec *prim_bra, *prim_ket;
+    int32_t *np_bra, *np_ket;
+    double *H_bra, *H_ket;
+};
+ClassDev class_dev(const WsLayout &L, char *ws);
+mdx_status upload_tables(const ClassPlan &cp, const ClassDev &d, hipStream_t s);
+void enqueue_pairdata(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const ClassDev &d, int side,
+                      hipStream_t s);
+mdx_status class_args(mdx_ctx *c, const ClassPlan &cp, const ClassDev &d, double *out, EriArgs &a, int &nblocks);
+mdx_status launch_class(mdx_ctx *c, const ClassPlan &cp, const EriArgs &a, int nblocks, hipStream_t s);
 mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
                          double *out, hipStream_t s, bool upload);
 

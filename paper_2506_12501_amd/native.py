@@ -57,6 +57,9 @@ EXPORTS = {
                                                       _pi32, _i32, _pi32, ctypes.c_int]),
     "mdx_eri_grad_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32,
                                           _pi32, ctypes.c_int, _p, _p, _p, ctypes.c_size_t, _p]),
+    "mdx_schwarz_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
+    "mdx_schwarz": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int, _p, _p,
+                                   ctypes.c_size_t, _p]),
     "mdx_plan_create": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int,
                                        ctypes.POINTER(MdxBatchDesc), ctypes.c_int, ctypes.POINTER(_p)]),
     "mdx_plan_workspace_size": (ctypes.c_size_t, [_p]),
@@ -234,3 +237,77 @@ def eri_grad(shells: DeviceShells, ncentre: int, bra, ket, adjoint, cartesian: b
                                _i32p(ket), flags, _ptr(W), _ptr(grad), ctypes.c_void_p(aligned), wsz,
                                _stream(torch)), "mdx_eri_grad_batch")
     return grad.view(nket, 12, nbra).permute(2, 1, 0)
+
+
+def schwarz(shells: DeviceShells, pairs, cartesian: bool = False, ctx: Context | None = None):
+    """Q[i] = sqrt(max_ab |(ab|ab)|) of each shell pair (one class), on the device."""
+    import torch
+    dev = shells.center.device
+    ctx = ctx or Context.get(dev.index or 0)
+    pairs = _pairs(pairs)
+    n = pairs.shape[0]
+    flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
+    L = lib()
+    Q = torch.empty(n, dtype=torch.float64, device=dev)
+    wsz = L.mdx_schwarz_workspace_size(ctx.handle, ctypes.byref(shells.struct), n, _i32p(pairs), flags)
+    if wsz == 0:
+        check(L.mdx_schwarz(ctx.handle, ctypes.byref(shells.struct), n, _i32p(pairs), flags, None, None, 0,
+                            _stream(torch)), "mdx_schwarz")
+    ws = torch.empty(wsz // 8 + 32, dtype=torch.float64, device=dev)
+    aligned = (_ptr(ws) + 255) // 256 * 256
+    check(L.mdx_schwarz(ctx.handle, ctypes.byref(shells.struct), n, _i32p(pairs), flags, _ptr(Q),
+                        ctypes.c_void_p(aligned), wsz, _stream(torch)), "mdx_schwarz")
+    return Q
+
+
+class Batch:
+    """One class batch of a plan: pair lists, optional ragged bra prefix
+    counts per ket pair, and the offset of its output block."""
+
+    def __init__(self, ncentre, bra, ket, bra_count=None, out_offset=0):
+        self.ncentre = ncentre
+        self.bra = _pairs(bra)
+        self.ket = _pairs(ket)
+        self.bra_count = None if bra_count is None else np.ascontiguousarray(bra_count, dtype=np.int32)
+        self.out_offset = int(out_offset)
+
+
+class Plan:
+    """mdx_plan over a list of Batch; fused=True -> one captured graph with
+    persistent work-queue kernels."""
+
+    def __init__(self, shells: DeviceShells, batches, cartesian=False, fused=False, ctx: Context | None = None):
+        import torch
+        self.ctx = ctx or Context.get(shells.center.device.index or 0)
+        self.shells = shells
+        self.batches = list(batches)
+        n = len(self.batches)
+        descs = (MdxBatchDesc * max(n, 1))()
+        for i, b in enumerate(self.batches):
+            descs[i] = MdxBatchDesc(b.ncentre, b.bra.shape[0], _i32p(b.bra), b.ket.shape[0], _i32p(b.ket),
+                                    _i32p(b.bra_count) if b.bra_count is not None else None, b.out_offset)
+        flags = (MDX_CARTESIAN if cartesian else 0) | (MDX_FUSED if fused else 0)
+        h = _p()
+        check(lib().mdx_plan_create(self.ctx.handle, ctypes.byref(shells.struct), n, descs, flags, ctypes.byref(h)),
+              "mdx_plan_create")
+        self.handle = h
+        self.ws_bytes = lib().mdx_plan_workspace_size(h)
+        self.out_size = lib().mdx_plan_output_size(h)
+        self.ws = torch.empty(self.ws_bytes // 8 + 32, dtype=torch.float64, device=shells.center.device)
+        self.wsp = (_ptr(self.ws) + 255) // 256 * 256
+
+    def execute(self, out=None):
+        import torch
+        if out is None:
+            out = torch.empty(max(self.out_size, 1), dtype=torch.float64, device=self.shells.center.device)
+        check(lib().mdx_plan_execute(self.handle, ctypes.byref(self.shells.struct), ctypes.c_void_p(_ptr(out)),
+                                     ctypes.c_void_p(self.wsp), self.ws_bytes, _stream(torch)), "mdx_plan_execute")
+        return out
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().mdx_plan_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass

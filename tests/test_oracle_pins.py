@@ -403,3 +403,23 @@ def test_contraction_is_linear_in_primitives():
         bb = sb.basis()
         total += O.eri(bb, 4, [[new[0], new[1]]], [[new[2], new[3]]])[0, :, :, 0]
     assert np.allclose(total, full, rtol=1e-13, atol=1e-15)
+
+
+def test_cluster_fp64_within_schwarz_scaled_bar():
+    """The fp64 oracle against its __float128 build on the screened s/p batches
+    of a small water-like cluster (exponents to 5000, K = 8 contractions, many
+    one-centre quartets that vanish by symmetry): every element within 1e-12
+    abs, 1e-10 rel, or 1e-12 Q_ab Q_cd -- the bar the GPU plans are held to,
+    which therefore is one that fp64 evaluation can meet."""
+    from paper_2506_12501_amd import screening as S
+    import tests.cluster_util as T
+    b, _ = W.water_cluster(seed=5, nx=2, ny=2, nz=2)
+    P = S.canonical_pairs(b.l, 1)
+    Q = {pc: T.oracle_Q(b, p) for pc, p in P.items()}
+    bts = S.class_batches(P, Q, 1e-12)
+    S.with_offsets(bts, b.l)
+    assert [bt["name"] for bt in bts] == ["(ss|ss)", "(ps|ss)", "(ps|ps)", "(pp|ss)", "(pp|ps)", "(pp|pp)"]
+    for bt in bts:
+        ref, scale = T.oracle_batch(b, bt, quad=True)
+        f64, _ = T.oracle_batch(b, bt, quad=False)
+        T.assert_close_cs(f64, ref, scale, bt["name"])

@@ -190,6 +190,111 @@ def extra_legs(native, ctx, torch, tune, reps):
     return out
 
 
+def cluster_leg(native, ctx, torch, reps, sample):
+    """Mixed-L screened batch over the 32-molecule water-like cluster: every
+    canonical class in one plan; plain per-class launches vs one fused graph."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_2506_12501_amd import flops as F, screening as S, workloads as W
+    from tests.cluster_util import oracle_Q
+    from tests.gpu_util import ATOL, RTOL
+    b, _ = W.water_cluster(seed=0)
+    sh = native.DeviceShells(b)
+    P = S.canonical_pairs(b.l, 2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Qd = {pc: native.schwarz(sh, p) for pc, p in P.items()}
+    torch.cuda.synchronize()
+    schwarz_ms = (time.perf_counter() - t0) * 1e3
+    Q = {pc: q.cpu().numpy() for pc, q in Qd.items()}
+    batches = S.class_batches(P, Q, 1e-12, nprim=b.nprim)
+    total = S.with_offsets(batches, b.l)
+    nquart = sum(bt["quartets"] for bt in batches)
+    log(f"cluster: {len(b.l)} shells, {sum(p.shape[0] for p in P.values())} pairs, {len(batches)} batches, "
+        f"{nquart} quartets, {total * 8 / 1e9:.2f} GB output")
+    nb = [native.Batch(4, bt["bra"], bt["ket"], bt["bra_count"], bt["out_offset"]) for bt in batches]
+    plain = native.Plan(sh, nb, fused=False)
+    fused = native.Plan(sh, nb, fused=True)
+    o_plain = torch.empty(total, dtype=torch.float64, device="cuda")
+    o_fused = torch.empty(total, dtype=torch.float64, device="cuda")
+
+    def timed(plan, out):
+        plan.execute(out)                       # warm-up (graph capture for the fused plan)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        ts = []
+        for _ in range(reps):
+            e0.record()
+            plan.execute(out)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return ts
+
+    t_plain = timed(plain, o_plain)
+    t_fused = timed(fused, o_fused)
+    identical = bool(torch.equal(o_plain, o_fused))
+    log(f"cluster: plain {min(t_plain):.2f} ms, fused {min(t_fused):.2f} ms")
+    # algorithmic FLOPs with each pair's own contraction degree
+    Kp = lambda pairs: b.nprim[pairs[:, 0]].astype(np.float64) * b.nprim[pairs[:, 1]]
+    flops = 0.0
+    for bt in batches:
+        la, lb = b.l[bt["bra"][0]]
+        lc, ld = b.l[bt["ket"][0]]
+        f11 = F.shellset_flops(la, lb, lc, ld, 1, 1, 1, 1)
+        per_q = F.shellset_flops(la, lb, lc, ld, 1, 1, 2, 1) - f11
+        per_b = f11 - per_q
+        kb, kk = Kp(bt["bra"]), Kp(bt["ket"])
+        csum = np.concatenate([[0.0], np.cumsum(kb)])
+        sb = csum[bt["bra_count"]]                      # sum of K_bra over each ket's prefix
+        flops += float(np.sum(sb * kk) * per_q + np.sum(sb) * per_b)
+    # stratified parity sample against the __float128 oracle
+    rng = np.random.default_rng(11)
+    out_h = None
+    nchk = nbad = 0
+    worst_cs = 0.0
+    for bt in batches:
+        cnt = bt["bra_count"]
+        starts = np.concatenate([[0], np.cumsum(cnt)])
+        pick = np.unique(rng.integers(0, bt["quartets"], min(sample, bt["quartets"])))
+        ks = np.searchsorted(starts, pick, side="right") - 1
+        iis = pick - starts[ks]
+        qs = np.stack([iis, ks], axis=1)
+        ref = O.eri(b, 4, bt["bra"], bt["ket"], quartets=qs, quad=True)          # [q, nab, ncd]
+        qq = oracle_Q(b, bt["bra"])[iis] * oracle_Q(b, bt["ket"])[ks]
+        nab, ncd = bt["nab"], bt["ncd"]
+        obase = np.concatenate([[0], np.cumsum(cnt.astype(np.int64) * nab * ncd)])
+        ab, cd = np.meshgrid(np.arange(nab), np.arange(ncd), indexing="ij")
+        idx = (bt["out_offset"] + obase[ks][:, None, None] + iis[:, None, None]
+               + cnt[ks][:, None, None] * (ab[None] + nab * cd[None]))
+        got = o_fused[torch.as_tensor(idx.reshape(-1), device="cuda")].cpu().numpy().reshape(ref.shape)
+        err = np.abs(got - ref)
+        ok = (err <= ATOL) | (err <= RTOL * np.abs(ref)) | (err <= 1e-12 * qq[:, None, None])
+        nchk += ok.size
+        nbad += int(np.count_nonzero(~ok))
+        worst_cs = max(worst_cs, float(np.max(err / qq[:, None, None])))
+    best_f, best_p = min(t_fused), min(t_plain)
+    return {
+        "workload": "32 water-like molecules (96 atoms, 3 A simple-cubic lattice, 384 shells, 800 primitives, "
+                    "768 spherical AOs); heavy s K=(8,1,1), p K=(3,1), d K=1; light s K=(3,1), p K=1; zeta "
+                    "log-U[0.1,5000]; canonical quartets with Q_ab Q_cd >= 1e-12, 21 classes split into batches of equal (K_bra, K_ket), seed 0",
+        "classes": len({bt["name"] for bt in batches}), "batches": len(batches), "quartets": nquart,
+        "output_gb": total * 8 / 1e9,
+        "schwarz_ms": schwarz_ms,
+        "plain_ms": best_p, "fused_ms": best_f, "plain_ms_all": t_plain, "fused_ms_all": t_fused,
+        "fused_speedup": best_p / best_f, "outputs_identical": identical,
+        "shellsets_per_s_fused": nquart / (best_f * 1e-3),
+        "algorithmic_gflop": flops / 1e9, "fused_tflops": flops / (best_f * 1e-3) / 1e12,
+        "pct_fp64_peak_fused": 100 * flops / (best_f * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+        "parity_sample": {"checked": nchk, "failed": nbad, "max_err_over_QQ": worst_cs, "reference": "__float128 oracle",
+                          "tolerance": "|err| <= 1e-12 or <= 1e-10 |ref| or <= 1e-12 Q_ab Q_cd",
+                          "sample": f"up to {sample} quartets per class, uniform"},
+        "per_class_quartets": {n: sum(bt["quartets"] for bt in batches if bt["name"] == n)
+                               for n in dict.fromkeys(bt["name"] for bt in batches)},
+    }
+
+
 def class_flops(batch):
     from paper_2506_12501_amd import flops as F, workloads as W
     la, lb, lc, ld = W.parse_class(batch.name)
@@ -262,6 +367,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=224)
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient / high-L / s-p legs")
     ap.add_argument("--extra-reps", type=int, default=5)
+    ap.add_argument("--no-cluster", action="store_true", help="skip the mixed-L cluster leg")
+    ap.add_argument("--cluster-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -352,6 +459,10 @@ def main():
     if not args.no_extras:
         extras = extra_legs(native, ctx, torch, not args.no_tune, args.extra_reps)
         log("extra legs done")
+    cluster = None
+    if not args.no_cluster:
+        cluster = cluster_leg(native, ctx, torch, args.extra_reps, args.cluster_sample)
+        log("cluster leg done")
 
     cpu, parity = (None, None)
     if not args.no_cpu:
@@ -383,6 +494,7 @@ def main():
         "cpu_baseline": cpu,
         "parity_sample": parity,
         "extras": extras,
+        "mixed_cluster": cluster,
         "wall_s_timed": wall,
     }
     print(json.dumps(rec), flush=True)

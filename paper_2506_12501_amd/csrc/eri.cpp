@@ -114,6 +114,10 @@ SidePlan make_side(const mdx_shells *sh, const int32_t *lst, int32_t n, bool two
         kmax = std::max(kmax, r.ka * r.kb);
     }
     sp.g = make_geom(l0, two ? l1 : -1, cart, role, n, kmax, allow_grouped);
+    if (!sp.g.grouped) {
+        for (int32_t i = 0; i < n; ++i)
+            for (int k = 0; k < sp.pairs[i].ka * sp.pairs[i].kb; ++k) sp.items.push_back(make_int2(i, k));
+    }
     return sp;
 }
 
@@ -221,6 +225,8 @@ WsLayout ws_layout(const ClassPlan &cp, size_t base)
     const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
     L.pairs_bra = take(nb * sizeof(PairRec));
     L.pairs_ket = take(nk * sizeof(PairRec));
+    L.items_bra = take(cp.bra.items.size() * sizeof(int2));
+    L.items_ket = take(cp.ket.items.size() * sizeof(int2));
     L.np_bra = take(nb * sizeof(int32_t));
     L.np_ket = take(nk * sizeof(int32_t));
     L.prim_bra = take(nb * cp.bra.g.kmax * sizeof(PrimRec));
@@ -239,6 +245,8 @@ ClassDev class_dev(const WsLayout &L, char *ws)
     ClassDev d{};
     d.pairs_bra = (const PairRec *)(ws + L.pairs_bra);
     d.pairs_ket = (const PairRec *)(ws + L.pairs_ket);
+    d.items_bra = (const int2 *)(ws + L.items_bra);
+    d.items_ket = (const int2 *)(ws + L.items_ket);
     d.count = (const int32_t *)(ws + L.count);
     d.obase = (const int64_t *)(ws + L.obase);
     d.tile_off = (const int32_t *)(ws + L.tile_off);
@@ -256,6 +264,12 @@ mdx_status upload_tables(const ClassPlan &cp, const ClassDev &d, hipStream_t s)
     const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
     HIP_TRY2(hipMemcpyAsync((void *)d.pairs_bra, cp.bra.pairs.data(), nb * sizeof(PairRec), hipMemcpyHostToDevice, s));
     HIP_TRY2(hipMemcpyAsync((void *)d.pairs_ket, cp.ket.pairs.data(), nk * sizeof(PairRec), hipMemcpyHostToDevice, s));
+    if (!cp.bra.items.empty())
+        HIP_TRY2(hipMemcpyAsync((void *)d.items_bra, cp.bra.items.data(), cp.bra.items.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, s));
+    if (!cp.ket.items.empty())
+        HIP_TRY2(hipMemcpyAsync((void *)d.items_ket, cp.ket.items.data(), cp.ket.items.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, s));
     if (!cp.count.empty()) {
         HIP_TRY2(hipMemcpyAsync((void *)d.count, cp.count.data(), cp.count.size() * 4, hipMemcpyHostToDevice, s));
         HIP_TRY2(hipMemcpyAsync((void *)d.obase, cp.obase.data(), cp.obase.size() * 8, hipMemcpyHostToDevice, s));
@@ -273,6 +287,8 @@ void enqueue_pairdata(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, con
     PairDataArgs pa{};
     pa.g = sp.g;
     pa.pairs = side == 0 ? d.pairs_bra : d.pairs_ket;
+    pa.items = side == 0 ? d.items_bra : d.items_ket;
+    pa.nitems = (int)sp.items.size();
     pa.center = sh->center;
     pa.expo = sh->exponent;
     pa.coef = sh->coef;

@@ -76,7 +76,7 @@ struct GradPlan {
 };
 
 struct GradWs {
-    size_t pairs_d, pairs_w, np_d, np_w, prim_d, prim_w, H_d, H_w, total;
+    size_t pairs_d, pairs_w, items_d, items_w, np_d, np_w, prim_d, prim_w, H_d, H_w, total;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -89,6 +89,8 @@ GradWs grad_ws(const GradPass &p)
     const size_t nd = p.d.pairs.size(), nw = p.w.pairs.size();
     L.pairs_d = take(nd * sizeof(PairRec));
     L.pairs_w = take(nw * sizeof(PairRec));
+    L.items_d = take(p.d.items.size() * sizeof(int2));
+    L.items_w = take(p.w.items.size() * sizeof(int2));
     L.np_d = take(nd * sizeof(int32_t));
     L.np_w = take(nw * sizeof(int32_t));
     L.prim_d = take(nd * p.d.g.kmax * sizeof(PrimRec));
@@ -232,11 +234,17 @@ extern "C" mdx_status mdx_eri_grad_batch(mdx_ctx *c, const mdx_shells *sh, int n
         const size_t nd = p.d.pairs.size(), nw = p.w.pairs.size();
         HIP_TRY2(hipMemcpyAsync(w + L.pairs_d, p.d.pairs.data(), nd * sizeof(PairRec), hipMemcpyHostToDevice, s));
         HIP_TRY2(hipMemcpyAsync(w + L.pairs_w, p.w.pairs.data(), nw * sizeof(PairRec), hipMemcpyHostToDevice, s));
+        HIP_TRY2(hipMemcpyAsync(w + L.items_d, p.d.items.data(), p.d.items.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, s));
+        HIP_TRY2(hipMemcpyAsync(w + L.items_w, p.w.items.data(), p.w.items.size() * sizeof(int2),
+                                hipMemcpyHostToDevice, s));
         for (int side = 0; side < 2; ++side) {
             const SidePlan &sp = side == 0 ? p.d : p.w;
             PairDataArgs pa{};
             pa.g = sp.g;
             pa.pairs = (const PairRec *)(w + (side == 0 ? L.pairs_d : L.pairs_w));
+            pa.items = (const int2 *)(w + (side == 0 ? L.items_d : L.items_w));
+            pa.nitems = (int)sp.items.size();
             pa.center = sh->center;
             pa.expo = sh->exponent;
             pa.coef = sh->coef;

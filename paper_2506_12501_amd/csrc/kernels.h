@@ -56,6 +56,8 @@ struct EriArgs {
 struct PairDataArgs {
     SideGeom g;
     const PairRec *pairs;
+    const int2 *items;   // (pair, primitive pair) of every block; unused for a grouped side
+    int nitems;
     const double *center, *expo, *coef;
     const double *Ca, *Cb;   // solid coefficients [nsph(l)][ncart(l)], null for Cartesian
     PrimRec *prim;

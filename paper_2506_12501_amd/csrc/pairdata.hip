@@ -16,9 +16,6 @@
 
 namespace mdx {
 
-constexpr int PD_LMAX = 7;
-constexpr int PD_ED = PD_LMAX + 1;
-constexpr int PD_ET = 2 * PD_LMAX + 1;
 
 __device__ __forceinline__ void cart_of(int l, int idx, int &ax, int &ay, int &az)
 {
@@ -30,18 +27,63 @@ __device__ __forceinline__ void cart_of(int l, int idx, int &ax, int &ay, int &a
     ax = l - s;
 }
 
+// LDS of one block, sized for the side's angular momenta (see pairdata_lds_bytes)
+struct PdLayout {
+    int EA, EB, ET;   // E[3][EA][EB][ET]
+    int na, nb;       // output functions per centre
+};
+
+__host__ __device__ inline PdLayout pd_layout(const SideGeom &g)
+{
+    PdLayout L;
+    const int d = g.role == 2 ? 1 : 0;
+    const int lb = g.lb < 0 ? 0 : g.lb;
+    L.EA = g.la + d + 1;
+    L.EB = lb + d + 1;
+    L.ET = g.la + lb + 2 * d + 1;
+    L.na = nfunc(g.la, g.cart);
+    L.nb = g.lb >= 0 ? nfunc(lb, g.cart) : 1;
+    return L;
+}
+
+constexpr int PD_NTM = 10;   // nonzero Cartesian terms per real solid harmonic, l <= 7
+
+__host__ __device__ inline size_t pairdata_lds_bytes(const SideGeom &g)
+{
+    const PdLayout L = pd_layout(g);
+    const size_t nf = L.na + L.nb;
+    return (3 * (size_t)L.EA * L.EB * L.ET + nf * PD_NTM + 2) * 8 + (nf + nf * PD_NTM * 3) * 4;
+}
+
 __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
 {
     const SideGeom &g = a.g;
-    const int kblk = g.grouped ? 1 : g.kmax;
-    const int pair = blockIdx.x / kblk;
-    const int k = blockIdx.x % kblk;
+    // one block per primitive pair of a pair (items), or per pair (grouped side)
+    int pair, k;
+    if (g.grouped) {
+        pair = blockIdx.x;
+        k = 0;
+    } else {
+        const int2 it = a.items[blockIdx.x];
+        pair = it.x;
+        k = it.y;
+    }
     const PairRec pr = a.pairs[pair];
     const int np = pr.ka * pr.kb;
     const int la = g.la;
     const int lb = g.lb < 0 ? 0 : g.lb;
-    __shared__ double E[3][PD_ED][PD_ED][PD_ET];
-    __shared__ double sh_pref;
+    const PdLayout PL = pd_layout(g);
+    const int EA = PL.EA, EB = PL.EB, ET = PL.ET;
+    extern __shared__ double pd_smem[];
+    double *Eb = pd_smem;                                   // [3][EA][EB][ET]
+#define E(ax, i, j, t) Eb[(((ax) * EA + (i)) * EB + (j)) * ET + (t)]
+    double &sh_pref = Eb[3 * EA * EB * ET];
+    double *ta_w = Eb + 3 * EA * EB * ET + 2;               // [na][NTM]
+    double *tb_w = ta_w + PL.na * PD_NTM;                   // [nb][NTM]
+    int *ta_n = (int *)(tb_w + PL.nb * PD_NTM);             // [na]
+    int *tb_n = ta_n + PL.na;                               // [nb]
+    int *ta_c = tb_n + PL.nb;                               // [na][NTM][3]
+    int *tb_c = ta_c + PL.na * PD_NTM * 3;                  // [nb][NTM][3]
 
     if (threadIdx.x == 0 && k == 0) a.nprim[pair] = np;
 
@@ -100,23 +142,23 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         const double P = (za * Av[ax] + zb * B[ax]) / p;
         const double XPA = P - Av[ax], XPB = P - B[ax];
         // Eqs. (10), (11) with E^0_00 = 1 (the exponential is applied below)
-        E[ax][0][0][0] = 1.0;
+        E(ax, 0, 0, 0) = 1.0;
         // the derivative-bra role also needs a+1 and b+1 (d/dA of Eq. (1))
         const int la_e = la + (g.role == 2), lb_e = lb + (g.role == 2);
         for (int i = 0; i <= la_e; ++i) {
             if (i > 0)
                 for (int t = 0; t <= i; ++t) {
-                    double v = XPA * (t <= i - 1 ? E[ax][i - 1][0][t] : 0.0);
-                    if (t > 0) v += i2p * E[ax][i - 1][0][t - 1];
-                    if (t + 1 <= i - 1) v += (t + 1) * E[ax][i - 1][0][t + 1];
-                    E[ax][i][0][t] = v;
+                    double v = XPA * (t <= i - 1 ? E(ax, i - 1, 0, t) : 0.0);
+                    if (t > 0) v += i2p * E(ax, i - 1, 0, t - 1);
+                    if (t + 1 <= i - 1) v += (t + 1) * E(ax, i - 1, 0, t + 1);
+                    E(ax, i, 0, t) = v;
                 }
             for (int j = 1; j <= lb_e; ++j)
                 for (int t = 0; t <= i + j; ++t) {
-                    double v = XPB * (t <= i + j - 1 ? E[ax][i][j - 1][t] : 0.0);
-                    if (t > 0) v += i2p * E[ax][i][j - 1][t - 1];
-                    if (t + 1 <= i + j - 1) v += (t + 1) * E[ax][i][j - 1][t + 1];
-                    E[ax][i][j][t] = v;
+                    double v = XPB * (t <= i + j - 1 ? E(ax, i, j - 1, t) : 0.0);
+                    if (t > 0) v += i2p * E(ax, i, j - 1, t - 1);
+                    if (t + 1 <= i + j - 1) v += (t + 1) * E(ax, i, j - 1, t + 1);
+                    E(ax, i, j, t) = v;
                 }
         }
     }
@@ -144,7 +186,8 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
     if (g.role != 1) {
         row0 = k * g.nh;
         nrows = g.nh;
-        if (k == g.kmax - 1) nrows = g.rows_per_block - row0;   // include zero padding
+        // the pair's last primitive also zeroes the rows up to the next 16-row tile
+        if (k == np - 1) nrows = round_up(np * g.nh, 16) - row0;
         Hp = a.H + (int64_t)pair * g.pair_stride;
     } else {
         row0 = 0;
@@ -154,11 +197,8 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
     const int nb_out = g.lb >= 0 ? nfunc(lb, g.cart) : 1;
     const int na_out = nfunc(la, g.cart);
     // nonzero Cartesian->solid terms of every output function, both centres
-    // (at most 10 nonzero terms per real solid harmonic for l <= 7; one per Cartesian)
-    constexpr int NF = PD_ED * (PD_ED + 1) / 2, NTM = 10;
-    __shared__ int ta_n[NF], tb_n[NF];
-    __shared__ int ta_c[NF][NTM][3], tb_c[NF][NTM][3];
-    __shared__ double ta_w[NF][NTM], tb_w[NF][NTM];
+    // (at most PD_NTM nonzero terms per real solid harmonic; one per Cartesian)
+    constexpr int NTM = PD_NTM;
     for (int side = 0; side < 2; ++side) {
         const int l = side == 0 ? la : lb, nout = side == 0 ? na_out : nb_out;
         const double *C = side == 0 ? a.Ca : a.Cb;
@@ -170,10 +210,10 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
                 if (w == 0.0 || n == NTM) continue;
                 int x, y, z;
                 cart_of(l, ic, x, y, z);
-                (side == 0 ? ta_c : tb_c)[mo][n][0] = x;
-                (side == 0 ? ta_c : tb_c)[mo][n][1] = y;
-                (side == 0 ? ta_c : tb_c)[mo][n][2] = z;
-                (side == 0 ? ta_w : tb_w)[mo][n] = w;
+                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 0] = x;
+                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 1] = y;
+                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 2] = z;
+                (side == 0 ? ta_w : tb_w)[mo * NTM + n] = w;
                 ++n;
             }
             (side == 0 ? ta_n : tb_n)[mo] = n;
@@ -185,7 +225,7 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         // (likewise for B), so along axis i the Hermite coefficient of the derivative is
         // 2 zeta_a E^{a+1,b}_t - a_i E^{a-1,b}_t, expanded about the same P up to order L+1.
         auto e1 = [&](int ax, int i, int j, int t) -> double {
-            return (i >= 0 && j >= 0 && t <= i + j) ? E[ax][i][j][t] : 0.0;
+            return (i >= 0 && j >= 0 && t <= i + j) ? E(ax, i, j, t) : 0.0;
         };
         const int64_t dstride = (int64_t)g.rows_per_block * g.ncolp;
         for (int e = threadIdx.x; e < 6 * nrows * g.ncolp; e += blockDim.x) {
@@ -202,9 +242,9 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
                 double s = 0.0;
                 for (int i = 0; i < ta_n[ma]; ++i)
                     for (int j = 0; j < tb_n[mb]; ++j) {
-                        double f = ta_w[ma][i] * tb_w[mb][j];
+                        double f = ta_w[ma * NTM + i] * tb_w[mb * NTM + j];
                         for (int ax = 0; ax < 3 && f != 0.0; ++ax) {
-                            const int ai = ta_c[ma][i][ax], bi = tb_c[mb][j][ax], t = tv[ax];
+                            const int ai = ta_c[(ma * NTM + i) * 3 + ax], bi = tb_c[(mb * NTM + j) * 3 + ax], t = tv[ax];
                             double c;
                             if (ax != dax) c = e1(ax, ai, bi, t);
                             else if (onA) c = 2.0 * za * e1(ax, ai + 1, bi, t) - ai * e1(ax, ai - 1, bi, t);
@@ -237,11 +277,13 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
             const int ma = col / nb_out, mb = col % nb_out;
             double s = 0.0;
             for (int i = 0; i < ta_n[ma]; ++i) {
-                const int ax = ta_c[ma][i][0], ay = ta_c[ma][i][1], az = ta_c[ma][i][2];
+                const int *ca = ta_c + (ma * NTM + i) * 3;
+                const int ax = ca[0], ay = ca[1], az = ca[2];
                 for (int j = 0; j < tb_n[mb]; ++j) {
-                    const int bx = tb_c[mb][j][0], by = tb_c[mb][j][1], bz = tb_c[mb][j][2];
+                    const int *cb = tb_c + (mb * NTM + j) * 3;
+                    const int bx = cb[0], by = cb[1], bz = cb[2];
                     if (r.t > ax + bx || r.u > ay + by || r.v > az + bz) continue;
-                    s += ta_w[ma][i] * tb_w[mb][j] * E[0][ax][bx][r.t] * E[1][ay][by][r.u] * E[2][az][bz][r.v];
+                    s += ta_w[ma * NTM + i] * tb_w[mb * NTM + j] * E(0, ax, bx, r.t) * E(1, ay, by, r.u) * E(2, az, bz, r.v);
                 }
             }
             v = pref * s;
@@ -251,11 +293,12 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
     }
 }
 
+#undef E
+
 void launch_pairdata(const PairDataArgs &a, hipStream_t s)
 {
-    const int kblk = a.g.grouped ? 1 : a.g.kmax;
-    const int nblk = a.g.npair * kblk;
-    if (nblk > 0) hipLaunchKernelGGL(pairdata_kernel, dim3(nblk), dim3(128), 0, s, a);
+    const int nblk = a.g.grouped ? a.g.npair : a.nitems;
+    if (nblk > 0) hipLaunchKernelGGL(pairdata_kernel, dim3(nblk), dim3(128), pairdata_lds_bytes(a.g), s, a);
 }
 
 }  // namespace mdx

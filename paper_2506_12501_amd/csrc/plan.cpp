@@ -18,9 +18,22 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 struct PlanBatch {
     ClassPlan cp;
     int64_t out_offset = 0;
-    size_t t_pairs_bra = 0, t_pairs_ket = 0, t_count = 0, t_obase = 0, t_tile_off = 0;   // in the plan's tables
+    size_t t_pairs_bra = 0, t_pairs_ket = 0, t_items_bra = 0, t_items_ket = 0, t_count = 0, t_obase = 0,
+           t_tile_off = 0;   // in the plan's tables
     size_t w_prim_bra = 0, w_prim_ket = 0, w_np_bra = 0, w_np_ket = 0, w_H_bra = 0, w_H_ket = 0;   // in ws
     int nqmax = 1;
+    int rec[2] = {-1, -1};   // fused: side records of the bra and ket pair data
+};
+
+// Fused plans compute the pair data of a side once: a record is the longest
+// pair list of one role and class, and every batch side whose list is a prefix
+// of it reads the record's rows (the screened ket lists are prefixes of the
+// sorted bucket lists).
+struct SideRec {
+    SidePlan sp;
+    int role = 0;
+    size_t t_pairs = 0, t_items = 0;
+    size_t w_prim = 0, w_np = 0, w_H = 0;
 };
 
 // batches of a fused plan that share one kernel instance
@@ -44,6 +57,7 @@ struct mdx_plan {
     bool fused = false;
     std::vector<PlanBatch> b;
     std::vector<QueueGroup> q;
+    std::vector<SideRec> recs;
     int64_t out_size = 0;
     size_t ws_total = 0;
     char *dtab = nullptr;        // device tables (plan-owned)
@@ -79,8 +93,27 @@ namespace {
 ClassDev batch_dev(const mdx_plan *p, const PlanBatch &pb, char *ws)
 {
     ClassDev d{};
+    if (pb.rec[0] >= 0) {
+        const SideRec &rb = p->recs[pb.rec[0]], &rk = p->recs[pb.rec[1]];
+        d.pairs_bra = (const PairRec *)(p->dtab + rb.t_pairs);
+        d.pairs_ket = (const PairRec *)(p->dtab + rk.t_pairs);
+        d.items_bra = (const int2 *)(p->dtab + rb.t_items);
+        d.items_ket = (const int2 *)(p->dtab + rk.t_items);
+        d.count = (const int32_t *)(p->dtab + pb.t_count);
+        d.obase = (const int64_t *)(p->dtab + pb.t_obase);
+        d.tile_off = (const int32_t *)(p->dtab + pb.t_tile_off);
+        d.prim_bra = (PrimRec *)(ws + rb.w_prim);
+        d.prim_ket = (PrimRec *)(ws + rk.w_prim);
+        d.np_bra = (int32_t *)(ws + rb.w_np);
+        d.np_ket = (int32_t *)(ws + rk.w_np);
+        d.H_bra = (double *)(ws + rb.w_H);
+        d.H_ket = (double *)(ws + rk.w_H);
+        return d;
+    }
     d.pairs_bra = (const PairRec *)(p->dtab + pb.t_pairs_bra);
     d.pairs_ket = (const PairRec *)(p->dtab + pb.t_pairs_ket);
+    d.items_bra = (const int2 *)(p->dtab + pb.t_items_bra);
+    d.items_ket = (const int2 *)(p->dtab + pb.t_items_ket);
     d.count = (const int32_t *)(p->dtab + pb.t_count);
     d.obase = (const int64_t *)(p->dtab + pb.t_obase);
     d.tile_off = (const int32_t *)(p->dtab + pb.t_tile_off);
@@ -127,11 +160,21 @@ mdx_status build_graph(mdx_plan *p, const mdx_shells *sh, double *out, char *ws,
         HIP_TRY2(hipEventRecord(p->ev[0], s0));
         for (int k = 1; k < mdx_plan::NS; ++k) HIP_TRY2(hipStreamWaitEvent(p->cs[k], p->ev[0], 0));
         int rr = 0;
-        for (const PlanBatch &pb : p->b) {
-            if (pb.cp.bra.pairs.empty() || pb.cp.ket.pairs.empty() || pb.cp.tile_off.back() == 0) continue;
-            const ClassDev d = batch_dev(p, pb, ws);
-            enqueue_pairdata(c, sh, pb.cp, d, 0, p->cs[rr++ % mdx_plan::NS]);
-            enqueue_pairdata(c, sh, pb.cp, d, 1, p->cs[rr++ % mdx_plan::NS]);
+        for (const SideRec &r : p->recs) {
+            PairDataArgs pa{};
+            pa.g = r.sp.g;
+            pa.pairs = (const PairRec *)(p->dtab + r.t_pairs);
+            pa.items = (const int2 *)(p->dtab + r.t_items);
+            pa.nitems = (int)r.sp.items.size();
+            pa.center = sh->center;
+            pa.expo = sh->exponent;
+            pa.coef = sh->coef;
+            pa.Ca = c->solid + c->solid_off[r.sp.g.la];
+            pa.Cb = r.sp.g.lb >= 0 ? c->solid + c->solid_off[r.sp.g.lb] : nullptr;
+            pa.prim = (PrimRec *)(ws + r.w_prim);
+            pa.H = (double *)(ws + r.w_H);
+            pa.nprim = (int32_t *)(ws + r.w_np);
+            launch_pairdata(pa, p->cs[rr++ % mdx_plan::NS]);
         }
         for (int k = 1; k < mdx_plan::NS; ++k) {
             HIP_TRY2(hipEventRecord(p->ev[k], p->cs[k]));
@@ -225,6 +268,8 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
         const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
         pb.t_pairs_bra = ttake(nb * sizeof(PairRec));
         pb.t_pairs_ket = ttake(nk * sizeof(PairRec));
+        pb.t_items_bra = ttake(cp.bra.items.size() * sizeof(int2));
+        pb.t_items_ket = ttake(cp.ket.items.size() * sizeof(int2));
         pb.t_count = ttake(cp.count.size() * 4);
         pb.t_obase = ttake(cp.obase.size() * 8);
         pb.t_tile_off = ttake(cp.tile_off.size() * 4);
@@ -235,8 +280,60 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
         pb.w_H_bra = wtake(nb * (size_t)cp.bra.g.pair_stride * 8);
         pb.w_H_ket = wtake(nk * (size_t)cp.ket.g.pair_stride * 8);
     }
-    // fused: group the batches by kernel instance
+    // fused: one pair-data record per distinct side (prefix sharing), then
+    // group the batches by kernel instance
     if (p->fused) {
+        struct Ref { int batch, side; size_t len; };
+        std::vector<Ref> refs;
+        for (int i = 0; i < nbatch; ++i) {
+            const ClassPlan &cp = p->b[i].cp;
+            if (cp.bra.pairs.empty() || cp.ket.pairs.empty()) continue;
+            refs.push_back({i, 0, cp.bra.pairs.size()});
+            refs.push_back({i, 1, cp.ket.pairs.size()});
+        }
+        std::stable_sort(refs.begin(), refs.end(), [](const Ref &x, const Ref &y) { return x.len > y.len; });
+        std::multimap<std::tuple<int, int, int, int, int32_t, int32_t>, int> index;
+        for (const Ref &r : refs) {
+            ClassPlan &cp = p->b[r.batch].cp;
+            SidePlan &sp = r.side == 0 ? cp.bra : cp.ket;
+            const auto key = std::make_tuple(r.side, sp.g.la, sp.g.lb, sp.g.cart, sp.pairs[0].sa, sp.pairs[0].sb);
+            int found = -1;
+            for (auto it = index.lower_bound(key); it != index.end() && it->first == key; ++it) {
+                const SideRec &rec = p->recs[it->second];
+                if (rec.sp.g.grouped == sp.g.grouped && rec.sp.pairs.size() >= sp.pairs.size() &&
+                    std::memcmp(rec.sp.pairs.data(), sp.pairs.data(), sp.pairs.size() * sizeof(PairRec)) == 0) {
+                    found = it->second;
+                    break;
+                }
+            }
+            if (found < 0) {
+                found = (int)p->recs.size();
+                SideRec rec;
+                rec.sp = sp;
+                rec.role = r.side;
+                p->recs.push_back(std::move(rec));
+                index.emplace(key, found);
+            }
+            p->b[r.batch].rec[r.side] = found;
+        }
+        // batches address the record's rows: take its geometry (kmax, strides)
+        for (PlanBatch &pb : p->b) {
+            if (pb.rec[0] < 0) continue;
+            const int na = (int)pb.cp.bra.pairs.size(), nk = (int)pb.cp.ket.pairs.size();
+            pb.cp.bra.g = p->recs[pb.rec[0]].sp.g;
+            pb.cp.ket.g = p->recs[pb.rec[1]].sp.g;
+            pb.cp.bra.g.npair = na;
+            pb.cp.ket.g.npair = nk;
+        }
+        ws = 0;
+        for (SideRec &r : p->recs) {
+            const size_t n = r.sp.pairs.size();
+            r.t_pairs = ttake(n * sizeof(PairRec));
+            r.t_items = ttake(r.sp.items.size() * sizeof(int2));
+            r.w_np = wtake(n * 4);
+            r.w_prim = wtake(n * r.sp.g.kmax * sizeof(PrimRec));
+            r.w_H = wtake(n * (size_t)r.sp.g.pair_stride * 8);
+        }
         std::map<std::tuple<int, int, int, int, int, int, int, int>, int> gi;
         for (int i = 0; i < nbatch; ++i) {
             PlanBatch &pb = p->b[i];
@@ -308,12 +405,22 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
         };
         up(pb.t_pairs_bra, cp.bra.pairs.data(), cp.bra.pairs.size() * sizeof(PairRec));
         up(pb.t_pairs_ket, cp.ket.pairs.data(), cp.ket.pairs.size() * sizeof(PairRec));
+        up(pb.t_items_bra, cp.bra.items.data(), cp.bra.items.size() * sizeof(int2));
+        up(pb.t_items_ket, cp.ket.items.data(), cp.ket.items.size() * sizeof(int2));
         up(pb.t_count, cp.count.data(), cp.count.size() * 4);
         up(pb.t_obase, cp.obase.data(), cp.obase.size() * 8);
         up(pb.t_tile_off, cp.tile_off.data(), cp.tile_off.size() * 4);
     }
     for (const QueueGroup &g : p->q)
         if (e == hipSuccess) e = hipMemcpy(p->dtab + g.t_base, g.base.data(), g.base.size() * 4, hipMemcpyHostToDevice);
+    for (const SideRec &r : p->recs) {
+        if (e == hipSuccess && !r.sp.pairs.empty())
+            e = hipMemcpy(p->dtab + r.t_pairs, r.sp.pairs.data(), r.sp.pairs.size() * sizeof(PairRec),
+                          hipMemcpyHostToDevice);
+        if (e == hipSuccess && !r.sp.items.empty())
+            e = hipMemcpy(p->dtab + r.t_items, r.sp.items.data(), r.sp.items.size() * sizeof(int2),
+                          hipMemcpyHostToDevice);
+    }
     if (e == hipSuccess && p->fused) {
         for (auto &s : p->cs)
             if (e == hipSuccess) e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);

@@ -45,6 +45,7 @@ void build_tket(mdx_ctx *c, int lc, int ld, bool cart, std::vector<double> &T);
 struct SidePlan {
     SideGeom g{};
     std::vector<PairRec> pairs;
+    std::vector<int2> items;   // (pair, primitive pair) for the pair-data kernel; empty if grouped
 };
 
 // kernel families
@@ -73,7 +74,7 @@ struct ClassPlan {
 
 // workspace layout of one class
 struct WsLayout {
-    size_t pairs_bra, pairs_ket, np_bra, np_ket, prim_bra, prim_ket, H_bra, H_ket;
+    size_t pairs_bra, pairs_ket, items_bra, items_ket, np_bra, np_ket, prim_bra, prim_ket, H_bra, H_ket;
     size_t count, obase, tile_off;
     size_t total;
 };
@@ -93,6 +94,7 @@ WsLayout ws_layout(const ClassPlan &cp, size_t base);
 // device addresses of one class's tables and pair data
 struct ClassDev {
     const PairRec *pairs_bra, *pairs_ket;
+    const int2 *items_bra, *items_ket;
     const int32_t *count;
     const int64_t *obase;
     const int32_t *tile_off;

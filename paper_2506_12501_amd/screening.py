@@ -39,37 +39,55 @@ def canonical_pairs(l: np.ndarray, lmax: int):
     return res
 
 
-def class_batches(pairs_by_class: dict, Q_by_class: dict, tau: float = 1e-12):
+def class_batches(pairs_by_class: dict, Q_by_class: dict, tau: float = 1e-12, nprim=None):
     """Sorted, screened batches.  Returns a list of dicts with keys
-    name, bra, ket, bra_count, quartets, Qbra, Qket (bra pair class >= ket)."""
+    name, bra, ket, bra_count, quartets, Qbra, Qket (bra pair class >= ket).
+
+    nprim (contraction degree per shell): if given, each pair class is split
+    into buckets of equal pair contraction degree K_a K_b, and there is one
+    batch per (quartet class, bra bucket, ket bucket) -- so that the work items
+    of a batch have equal primitive counts.  Within one pair class the bucket
+    pairs (b, k) with b > k are kept whole, b == k triangular."""
     order = list(pairs_by_class)
-    srt = {}
+    buckets = {}   # pair class -> [(K, sorted pairs, sorted Q)]
     for pc in order:
+        P = pairs_by_class[pc]
         Q = np.asarray(Q_by_class[pc], dtype=np.float64)
-        idx = np.argsort(-Q, kind="stable")
-        srt[pc] = (pairs_by_class[pc][idx], Q[idx])
+        if nprim is None:
+            groups = [(0, np.arange(P.shape[0]))]
+        else:
+            K = np.asarray(nprim)[P[:, 0]] * np.asarray(nprim)[P[:, 1]]
+            groups = [(int(k), np.nonzero(K == k)[0]) for k in sorted(set(K.tolist()), reverse=True)]
+        lst = []
+        for k, sel in groups:
+            idx = sel[np.argsort(-Q[sel], kind="stable")]
+            lst.append((k, P[idx], Q[idx]))
+        buckets[pc] = lst
     out = []
     ch = "spdfghik"
     for ib, pb in enumerate(order):
         for ik in range(ib + 1):
             pk = order[ik]
-            bra, Qb = srt[pb]
-            ket, Qk = srt[pk]
-            if bra.shape[0] == 0 or ket.shape[0] == 0:
-                continue
-            # bra prefix per ket: Q_bra >= tau / Q_ket (Q_bra sorted descending)
-            with np.errstate(divide="ignore"):
-                lim = np.where(Qk > 0, tau / Qk, np.inf)
-            cnt = np.searchsorted(-Qb, -lim, side="right").astype(np.int64)
-            if pb == pk:
-                cnt = np.minimum(cnt, np.arange(1, ket.shape[0] + 1))
-            nz = np.nonzero(cnt)[0]
-            if nz.size == 0:
-                continue
-            nket = int(nz[-1]) + 1      # counts are nonincreasing in the ket position up to the triangle
-            out.append({"name": f"({ch[pb[0]]}{ch[pb[1]]}|{ch[pk[0]]}{ch[pk[1]]})", "bra": bra, "ket": ket[:nket],
-                        "bra_count": cnt[:nket].astype(np.int32), "quartets": int(cnt[:nket].sum()),
-                        "Qbra": Qb, "Qket": Qk[:nket]})
+            for bb, (Kb, bra, Qb) in enumerate(buckets[pb]):
+                for bk, (Kk, ket, Qk) in enumerate(buckets[pk]):
+                    if pb == pk and bk > bb:
+                        continue
+                    if bra.shape[0] == 0 or ket.shape[0] == 0:
+                        continue
+                    # bra prefix per ket: Q_bra >= tau / Q_ket (Q_bra sorted descending)
+                    with np.errstate(divide="ignore"):
+                        lim = np.where(Qk > 0, tau / Qk, np.inf)
+                    cnt = np.searchsorted(-Qb, -lim, side="right").astype(np.int64)
+                    if pb == pk and bb == bk:
+                        cnt = np.minimum(cnt, np.arange(1, ket.shape[0] + 1))
+                    nz = np.nonzero(cnt)[0]
+                    if nz.size == 0:
+                        continue
+                    nket = int(nz[-1]) + 1      # counts are nonincreasing in the ket position (up to the triangle)
+                    name = f"({ch[pb[0]]}{ch[pb[1]]}|{ch[pk[0]]}{ch[pk[1]]})"
+                    out.append({"name": name, "Kbra": Kb, "Kket": Kk, "bra": bra, "ket": ket[:nket],
+                                "bra_count": cnt[:nket].astype(np.int32), "quartets": int(cnt[:nket].sum()),
+                                "Qbra": Qb, "Qket": Qk[:nket]})
     return out
 
 

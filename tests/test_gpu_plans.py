@@ -26,13 +26,13 @@ def test_schwarz_factors():
         assert_close(got, ref, f"Q {pc}")
 
 
-def plan_setup(tau=1e-12, seed=5):
+def plan_setup(tau=1e-12, seed=5, buckets=False):
     from paper_2506_12501_amd import native
     b, _ = W.water_cluster(seed=seed, nx=2, ny=2, nz=2)
     sh = native.DeviceShells(b)
     P = S.canonical_pairs(b.l, 2)
     Q = {pc: native.schwarz(sh, p).cpu().numpy() for pc, p in P.items()}
-    batches = S.class_batches(P, Q, tau)
+    batches = S.class_batches(P, Q, tau, nprim=b.nprim if buckets else None)
     total = S.with_offsets(batches, b.l)
     nb = [native.Batch(4, bt["bra"], bt["ket"], bt["bra_count"], bt["out_offset"]) for bt in batches]
     return b, sh, batches, nb, total
@@ -54,6 +54,24 @@ def test_plain_and_fused_plans_match_oracle():
         ref, scale = oracle_batch(b, bt)
         assert_close_cs(o2[off:off + n], ref, scale, bt["name"])
     print("quartets", sum(bt["quartets"] for bt in batches), "doubles", total)
+
+
+def test_bucketed_plans_share_pair_data():
+    """contraction-degree buckets: many batches whose ket lists are prefixes of
+    shared sorted lists; the fused plan computes each side's pair data once"""
+    from paper_2506_12501_amd import native
+    b, sh, batches, nb, total = plan_setup(buckets=True)
+    assert len(batches) > 50
+    plain = native.Plan(sh, nb, fused=False)
+    fused = native.Plan(sh, nb, fused=True)
+    o1 = plain.execute().cpu().numpy()
+    o2 = fused.execute().cpu().numpy()
+    assert np.array_equal(o1, o2)
+    for bt in batches:
+        off, n = bt["out_offset"], bt["quartets"] * bt["nab"] * bt["ncd"]
+        ref, scale = oracle_batch(b, bt)
+        assert_close_cs(o2[off:off + n], ref, scale, f"{bt['name']} K{bt['Kbra']}x{bt['Kket']}")
+    print("batches", len(batches), "quartets", sum(bt["quartets"] for bt in batches))
 
 
 def test_graph_replays():

@@ -55,3 +55,33 @@ def test_prefixes_equal_brute_force():
                         continue
                 want.add((tuple(pairs[pb][i]), tuple(pairs[pk][j])))
     assert got == want
+
+
+def test_k_buckets_cover_the_same_quartets():
+    """Splitting the pair classes into contraction-degree buckets keeps exactly
+    the same set of screened canonical quartets."""
+    b, _ = W.water_cluster(nx=2, ny=2, nz=2)
+    P = S.canonical_pairs(b.l, 2)
+    rng = np.random.default_rng(4)
+    Q = {pc: 10.0 ** rng.uniform(-8, 1, p.shape[0]) for pc, p in P.items()}
+
+    def kept(batches):
+        out = set()
+        for bt in batches:
+            for k, c in enumerate(bt["bra_count"]):
+                for i in range(c):
+                    a, bb = tuple(bt["bra"][i]), tuple(bt["ket"][k])
+                    out.add((a, bb))
+        return out
+
+    plain = S.class_batches(P, Q, 1e-9)
+    bucketed = S.class_batches(P, Q, 1e-9, nprim=b.nprim)
+    assert len(bucketed) > len(plain)
+    assert sum(x["quartets"] for x in bucketed) == sum(x["quartets"] for x in plain)
+    kp, kb = kept(plain), kept(bucketed)
+    # the same unordered quartets (a same-class pair of pairs may appear as (x|y) or (y|x))
+    norm = lambda s: {tuple(sorted(q)) for q in s}
+    assert norm(kp) == norm(kb) and len(kb) == len(kp)
+    for bt in bucketed:
+        Kb = b.nprim[bt["bra"][:, 0]] * b.nprim[bt["bra"][:, 1]]
+        assert np.all(Kb == bt["Kbra"])

@@ -128,40 +128,71 @@ __device__ __forceinline__ void xsweep(double *__restrict__ cuv /* cube + u*D + 
     }
 }
 
-// z/y sweep for column v = L - M, executed by wave (v % NW); lanes over quartets
-template <int D, int NW, int M>
-__device__ __forceinline__ void ypass(double *cube, const double *S, const double *PQ, int NQ, int w, int lane)
+// Sweep work of one wave as straight-line code.  Wave W owns the z/y columns
+// v with v % NW == W and the x passes of order M with (L - M) % NW == W; lanes
+// take quartets (y) or (quartet, column) pairs (x).  Lanes beyond the live
+// work compute on valid inputs (quartet 0) and write to a dummy cube slot
+// `qdummy`, so the wave's independent recursion chains form one basic block
+// that the scheduler can interleave.  Requires NQ <= 64.
+template <int D, int NW, int W, int M>
+__device__ __forceinline__ void ycol(double *cq, const double *Sq, double Y, double Z)
 {
-    constexpr int L = D - 1, v = L - M, CUBE = D * D * D;
-    if (w == v % NW)
-        for (int q = lane; q < NQ; q += 64) ysweep<D, M>(cube + q * CUBE + v, S + q * D, PQ[q * 4 + 1], PQ[q * 4 + 2]);
+    constexpr int v = D - 1 - M;
+    if constexpr (v % NW == W) ysweep<D, M>(cq + v, Sq, Y, Z);
 }
 
-// x sweep for all columns (u, v) with u + v = L - M, executed by wave
-// (M % NW); lanes over (quartet, column)
-template <int D, int NW, int M>
-__device__ __forceinline__ void xpass(double *cube, const double *PQ, int NQ, int w, int lane)
+template <int D, int NW, int W, int... Ms>
+__device__ __forceinline__ void ywave(double *cube, const double *S, const double *PQ, int NQ, int qdummy, int lane,
+                                      std::integer_sequence<int, Ms...>)
+{
+    constexpr int CUBE = D * D * D;
+    const bool live = lane < NQ;
+    const int qs = live ? lane : 0;
+    double *cq = cube + (live ? lane : qdummy) * CUBE;
+    const double *Sq = S + qs * D;
+    const double Y = PQ[qs * 4 + 1], Z = PQ[qs * 4 + 2];
+    (ycol<D, NW, W, Ms>(cq, Sq, Y, Z), ...);
+}
+
+template <int D, int NW, int W, int NQCT, int M>
+__device__ __forceinline__ void xcols(double *cube, const double *PQ, int NQ, int qdummy, int lane)
 {
     constexpr int L = D - 1, s = L - M, CUBE = D * D * D;
-    if (w == (L - M) % NW)
-        for (int e = lane; e < NQ * (s + 1); e += 64) {
-            const int q = e / (s + 1), v = e - q * (s + 1), u = s - v;
-            xsweep<D, M>(cube + q * CUBE + u * D + v, PQ[q * 4]);
+    if constexpr (M > 0 && s % NW == W) {   // order 0 columns are complete after the y sweep
+        constexpr int R = (NQCT * (s + 1) + 63) / 64;
+        const int n = NQ * (s + 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int e = lane + 64 * r;
+            const bool live = e < n;
+            const int ee = live ? e : 0;
+            const int q = ee / (s + 1), v = ee - q * (s + 1), u = s - v;
+            xsweep<D, M>(cube + (live ? q : qdummy) * CUBE + u * D + v, PQ[q * 4]);
         }
+    }
 }
 
-template <int D, int NW, int... Ms>
-__device__ __forceinline__ void ypasses(double *cube, const double *S, const double *PQ, int NQ, int w, int lane,
-                                        std::integer_sequence<int, Ms...>)
+template <int D, int NW, int W, int NQCT, int... Ms>
+__device__ __forceinline__ void xwave(double *cube, const double *PQ, int NQ, int qdummy, int lane,
+                                      std::integer_sequence<int, Ms...>)
 {
-    (ypass<D, NW, Ms>(cube, S, PQ, NQ, w, lane), ...);
+    (xcols<D, NW, W, NQCT, Ms>(cube, PQ, NQ, qdummy, lane), ...);
 }
 
-template <int D, int NW, int... Ms>
-__device__ __forceinline__ void xpasses(double *cube, const double *PQ, int NQ, int w, int lane,
-                                        std::integer_sequence<int, Ms...>)
+// z/y sweeps of all live quartets (every wave calls this; wave w does its share)
+template <int D, int NW, int... Ws>
+__device__ __forceinline__ void ysweeps(double *cube, const double *S, const double *PQ, int NQ, int qdummy, int w,
+                                        int lane, std::integer_sequence<int, Ws...>)
 {
-    (xpass<D, NW, Ms>(cube, PQ, NQ, w, lane), ...);
+    ((w == Ws ? ywave<D, NW, Ws>(cube, S, PQ, NQ, qdummy, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
+}
+
+// x sweeps (after the z/y sweeps of all waves are visible)
+template <int D, int NW, int NQCT, int... Ws>
+__device__ __forceinline__ void xsweeps(double *cube, const double *PQ, int NQ, int qdummy, int w, int lane,
+                                        std::integer_sequence<int, Ws...>)
+{
+    ((w == Ws ? xwave<D, NW, Ws, NQCT>(cube, PQ, NQ, qdummy, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
 }
 
 }  // namespace mdx

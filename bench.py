@@ -44,6 +44,12 @@ class HipEvents:
             self.ev[i] = h
         self.n = n
 
+    def close(self):
+        for i in range(self.n):
+            if self.ev[i]:
+                self.hip.hipEventDestroy(ctypes.c_void_p(self.ev[i]))
+                self.ev[i] = None
+
     def elapsed_ms(self, i):
         ms = ctypes.c_float()
         assert self.hip.hipEventSynchronize(ctypes.c_void_p(self.ev[2 * i + 1])) == 0
@@ -133,6 +139,7 @@ def measure(fn, nlaunch, reps, native, ctx, torch):
     torch.cuda.synchronize()
     native.check(native.lib().mdx_set_profile_events(ctx.handle, None, 0), "profile hook off")
     ks = [ev.elapsed_ms(i) for i in range(nlaunch * reps)]
+    ev.close()
     return t0.elapsed_time(t1) / reps, [sum(ks[j::nlaunch]) / reps for j in range(nlaunch)]
 
 
@@ -345,7 +352,7 @@ def load_traffic(kernel_tag):
     return d.get("bytes_per_launch")
 
 
-KERNEL_SOURCES = ["eri_mfma.hip", "mfma_common.h", "eri_common.h", "kernels.h", "mdx_internal.h", "boys_device.h",
+KERNEL_SOURCES = ["eri_mfma.hip", "eri_mfma.h", "mfma_common.h", "eri_common.h", "kernels.h", "mdx_internal.h", "boys_device.h",
                   "eri.cpp"]
 
 
@@ -447,6 +454,7 @@ def main():
             "pct_fp64_peak": 100.0 * fl / (kms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
             "shellsets_per_s_kernel": r.n / (kms * 1e-3),
         }
+    ev.close()
     dom = runs[0].batch.name
     pc = per_class[dom]
     traffic = load_traffic("eri_mfma_dddd_k3")

@@ -75,8 +75,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     constexpr int RED = (NW - 1) * NTG * 256;
     extern __shared__ double smem[];
     double *cube = smem;
-    // nqmax live quartet slots plus one dummy slot for idle sweep lanes
-    const int cube_words = (SEPRED || (nqmax + 1) * CUBE > RED) ? (nqmax + 1) * CUBE : RED;
+    const int cube_words = (SEPRED || nqmax * CUBE > RED) ? nqmax * CUBE : RED;
     double *red = SEPRED ? smem + cube_words : cube;
     const int kkmax = a.ket.kmax;
     double *S = smem + cube_words + (SEPRED ? RED : 0);   // [kkmax][nqmax][D]
@@ -193,9 +192,9 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                 if (fresh) {
                     // one-axis sweeps of Eq. (31): z and y per column v, then x per (u, v)
                     const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
-                    ysweeps<D, NW>(cube, Sk, PQk, NQ, nqmax, w, lane, std::make_integer_sequence<int, NW>{});
+                    ysweeps<D, NW>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
                     __syncthreads();
-                    xsweeps<D, NW, NQCT>(cube, PQk, NQ, nqmax, w, lane, std::make_integer_sequence<int, NW>{});
+                    xsweeps<D, NW, NQCT>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
                 }
 #pragma unroll
                 for (int i = 0; i < HKR; ++i) {
@@ -322,7 +321,7 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     constexpr int KT = round_up(ncart(LK), 4) / 4;
     constexpr bool SEPRED = NTCD / NTG > 1;
     constexpr size_t RED = (size_t)(NW - 1) * NTG * 256;
-    const size_t cube_words = SEPRED ? (size_t)(nqmax + 1) * CUBE + RED : std::max((size_t)(nqmax + 1) * CUBE, RED);
+    const size_t cube_words = SEPRED ? (size_t)nqmax * CUBE + RED : std::max((size_t)nqmax * CUBE, RED);
     return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(NTPAD + 4 * KT) * NTG * 16) * 8 +
            (size_t)(NH + NTPAD + 4 * KT) * 4;
 }

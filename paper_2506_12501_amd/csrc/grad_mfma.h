@@ -65,8 +65,8 @@ eri_grad_kernel(GradArgs a)
     const int nw = a.nw, nwq = (nw + 3) & ~3, nwp = a.nwp;
 
     extern __shared__ double smem[];
-    double *cube = smem;                       // [nqmax + 1][CUBE] (last: dummy slot of idle sweep lanes)
-    double *S = cube + (nqmax + 1) * CUBE;     // [kkmax][nqmax][D]
+    double *cube = smem;                       // [nqmax][CUBE]
+    double *S = cube + nqmax * CUBE;           // [kkmax][nqmax][D]
     double *PQ = S + kkmax * nqmax * D;        // [kkmax][nqmax][4]
     double *Wt = PQ + kkmax * nqmax * 4;       // [kkmax]
     double *Hk = Wt + kkmax;                   // [NTPAD][NP]   adjoint-folded ket block
@@ -178,9 +178,9 @@ eri_grad_kernel(GradArgs a)
             }
             {
                 const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
-                ysweeps<D, NW>(cube, Sk, PQk, NQ, nqmax, w, lane, std::make_integer_sequence<int, NW>{});
+                ysweeps<D, NW>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
                 __syncthreads();
-                xsweeps<D, NW, NQCT>(cube, PQk, NQ, nqmax, w, lane, std::make_integer_sequence<int, NW>{});
+                xsweeps<D, NW, NQCT>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
             }
 #pragma unroll
             for (int i = 0; i < HKR; ++i) {
@@ -291,7 +291,7 @@ static size_t grad_lds_bytes(int nqmax, int kkmax, int nwq, int nwp)
     constexpr int NTPAD = round_up(nherm(LW - 1), 4);
     constexpr int KT = round_up(ncart(LW), 4) / 4;
     constexpr int NP = NTN * 16;
-    const size_t dbl = (size_t)(nqmax + 1) * CUBE + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)NTPAD * NP +
+    const size_t dbl = (size_t)nqmax * CUBE + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)NTPAD * NP +
                        (size_t)4 * KT * NP + (size_t)NP * nwq + (size_t)NTPAD * nwp + (size_t)NW * 6;
     return dbl * 8 + (size_t)(NH + NTPAD + 4 * KT) * 4;
 }

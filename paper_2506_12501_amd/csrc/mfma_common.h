@@ -128,12 +128,12 @@ __device__ __forceinline__ void xsweep(double *__restrict__ cuv /* cube + u*D + 
     }
 }
 
-// Sweep work of one wave as straight-line code.  Wave W owns the z/y columns
-// v with v % NW == W and the x passes of order M with (L - M) % NW == W; lanes
-// take quartets (y) or (quartet, column) pairs (x).  Lanes beyond the live
-// work compute on valid inputs (quartet 0) and write to a dummy cube slot
-// `qdummy`, so the wave's independent recursion chains form one basic block
-// that the scheduler can interleave.  Requires NQ <= 64.
+// Sweep work of one wave.  Wave W owns the z/y columns v with v % NW == W and
+// the x passes of order M with (L - M) % NW == W; lanes take quartets (y) or
+// (quartet, column) pairs (x).  All z/y columns of a wave sit in one block
+// under a single lane guard, so the scheduler can interleave their independent
+// recursion chains; idle lanes stay masked (a fully masked 16-lane group costs
+// no FP64 pipe time).  Requires NQ <= 64.
 template <int D, int NW, int W, int M>
 __device__ __forceinline__ void ycol(double *cq, const double *Sq, double Y, double Z)
 {
@@ -142,20 +142,19 @@ __device__ __forceinline__ void ycol(double *cq, const double *Sq, double Y, dou
 }
 
 template <int D, int NW, int W, int... Ms>
-__device__ __forceinline__ void ywave(double *cube, const double *S, const double *PQ, int NQ, int qdummy, int lane,
+__device__ __forceinline__ void ywave(double *cube, const double *S, const double *PQ, int NQ, int lane,
                                       std::integer_sequence<int, Ms...>)
 {
     constexpr int CUBE = D * D * D;
-    const bool live = lane < NQ;
-    const int qs = live ? lane : 0;
-    double *cq = cube + (live ? lane : qdummy) * CUBE;
-    const double *Sq = S + qs * D;
-    const double Y = PQ[qs * 4 + 1], Z = PQ[qs * 4 + 2];
+    if (lane >= NQ) return;
+    double *cq = cube + lane * CUBE;
+    const double *Sq = S + lane * D;
+    const double Y = PQ[lane * 4 + 1], Z = PQ[lane * 4 + 2];
     (ycol<D, NW, W, Ms>(cq, Sq, Y, Z), ...);
 }
 
 template <int D, int NW, int W, int NQCT, int M>
-__device__ __forceinline__ void xcols(double *cube, const double *PQ, int NQ, int qdummy, int lane)
+__device__ __forceinline__ void xcols(double *cube, const double *PQ, int NQ, int lane)
 {
     constexpr int L = D - 1, s = L - M, CUBE = D * D * D;
     if constexpr (M > 0 && s % NW == W) {   // order 0 columns are complete after the y sweep
@@ -164,35 +163,35 @@ __device__ __forceinline__ void xcols(double *cube, const double *PQ, int NQ, in
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int e = lane + 64 * r;
-            const bool live = e < n;
-            const int ee = live ? e : 0;
-            const int q = ee / (s + 1), v = ee - q * (s + 1), u = s - v;
-            xsweep<D, M>(cube + (live ? q : qdummy) * CUBE + u * D + v, PQ[q * 4]);
+            if (e < n) {
+                const int q = e / (s + 1), v = e - q * (s + 1), u = s - v;
+                xsweep<D, M>(cube + q * CUBE + u * D + v, PQ[q * 4]);
+            }
         }
     }
 }
 
 template <int D, int NW, int W, int NQCT, int... Ms>
-__device__ __forceinline__ void xwave(double *cube, const double *PQ, int NQ, int qdummy, int lane,
+__device__ __forceinline__ void xwave(double *cube, const double *PQ, int NQ, int lane,
                                       std::integer_sequence<int, Ms...>)
 {
-    (xcols<D, NW, W, NQCT, Ms>(cube, PQ, NQ, qdummy, lane), ...);
+    (xcols<D, NW, W, NQCT, Ms>(cube, PQ, NQ, lane), ...);
 }
 
 // z/y sweeps of all live quartets (every wave calls this; wave w does its share)
 template <int D, int NW, int... Ws>
-__device__ __forceinline__ void ysweeps(double *cube, const double *S, const double *PQ, int NQ, int qdummy, int w,
+__device__ __forceinline__ void ysweeps(double *cube, const double *S, const double *PQ, int NQ, int w,
                                         int lane, std::integer_sequence<int, Ws...>)
 {
-    ((w == Ws ? ywave<D, NW, Ws>(cube, S, PQ, NQ, qdummy, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
+    ((w == Ws ? ywave<D, NW, Ws>(cube, S, PQ, NQ, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
 }
 
 // x sweeps (after the z/y sweeps of all waves are visible)
 template <int D, int NW, int NQCT, int... Ws>
-__device__ __forceinline__ void xsweeps(double *cube, const double *PQ, int NQ, int qdummy, int w, int lane,
+__device__ __forceinline__ void xsweeps(double *cube, const double *PQ, int NQ, int w, int lane,
                                         std::integer_sequence<int, Ws...>)
 {
-    ((w == Ws ? xwave<D, NW, Ws, NQCT>(cube, PQ, NQ, qdummy, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
+    ((w == Ws ? xwave<D, NW, Ws, NQCT>(cube, PQ, NQ, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
 }
 
 }  // namespace mdx

@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import argparse
 import ctypes
+import gc
 import json
 import os
 import sys
@@ -132,11 +133,13 @@ def measure(fn, nlaunch, reps, native, ctx, torch):
     native.check(native.lib().mdx_set_profile_events(ctx.handle, ev.ev, ev.n), "profile hook")
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    gc.disable()   # a collection pass inside the loop would stall the enqueueing thread
     t0.record()
     for _ in range(reps):
         fn()
     t1.record()
     torch.cuda.synchronize()
+    gc.enable()
     native.check(native.lib().mdx_set_profile_events(ctx.handle, None, 0), "profile hook off")
     ks = [ev.elapsed_ms(i) for i in range(nlaunch * reps)]
     ev.close()
@@ -231,12 +234,14 @@ def cluster_leg(native, ctx, torch, reps, sample):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         ts = []
+        gc.disable()
         for _ in range(reps):
             e0.record()
             plan.execute(out)
             e1.record()
             torch.cuda.synchronize()
             ts.append(e0.elapsed_time(e1))
+        gc.enable()
         return ts
 
     t_plain = timed(plain, o_plain)
@@ -432,12 +437,15 @@ def main():
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
     t0.record()
     wall0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     t1.record()
     torch.cuda.synchronize()
+    gc.enable()
     wall = time.perf_counter() - wall0
     native.check(native.lib().mdx_set_profile_events(ctx.handle, None, 0), "profile hook off")
     ms_step = t0.elapsed_time(t1) / args.steps

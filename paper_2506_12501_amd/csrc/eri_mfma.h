@@ -55,6 +55,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     constexpr int GW = NTG * 16;
     constexpr int NT = 64 * NW;
     constexpr int HKR = (NTPAD * GW + NT - 1) / NT;   // staged ket values per thread
+    constexpr bool YSER = MTW * NTG * 4 + MTW * KT > 48;   // large accumulator set: sweep columns one branch each
     constexpr int NQCT = GB ? 1 : (NW * MTW * 16) / NHB + 2;   // bound on quartets per chunk (host: nqmax)
     static_assert(NTCD % NTG == 0, "cd tiles must split into groups");
     const int tid = threadIdx.x;
@@ -192,9 +193,9 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                 if (fresh) {
                     // one-axis sweeps of Eq. (31): z and y per column v, then x per (u, v)
                     const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
-                    ysweeps<D, NW>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
+                    ysweeps<D, NW, YSER>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
                     __syncthreads();
-                    xsweeps<D, NW, NQCT>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
+                    xsweeps<D, NW, NQCT, YSER>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
                 }
 #pragma unroll
                 for (int i = 0; i < HKR; ++i) {

@@ -46,6 +46,7 @@ eri_grad_kernel(GradArgs a)
     constexpr int NT = 64 * NW;
     constexpr int MK = (NTPAD + 15) / 16;   // 16-row tiles of the adjoint fold
     constexpr int HKR = (NTPAD * GRAD_NWP_MAX + NT - 1) / NT;
+    constexpr bool YSER = MTW * NTN * 4 + MTW * KT > 48;   // large accumulator set: sweep columns one branch each
     constexpr int NQCT = (NW * MTW * 16) / NHD + 2;   // bound on quartets per chunk (host: nqmax)
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
@@ -178,9 +179,9 @@ eri_grad_kernel(GradArgs a)
             }
             {
                 const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
-                ysweeps<D, NW>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
+                ysweeps<D, NW, YSER>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
                 __syncthreads();
-                xsweeps<D, NW, NQCT>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
+                xsweeps<D, NW, NQCT, YSER>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
             }
 #pragma unroll
             for (int i = 0; i < HKR; ++i) {

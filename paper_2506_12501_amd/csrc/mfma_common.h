@@ -178,20 +178,63 @@ __device__ __forceinline__ void xwave(double *cube, const double *PQ, int NQ, in
     (xcols<D, NW, W, NQCT, Ms>(cube, PQ, NQ, lane), ...);
 }
 
-// z/y sweeps of all live quartets (every wave calls this; wave w does its share)
-template <int D, int NW, int... Ws>
+// One z/y column per branch region: the chains of a wave run one after the
+// other, which keeps fewer registers live next to a large accumulator set.
+template <int D, int NW, int M>
+__device__ __forceinline__ void ycol_branch(double *cube, const double *S, const double *PQ, int NQ, int w, int lane)
+{
+    constexpr int v = D - 1 - M, CUBE = D * D * D;
+    if (w == v % NW && lane < NQ)
+        ysweep<D, M>(cube + lane * CUBE + v, S + lane * D, PQ[lane * 4 + 1], PQ[lane * 4 + 2]);
+}
+
+template <int D, int NW, int... Ms>
+__device__ __forceinline__ void ysweeps_serial(double *cube, const double *S, const double *PQ, int NQ, int w,
+                                               int lane, std::integer_sequence<int, Ms...>)
+{
+    (ycol_branch<D, NW, Ms>(cube, S, PQ, NQ, w, lane), ...);
+}
+
+// z/y sweeps of all live quartets (every wave calls this; wave w does its
+// share).  SER selects the column-per-branch form for register-heavy kernels.
+template <int D, int NW, bool SER, int... Ws>
 __device__ __forceinline__ void ysweeps(double *cube, const double *S, const double *PQ, int NQ, int w,
                                         int lane, std::integer_sequence<int, Ws...>)
 {
-    ((w == Ws ? ywave<D, NW, Ws>(cube, S, PQ, NQ, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
+    if constexpr (SER)
+        ysweeps_serial<D, NW>(cube, S, PQ, NQ, w, lane, std::make_integer_sequence<int, D>{});
+    else
+        ((w == Ws ? ywave<D, NW, Ws>(cube, S, PQ, NQ, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
 }
 
-// x sweeps (after the z/y sweeps of all waves are visible)
-template <int D, int NW, int NQCT, int... Ws>
+// x sweep of all columns of order M in a branch region of its own
+template <int D, int NW, int M>
+__device__ __forceinline__ void xorder_branch(double *cube, const double *PQ, int NQ, int w, int lane)
+{
+    constexpr int L = D - 1, s = L - M, CUBE = D * D * D;
+    if (M > 0 && w == s % NW)
+        for (int e = lane; e < NQ * (s + 1); e += 64) {
+            const int q = e / (s + 1), v = e - q * (s + 1), u = s - v;
+            xsweep<D, M>(cube + q * CUBE + u * D + v, PQ[q * 4]);
+        }
+}
+
+template <int D, int NW, int... Ms>
+__device__ __forceinline__ void xsweeps_serial(double *cube, const double *PQ, int NQ, int w, int lane,
+                                               std::integer_sequence<int, Ms...>)
+{
+    (xorder_branch<D, NW, Ms>(cube, PQ, NQ, w, lane), ...);
+}
+
+// x sweeps (after the z/y sweeps of all waves are visible); SER as for ysweeps
+template <int D, int NW, int NQCT, bool SER, int... Ws>
 __device__ __forceinline__ void xsweeps(double *cube, const double *PQ, int NQ, int w, int lane,
                                         std::integer_sequence<int, Ws...>)
 {
-    ((w == Ws ? xwave<D, NW, Ws, NQCT>(cube, PQ, NQ, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
+    if constexpr (SER)
+        xsweeps_serial<D, NW>(cube, PQ, NQ, w, lane, std::make_integer_sequence<int, D>{});
+    else
+        ((w == Ws ? xwave<D, NW, Ws, NQCT>(cube, PQ, NQ, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
 }
 
 }  // namespace mdx

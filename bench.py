@@ -200,7 +200,7 @@ def extra_legs(native, ctx, torch, tune, reps):
     return out
 
 
-def cluster_leg(native, ctx, torch, reps, sample):
+def cluster_leg(native, ctx, torch, reps, sample, tune=True):
     """Mixed-L screened batch over the 32-molecule water-like cluster: every
     canonical class in one plan; plain per-class launches vs one fused graph."""
     import numpy as np
@@ -222,9 +222,17 @@ def cluster_leg(native, ctx, torch, reps, sample):
     nquart = sum(bt["quartets"] for bt in batches)
     log(f"cluster: {len(b.l)} shells, {sum(p.shape[0] for p in P.values())} pairs, {len(batches)} batches, "
         f"{nquart} quartets, {total * 8 / 1e9:.2f} GB output")
+    # tile shapes per class for the fused plan (the plain baseline keeps the defaults)
     nb = [native.Batch(4, bt["bra"], bt["ket"], bt["bra_count"], bt["out_offset"]) for bt in batches]
     plain = native.Plan(sh, nb, fused=False)
+    from paper_2506_12501_amd import autotune
+    tuned = autotune.tune_batches(ctx, sh, batches) if tune else {}
+    log(f"cluster tuning: { {k: v[0] for k, v in tuned.items()} }")
     fused = native.Plan(sh, nb, fused=True)
+    for name, (best, _) in tuned.items():   # back to the defaults for everything after this leg
+        la, lb = (int(x) for x in b.l[next(bt for bt in batches if bt["name"] == name)["bra"][0]])
+        lc, ld = (int(x) for x in b.l[next(bt for bt in batches if bt["name"] == name)["ket"][0]])
+        ctx.set_variant(4, la, lb, lc, ld, 0, -1)
     o_plain = torch.empty(total, dtype=torch.float64, device="cuda")
     o_fused = torch.empty(total, dtype=torch.float64, device="cuda")
 
@@ -246,7 +254,8 @@ def cluster_leg(native, ctx, torch, reps, sample):
 
     t_plain = timed(plain, o_plain)
     t_fused = timed(fused, o_fused)
-    identical = bool(torch.equal(o_plain, o_fused))
+    identical = bool(torch.equal(o_plain, o_fused))        # expected only where tuning kept the default kernels
+    max_diff = float((o_plain - o_fused).abs().max())
     log(f"cluster: plain {min(t_plain):.2f} ms, fused {min(t_fused):.2f} ms")
     # algorithmic FLOPs with each pair's own contraction degree
     Kp = lambda pairs: b.nprim[pairs[:, 0]].astype(np.float64) * b.nprim[pairs[:, 1]]
@@ -295,7 +304,9 @@ def cluster_leg(native, ctx, torch, reps, sample):
         "output_gb": total * 8 / 1e9,
         "schwarz_ms": schwarz_ms,
         "plain_ms": best_p, "fused_ms": best_f, "plain_ms_all": t_plain, "fused_ms_all": t_fused,
-        "fused_speedup": best_p / best_f, "outputs_identical": identical,
+        "fused_speedup": best_p / best_f, "outputs_identical": identical, "max_abs_diff_plain_fused": max_diff,
+        "fused_tuning": {k: {"variant": v[0], "ms": {str(a): t for a, t in v[1].items()}} for k, v in tuned.items()},
+        "plain_uses": "default kernel choice per class",
         "shellsets_per_s_fused": nquart / (best_f * 1e-3),
         "algorithmic_gflop": flops / 1e9, "fused_tflops": flops / (best_f * 1e-3) / 1e12,
         "pct_fp64_peak_fused": 100 * flops / (best_f * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
@@ -477,7 +488,7 @@ def main():
         log("extra legs done")
     cluster = None
     if not args.no_cluster:
-        cluster = cluster_leg(native, ctx, torch, args.extra_reps, args.cluster_sample)
+        cluster = cluster_leg(native, ctx, torch, args.extra_reps, args.cluster_sample, not args.no_tune)
         log("cluster leg done")
 
     cpu, parity = (None, None)

@@ -120,3 +120,45 @@ def apply_cache(ctx, path: str = CACHE) -> int:
                                           int(rec["variant"]))
         n += st == native.MDX_OK
     return n
+
+
+def tune_batches(ctx, shells, batches, cartesian=False, reps=2):
+    """Pick a kernel variant per class for a list of plan batches (dicts with
+    bra, ket, bra_count, out_offset as built by screening.class_batches): for
+    every class with several variants, time a plain plan of that class's
+    batches under each variant and keep the fastest.  Returns
+    {class name: (best, {variant: ms})}; the choices stay set on ctx, so plans
+    created afterwards use them."""
+    import torch
+    by_class = {}
+    for bt in batches:
+        by_class.setdefault(bt["name"], []).append(bt)
+    L = native.lib()
+    out = {}
+    for name, bts in by_class.items():
+        la, lb = (int(x) for x in shells.l[bts[0]["bra"][0]])
+        lc, ld = (int(x) for x in shells.l[bts[0]["ket"][0]])
+        vs = variants(ctx, 4, la, lb, lc, ld, cartesian)
+        if len(vs) < 2:
+            continue
+        times = {}
+        for v in vs:
+            native.check(L.mdx_set_variant(ctx.handle, 4, la, lb, lc, ld, int(cartesian), v), "mdx_set_variant")
+            off = 0
+            nb = []
+            for bt in bts:
+                nb.append(native.Batch(4, bt["bra"], bt["ket"], bt["bra_count"], off))
+                off += bt["quartets"] * bt["nab"] * bt["ncd"]
+            try:
+                plan = native.Plan(shells, nb, cartesian=cartesian, fused=False, ctx=ctx)
+            except native.MdxError:
+                continue
+            o = torch.empty(max(plan.out_size, 1), dtype=torch.float64, device=shells.center.device)
+            times[v] = time_call(lambda: plan.execute(o), reps)
+            del plan, o
+        if not times:
+            continue
+        best = min(times, key=times.get)
+        native.check(L.mdx_set_variant(ctx.handle, 4, la, lb, lc, ld, int(cartesian), best), "mdx_set_variant")
+        out[name] = (best, times)
+    return out

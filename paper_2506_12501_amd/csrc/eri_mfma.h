@@ -73,7 +73,9 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     // With several column groups the [r]^(0) table may stay resident across
     // groups, so the cross-wave reduction gets a region of its own.
     constexpr bool SEPRED = NG > 1;
-    constexpr int RED = (NW - 1) * NTG * 256;
+    // reduction buffer: with one column group every wave's whole partial bra
+    // transform (overlaying the free cube), else waves 1.. one output tile at a time
+    constexpr int RED = SEPRED ? (NW - 1) * NTG * 256 : NW * NTAB * NTG * 256;
     extern __shared__ double smem[];
     double *cube = smem;
     const int cube_words = (SEPRED || nqmax * CUBE > RED) ? nqmax * CUBE : RED;
@@ -278,6 +280,43 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
 
             // sum the waves' partial bra transforms and store this column group
             // (a shellset with several row chunks accumulates through the output)
+            if constexpr (NW == 1) {   // one wave: nothing to reduce
+#pragma unroll
+                for (int mm = 0; mm < NTAB; ++mm)
+#pragma unroll
+                    for (int n = 0; n < NTG; ++n)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int ab = 16 * mm + 4 * r + g;
+                            const int cd = grp * GW + 16 * n + c;
+                            if (ab < a.nab && cd < a.ncd) {
+                                double *dst = a.om.out + obase + (int64_t)I * a.om.sI +
+                                              omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd]);
+                                *dst = ch == 0 ? O[mm][n][r] : *dst + O[mm][n][r];
+                            }
+                        }
+            } else if constexpr (!SEPRED) {
+                __syncthreads();   // every wave is past its last read of the cube
+#pragma unroll
+                for (int mm = 0; mm < NTAB; ++mm)
+#pragma unroll
+                    for (int n = 0; n < NTG; ++n)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) red[(((w * NTAB + mm) * NTG + n) * 4 + r) * 64 + lane] = O[mm][n][r];
+                __syncthreads();
+                // wave w sums and stores the slots s = w, w + NW, ...
+                for (int sl = w; sl < NTAB * NTG * 4; sl += NW) {
+                    const int mm = sl / (NTG * 4), n = (sl >> 2) % NTG, r = sl & 3;
+                    double v = 0.0;
+                    for (int ww = 0; ww < NW; ++ww) v += red[(((ww * NTAB + mm) * NTG + n) * 4 + r) * 64 + lane];
+                    const int ab = 16 * mm + 4 * r + g;
+                    const int cd = grp * GW + 16 * n + c;
+                    if (ab < a.nab && cd < a.ncd) {
+                        double *dst = a.om.out + obase + (int64_t)I * a.om.sI + omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd]);
+                        *dst = ch == 0 ? v : *dst + v;
+                    }
+                }
+            } else
 #pragma unroll
             for (int mm = 0; mm < NTAB; ++mm) {
                 __syncthreads();
@@ -321,7 +360,7 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     constexpr int NTPAD = round_up(nherm(LK - 1), 4);
     constexpr int KT = round_up(ncart(LK), 4) / 4;
     constexpr bool SEPRED = NTCD / NTG > 1;
-    constexpr size_t RED = (size_t)(NW - 1) * NTG * 256;
+    constexpr size_t RED = SEPRED ? (size_t)(NW - 1) * NTG * 256 : (size_t)NW * NTAB * NTG * 256;
     const size_t cube_words = SEPRED ? (size_t)nqmax * CUBE + RED : std::max((size_t)nqmax * CUBE, RED);
     return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(NTPAD + 4 * KT) * NTG * 16) * 8 +
            (size_t)(NH + NTPAD + 4 * KT) * 4;

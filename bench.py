@@ -159,9 +159,9 @@ def extra_legs(native, ctx, torch, tune, reps):
 
     # backward kernel: (dd|dd) K=3, 256 x 256 pairs, adjoint N(0,1) seed 1
     g = GradRun(native, W.config2("(dd|dd)"), ctx, torch, seed=1)
-    variant = None
+    variant, vt = None, None
     if tune:
-        variant, _ = autotune.tune(ctx, g.sh, 4, g.bra, g.ket, g, reps=2, cache=False, gradient=True)
+        variant, vt = autotune.tune(ctx, g.sh, 4, g.bra, g.ket, g, reps=2, cache=False, gradient=True)
     ms, kms = measure(g, 2, reps, native, ctx, torch)
     fl = kfl(g.batch, grad=True) * g.n
     log("gradient leg done")
@@ -171,21 +171,22 @@ def extra_legs(native, ctx, torch, tune, reps):
         "ms_per_call": ms, "shellsets_per_s": g.n / (ms * 1e-3), "kernel_ms_per_pass": kms,
         "algorithmic_gflop": fl / 1e9, "kernel_tflops": fl / (sum(kms) * 1e-3) / 1e12,
         "pct_fp64_peak": 100 * fl / (sum(kms) * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": variant,
-        "flop_model": "flops.grad_shellset_flops"}
+        "tuning_ms": vt, "flop_model": "flops.grad_shellset_flops"}
     del g
 
     # high-L primitive classes: (ff|ff), (gg|gg) 128 x 128; (X|dd) 256 x 256
     hl = {}
     for name in W.C4_CLASSES_4C + W.C4_CLASSES_3C:
         r = ClassRun(native, W.config4(name, seed=0), ctx, torch)
-        v = None
+        v, vt = None, None
         if tune:
-            v, _ = autotune.tune(ctx, r.sh, r.batch.ncentre, r.bra, r.ket, r, reps=2, cache=False)
+            v, vt = autotune.tune(ctx, r.sh, r.batch.ncentre, r.bra, r.ket, r, reps=2, cache=False)
         ms, kms = measure(r, 1, reps, native, ctx, torch)
         fl = kfl(r.batch) * r.n
         hl[name] = {"shellsets": r.n, "ms_per_call": ms, "kernel_ms": kms[0],
                     "shellsets_per_s": r.n / (ms * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
-                    "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": v}
+                    "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": v,
+                    "tuning_ms": vt}
         del r
     out["high_l"] = hl
 

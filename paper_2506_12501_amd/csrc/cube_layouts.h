@@ -1,0 +1,33 @@
+// cube_layouts.h -- written by gen_cube_layouts.py; do not edit.
+// Compact [r]^(0) table layouts: entry (t, u, v), t + u + v <= D - 1, at
+// t*ST + u*SU + v; tables of successive quartets SIZE doubles apart; valid
+// (every entry of up to 32 tables at its own address) for D = 1..18.
+#pragma once
+
+namespace mdx {
+
+constexpr int CUBE_COMPACT_QMAX = 32;
+constexpr int CUBE_COMPACT_DMAX = 18;
+// {D, SU, ST, SIZE}
+constexpr int CUBE_COMPACT[18][4] = {
+    {1, 1, 1, 1},
+    {2, 2, 3, 4},
+    {3, 4, 6, 13},
+    {4, 5, 12, 32},
+    {5, 9, 29, 62},
+    {6, 11, 28, 114},
+    {7, 11, 72, 159},
+    {8, 10, 72, 262},
+    {9, 20, 112, 363},
+    {10, 10, 93, 512},
+    {11, 11, 120, 659},
+    {12, 26, 171, 889},
+    {13, 13, 164, 1063},
+    {14, 18, 203, 1356},
+    {15, 30, 218, 1758},
+    {16, 20, 265, 2028},
+    {17, 18, 299, 2537},
+    {18, 19, 340, 2898},
+};
+
+}  // namespace mdx

@@ -22,7 +22,7 @@ __device__ __forceinline__ int queue_batch(const QueueArgs &q, int w)
     return lo;
 }
 
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE>
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE, int LAY, int KP>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 eri_mfma_queue(QueueArgs q)
 {
@@ -38,7 +38,7 @@ eri_mfma_queue(QueueArgs q)
         int J, I;
         ragged_tile(a.tile_off, a.nket, w - q.base[b], J, I);
         const int nI = a.om.count[J];
-        if (I < nI) eri_mfma_shellset<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB>(a, I, J, nI);
+        if (I < nI) eri_mfma_shellset<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB, LAY, KP>(a, I, J, nI);
     }
 }
 
@@ -85,11 +85,11 @@ static bool mkey_is(const EriKey &k, int lb, int lk, int nab, int ncd, bool gb)
 bool eri_mfma_config(const EriKey &k, int variant, int bra_kmax, int ket_kmax, int &nqmax, size_t &lds, int &nthreads)
 {
     int n = 0;
-#define MDX_CFG(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe)                                  \
+#define MDX_CFG(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp)                                  \
     if (mkey_is(k, lb, lk, nab, ncd, gb) && ++n == variant) {                                      \
         constexpr int NHB = gb ? ncart(lb) : nherm(lb);                                             \
         nqmax = gb ? 1 : std::min(bra_kmax, (nw * mtw * 16) / NHB + 2);                            \
-        lds = mfma_lds_bytes<lb, lk, ntab, ntcd, ntg, mtw, nw, gb>(nqmax, ket_kmax);                \
+        lds = mfma_lds_bytes<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, lay, kp>(nqmax, ket_kmax);                \
         nthreads = 64 * nw;                                                                         \
         return true;                                                                                \
     }
@@ -102,9 +102,9 @@ int eri_queue_prepare(const EriKey &k, bool mfma, int variant, size_t lds)
 {
     int n = 0;
     if (mfma) {
-#define MDX_QP(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe)                            \
+#define MDX_QP(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp)                            \
     if (mkey_is(k, lb, lk, nab, ncd, gb) && ++n == variant) {                                \
-        auto kern = eri_mfma_queue<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe>;               \
+        auto kern = eri_mfma_queue<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe, lay, kp>;               \
         return prepare(kern, lds) ? resident_blocks(kern, 64 * nw, lds) : 0;                 \
     }
         MDX_MFMA_INSTANCES(MDX_QP)
@@ -126,9 +126,9 @@ bool eri_queue_launch(const EriKey &k, bool mfma, int variant, const QueueArgs &
 {
     int n = 0;
     if (mfma) {
-#define MDX_QL(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe)                                        \
+#define MDX_QL(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp)                                        \
     if (mkey_is(k, lb, lk, nab, ncd, gb) && ++n == variant) {                                            \
-        hipLaunchKernelGGL((eri_mfma_queue<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe>), dim3(nblocks),    \
+        hipLaunchKernelGGL((eri_mfma_queue<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe, lay, kp>), dim3(nblocks),    \
                            dim3(64 * nw), lds, s, q);                                                    \
         return true;                                                                                     \
     }

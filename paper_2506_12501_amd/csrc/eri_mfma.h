@@ -22,9 +22,9 @@
 //
 // [r]^(0) follows the recursion of Eq. (31) in three one-axis sweeps (z, then
 // y per column v, then x per column (u, v)), each of compile-time length and
-// unrolled in registers.  The table is a dense (L+1)^3 cube indexed (t,u,v),
-// so [p+q] sits at offset(p) + offset(q): per-lane row offsets plus
-// compile-time ket offsets.
+// unrolled in registers.  The table is an (L+1)^3 cube indexed (t,u,v) with
+// bank-padded strides, so [p+q] sits at offset(p) + offset(q): per-lane row
+// offsets plus compile-time ket offsets.
 #pragma once
 
 #include <algorithm>
@@ -35,11 +35,12 @@ namespace mdx {
 
 // One shellset (bra pair I, ket pair J) per workgroup; every thread of the
 // workgroup calls this with the same (I, J); nI = bra pairs of ket J.
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB>
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int LAY, int KP>
 __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I, const int J, const int nI)
 {
     constexpr int L = LB + LK;
-    constexpr int D = L + 1, CUBE = D * D * D;
+    typedef Cube<L + 1, LAY> CB;
+    constexpr int D = L + 1, CUBE = CB::SIZE;
     constexpr int NH = nherm(L);
     constexpr int NUV = (L + 1) * (L + 2) / 2;
     constexpr int NHB = GB ? ncart(LB) : nherm(LB);
@@ -58,6 +59,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     constexpr bool YSER = MTW * NTG * 4 + MTW * KT > 48;   // large accumulator set: sweep columns one branch each
     constexpr int NQCT = GB ? 1 : (NW * MTW * 16) / NHB + 2;   // bound on quartets per chunk (host: nqmax)
     static_assert(NTCD % NTG == 0, "cd tiles must split into groups");
+    static_assert(KP >= 1 && KP * NQCT <= 64 && KP * NQCT <= CB::QMAX, "tables of one sweep round");
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
 
@@ -77,15 +79,16 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     // transform (overlaying the free cube), else waves 1.. one output tile at a time
     constexpr int RED = SEPRED ? (NW - 1) * NTG * 256 : NW * NTAB * NTG * 256;
     extern __shared__ double smem[];
-    double *cube = smem;
-    const int cube_words = (SEPRED || nqmax * CUBE > RED) ? nqmax * CUBE : RED;
+    double *cube = smem;   // KP blocks of nqmax tables: ket primitive kk0 + j, bra primitive q at slot j*nqmax + q
+    const int tabs = CB::words(KP * nqmax);
+    const int cube_words = (SEPRED || tabs > RED) ? tabs : RED;
     double *red = SEPRED ? smem + cube_words : cube;
     const int kkmax = a.ket.kmax;
     double *S = smem + cube_words + (SEPRED ? RED : 0);   // [kkmax][nqmax][D]
     double *PQ = S + kkmax * nqmax * D;                  // [kkmax][nqmax][4]
     double *Wt = PQ + kkmax * nqmax * 4;                 // [kkmax] terminal weights
-    double *Hk = Wt + kkmax;                             // [NTPAD][GW]
-    double *Tk = Hk + NTPAD * GW;                        // [4*KT][GW]
+    double *Hk = Wt + kkmax;                             // [KP][NTPAD][GW]
+    double *Tk = Hk + KP * NTPAD * GW;                   // [4*KT][GW]
     int *tuvt = (int *)(Tk + 4 * KT * GW);               // [NH] packed t | u<<8 | v<<16
     int *kq = tuvt + NH;                                 // [NTPAD] cube offsets, non-terminal ket
     int *kt = kq + NTPAD;                                // [4*KT] cube offsets, terminal ket
@@ -94,8 +97,8 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
         const Tuv r = herm_tuv(k);
         tuvt[k] = r.t | (r.u << 8) | (r.v << 16);
     }
-    for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? cube_off<D>(k) : 0;
-    for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? cube_off<D>(NKN + k) : 0;
+    for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? CB::off(k) : 0;
+    for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? CB::off(NKN + k) : 0;
 
     const PrimRec *bp = a.bra.prim + (int64_t)I * a.bra.kmax;
     const PrimRec *kp = a.ket.prim + (int64_t)J * a.ket.kmax;
@@ -126,7 +129,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                     const int kb = GB ? 0 : row / NHB;
                     const int h = GB ? row : row - kb * NHB;
                     const int pk = tuvt[HB0 + h];
-                    off = (kb - kb_lo) * CUBE + ((pk & 255) * D + ((pk >> 8) & 255)) * D + (pk >> 16);
+                    off = (kb - kb_lo) * CUBE + CB::off(pk & 255, (pk >> 8) & 255, pk >> 16);
                 }
                 abase[tt] = off;
             }
@@ -180,53 +183,68 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                 }
             }
 
-            for (int kk = 0; kk < nkk; ++kk) {
-                __syncthreads();   // previous k-loop reads of the table / Hk are complete
-                // ket block of this primitive: global loads now, LDS store after the recursion
-                double hv[HKR];
-                {
-                    const double *src = HkG + (int64_t)kk * RPB * NCDP + grp * GW;
+            // rounds of KP ket primitives: one set of sweeps fills the tables of
+            // all of them (more busy lanes per instruction, fewer barriers)
+            for (int kk0 = 0; kk0 < nkk; kk0 += KP) {
+                const int nk = min(KP, nkk - kk0);
+                __syncthreads();   // previous round's reads of the tables / Hk are complete
+                // ket blocks of this round: global loads now, LDS stores after the recursion
+                double hv[KP][HKR];
+#pragma unroll
+                for (int j = 0; j < KP; ++j) {
 #pragma unroll
                     for (int i = 0; i < HKR; ++i) {
                         const int e = tid + i * NT;
-                        hv[i] = e < NTPAD * GW ? src[(e / GW) * NCDP + (e % GW)] : 0.0;
+                        hv[j][i] = (j < nk && e < NTPAD * GW)
+                                       ? HkG[(int64_t)(kk0 + j) * RPB * NCDP + grp * GW + (e / GW) * NCDP + (e % GW)]
+                                       : 0.0;
                     }
                 }
                 if (fresh) {
                     // one-axis sweeps of Eq. (31): z and y per column v, then x per (u, v)
-                    const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
-                    ysweeps<D, NW, YSER>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
+                    const double *Sk = S + kk0 * nqmax * D, *PQk = PQ + kk0 * nqmax * 4;
+                    ysweeps<CB, NW, YSER>(cube, Sk, PQk, NQ, nk * nqmax, nqmax, w, lane,
+                                          std::make_integer_sequence<int, NW>{});
                     __syncthreads();
-                    xsweeps<D, NW, NQCT, YSER>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
+                    xsweeps<CB, NW, KP * NQCT, YSER>(cube, PQk, NQ, nk * nqmax, nqmax, w, lane,
+                                                     std::make_integer_sequence<int, NW>{});
                 }
 #pragma unroll
-                for (int i = 0; i < HKR; ++i) {
-                    const int e = tid + i * NT;
-                    if (e < NTPAD * GW) Hk[e] = hv[i];
-                }
+                for (int j = 0; j < KP; ++j)
+#pragma unroll
+                    for (int i = 0; i < HKR; ++i) {
+                        const int e = tid + i * NT;
+                        if (j < nk && e < NTPAD * GW) Hk[j * NTPAD * GW + e] = hv[j][i];
+                    }
                 __syncthreads();
 
-                // ket transform on MFMA over the non-terminal Hermites
+#pragma unroll
+                for (int j = 0; j < KP; ++j) {
+                    if (j >= nk) break;   // uniform
+                    const double *cj = cube + j * nqmax * CUBE;
+                    const double *Hj = Hk + j * NTPAD * GW;
+                    // ket transform on MFMA over the non-terminal Hermites
 #pragma unroll 2
-                for (int s = 0; s < KS; ++s) {
-                    const int qo = kq[4 * s + g];
-                    double bv[NTG];
+                    for (int s = 0; s < KS; ++s) {
+                        const int qo = kq[4 * s + g];
+                        double bv[NTG];
 #pragma unroll
-                    for (int n = 0; n < NTG; ++n) bv[n] = Hk[(4 * s + g) * GW + 16 * n + c];
+                        for (int n = 0; n < NTG; ++n) bv[n] = Hj[(4 * s + g) * GW + 16 * n + c];
 #pragma unroll
-                    for (int tt = 0; tt < MTW; ++tt) {
-                        const double av = cube[abase[tt] + qo];
+                        for (int tt = 0; tt < MTW; ++tt) {
+                            const double av = cj[abase[tt] + qo];
 #pragma unroll
-                        for (int n = 0; n < NTG; ++n) acc[tt][n] = mfma(av, bv[n], acc[tt][n]);
+                            for (int n = 0; n < NTG; ++n) acc[tt][n] = mfma(av, bv[n], acc[tt][n]);
+                        }
                     }
-                }
-                // terminal Hermites: early contraction over ket primitives
-                const double wt = Wt[kk];
+                    // terminal Hermites: early contraction over ket primitives
+                    const double wt = Wt[kk0 + j];
 #pragma unroll
-                for (int s = 0; s < KT; ++s) {
-                    const int to = kt[4 * s + g];
+                    for (int s = 0; s < KT; ++s) {
+                        const int to = kt[4 * s + g];
 #pragma unroll
-                    for (int tt = 0; tt < MTW; ++tt) Y[tt][s] = fma(wt, cube[abase[tt] + to], Y[tt][s]);
+                        for (int tt = 0; tt < MTW; ++tt) Y[tt][s] = fma(wt, cj[abase[tt] + to], Y[tt][s]);
+                    }
                 }
             }
 
@@ -353,52 +371,65 @@ struct MfmaShape {
     int NTAB, NTCD, NTG, MTW, NW;
 };
 
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB>
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int LAY, int KP>
 __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
 {
-    constexpr int L = LB + LK, D = L + 1, CUBE = D * D * D, NH = nherm(L);
+    constexpr int L = LB + LK, D = L + 1, NH = nherm(L);
     constexpr int NTPAD = round_up(nherm(LK - 1), 4);
     constexpr int KT = round_up(ncart(LK), 4) / 4;
     constexpr bool SEPRED = NTCD / NTG > 1;
     constexpr size_t RED = SEPRED ? (size_t)(NW - 1) * NTG * 256 : (size_t)NW * NTAB * NTG * 256;
-    const size_t cube_words = SEPRED ? (size_t)nqmax * CUBE + RED : std::max((size_t)nqmax * CUBE, RED);
-    return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(NTPAD + 4 * KT) * NTG * 16) * 8 +
+    const size_t tabs = (size_t)Cube<D, LAY>::words(KP * nqmax);
+    const size_t cube_words = SEPRED ? tabs + RED : std::max(tabs, RED);
+    return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(KP * NTPAD + 4 * KT) * NTG * 16) * 8 +
            (size_t)(NH + NTPAD + 4 * KT) * 4;
 }
 
-// Instances: class key (LB, LK, NAB, NCD, GB) and tile shape
-// (NTAB, NTCD, NTG, MTW, NW, WPE).  Several shapes per key are variants 1, 2, ...
-// in listing order; the autotuner picks one per class.
-#define MDX_MFMA_INSTANCES(X)                                                         \
-    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 2)   /* (dd|dd)                    */       \
-    X(4, 4, 25, 25, false, 2, 2, 2, 3, 4, 2)                                          \
-    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 1)                                          \
-    X(4, 4, 25, 25, false, 2, 2, 1, 5, 4, 2)                                          \
-    X(4, 4, 25, 25, false, 2, 2, 2, 3, 2, 3)                                          \
-    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2)   /* (dd|dp), (pd|dd) swapped   */       \
-    X(4, 3, 25, 15, false, 2, 1, 1, 3, 4, 2)                                          \
-    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 1)                                          \
-    X(4, 3, 25, 15, false, 2, 1, 1, 3, 2, 3)                                          \
-    X(4, 2, 25, 9, false, 2, 1, 1, 5, 4, 2)    /* (dd|pp)                    */       \
-    X(4, 2, 25, 5, false, 2, 1, 1, 5, 4, 2)    /* (dd|ds)                    */       \
-    X(3, 3, 15, 15, false, 1, 1, 1, 5, 4, 2)   /* (dp|dp)                    */       \
-    X(3, 2, 15, 9, false, 1, 1, 1, 5, 4, 2)    /* (dp|pp)                    */       \
-    X(3, 2, 15, 5, false, 1, 1, 1, 5, 4, 2)    /* (dp|ds)                    */       \
-    X(2, 2, 9, 9, false, 1, 1, 1, 5, 4, 2)     /* (pp|pp)                    */       \
-    X(4, 4, 36, 36, false, 3, 3, 3, 5, 4, 2)   /* (dd|dd) Cartesian          */       \
-    X(4, 3, 36, 18, false, 3, 2, 2, 5, 4, 2)   /* (dd|dp) Cartesian          */       \
-    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 2)   /* (ff|ff)                    */       \
-    X(6, 6, 49, 49, false, 4, 4, 1, 2, 3, 2)                                          \
-    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 1)                                          \
-    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 2)   /* (gg|gg)                    */       \
-    X(8, 8, 81, 81, false, 6, 6, 1, 3, 4, 2)                                          \
-    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 1)                                          \
-    X(2, 4, 5, 25, true, 1, 2, 2, 1, 1, 2)     /* (d|dd)                     */       \
-    X(3, 4, 7, 25, true, 1, 2, 2, 1, 1, 2)     /* (f|dd)                     */       \
-    X(4, 4, 9, 25, true, 1, 2, 2, 1, 1, 2)     /* (g|dd)                     */       \
-    X(5, 4, 11, 25, true, 1, 2, 2, 2, 1, 2)    /* (h|dd)                     */       \
-    X(6, 4, 13, 25, true, 1, 2, 2, 2, 1, 2)    /* (i|dd)                     */       \
-    X(0, 4, 1, 25, true, 1, 2, 2, 1, 1, 2)     /* (s|dd)                     */       \
-    X(1, 4, 3, 25, true, 1, 2, 2, 1, 1, 2)     /* (p|dd)                     */
+// Instances: class key (LB, LK, NAB, NCD, GB), tile shape
+// (NTAB, NTCD, NTG, MTW, NW, WPE), table layout LAY (see Cube; C = compact)
+// and ket primitives per sweep round KP.  Several instances per key are
+// variants 1, 2, ... in listing order; the autotuner picks one per class.
+#define MDX_MFMA_INSTANCES(X)                                                                      \
+    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 2, CUBE_LAY_COMPACT, 2)/* (dd|dd)                   */   \
+    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 2, 141, 1)                                               \
+    X(4, 4, 25, 25, false, 2, 2, 2, 3, 4, 2, 141, 1)                                               \
+    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 1, 141, 1)                                               \
+    X(4, 4, 25, 25, false, 2, 2, 1, 5, 4, 2, 141, 1)                                               \
+    X(4, 4, 25, 25, false, 2, 2, 2, 3, 2, 3, 141, 1)                                               \
+    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 2)/* (dd|dp), (pd|dd) swapped  */   \
+    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2, 141, 1)                                               \
+    X(4, 3, 25, 15, false, 2, 1, 1, 3, 4, 2, 141, 1)                                               \
+    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 1, 141, 1)                                               \
+    X(4, 3, 25, 15, false, 2, 1, 1, 3, 2, 3, 141, 1)                                               \
+    X(4, 2, 25, 9, false, 2, 1, 1, 5, 4, 2, 141, 1)             /* (dd|pp)                   */    \
+    X(4, 2, 25, 9, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 2)                                   \
+    X(4, 2, 25, 5, false, 2, 1, 1, 5, 4, 2, 141, 1)             /* (dd|ds)                   */    \
+    X(4, 2, 25, 5, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 2)                                   \
+    X(3, 3, 15, 15, false, 1, 1, 1, 5, 4, 2, 141, 1)            /* (dp|dp)                   */    \
+    X(3, 3, 15, 15, false, 1, 1, 1, 3, 4, 2, CUBE_LAY_COMPACT, 2)                                  \
+    X(3, 2, 15, 9, false, 1, 1, 1, 5, 4, 2, 141, 1)             /* (dp|pp)                   */    \
+    X(3, 2, 15, 9, false, 1, 1, 1, 3, 4, 2, CUBE_LAY_COMPACT, 2)                                   \
+    X(3, 2, 15, 5, false, 1, 1, 1, 5, 4, 2, 141, 1)             /* (dp|ds)                   */    \
+    X(3, 2, 15, 5, false, 1, 1, 1, 3, 4, 2, CUBE_LAY_COMPACT, 2)                                   \
+    X(2, 2, 9, 9, false, 1, 1, 1, 5, 4, 2, 141, 1)              /* (pp|pp)                   */    \
+    X(2, 2, 9, 9, false, 1, 1, 1, 2, 4, 2, CUBE_LAY_COMPACT, 2)                                    \
+    X(4, 4, 36, 36, false, 3, 3, 3, 5, 4, 2, CUBE_LAY_COMPACT, 2)/* (dd|dd) Cartesian         */   \
+    X(4, 4, 36, 36, false, 3, 3, 3, 5, 4, 2, 141, 1)                                               \
+    X(4, 3, 36, 18, false, 3, 2, 2, 5, 4, 2, CUBE_LAY_COMPACT, 2)/* (dd|dp) Cartesian         */   \
+    X(4, 3, 36, 18, false, 3, 2, 2, 5, 4, 2, 141, 1)                                               \
+    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 2, 10, 1)             /* (ff|ff)                   */    \
+    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 2, 141, 1)                                               \
+    X(6, 6, 49, 49, false, 4, 4, 1, 2, 3, 2, 141, 1)                                               \
+    X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 1, 141, 1)                                               \
+    X(8, 8, 81, 81, false, 6, 6, 1, 3, 4, 2, 141, 1)            /* (gg|gg)                   */    \
+    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 2, 141, 1)                                               \
+    X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 1, 141, 1)                                               \
+    X(2, 4, 5, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (d|dd)                    */    \
+    X(3, 4, 7, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (f|dd)                    */    \
+    X(4, 4, 9, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (g|dd)                    */    \
+    X(5, 4, 11, 25, true, 1, 2, 2, 2, 1, 2, 0, 1)               /* (h|dd)                    */    \
+    X(6, 4, 13, 25, true, 1, 2, 2, 2, 1, 2, 0, 1)               /* (i|dd)                    */    \
+    X(0, 4, 1, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (s|dd)                    */    \
+    X(1, 4, 3, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (p|dd)                    */
 
 }  // namespace mdx

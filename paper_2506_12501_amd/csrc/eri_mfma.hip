@@ -4,7 +4,7 @@
 
 namespace mdx {
 
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE>
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE, int LAY, int KP>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 eri_mfma_kernel(EriArgs a)
 {
@@ -27,18 +27,18 @@ eri_mfma_kernel(EriArgs a)
     if (J >= a.nket) return;   // whole workgroup
     const int nI = a.diag ? J + 1 : (a.om.count ? a.om.count[J] : a.nbra);
     if (I >= nI) return;       // whole workgroup
-    eri_mfma_shellset<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB>(a, I, J, nI);
+    eri_mfma_shellset<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB, LAY, KP>(a, I, J, nI);
 }
 
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE>
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE, int LAY, int KP>
 static bool launch_mfma(const EriArgs &a0, int nblocks, hipStream_t s)
 {
     EriArgs a = a0;
     constexpr int NHB = GB ? ncart(LB) : nherm(LB);
     a.nqmax = GB ? 1 : std::min(a.bra.kmax, (NW * MTW * 16) / NHB + 2);
-    const size_t lds = mfma_lds_bytes<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB>(a.nqmax, a.ket.kmax);
+    const size_t lds = mfma_lds_bytes<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB, LAY, KP>(a.nqmax, a.ket.kmax);
     if (lds > 160 * 1024) return false;
-    auto kern = eri_mfma_kernel<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB, WPE>;
+    auto kern = eri_mfma_kernel<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB, WPE, LAY, KP>;
     static size_t lds_set = 0;   // largest dynamic LDS granted to this instance so far
     if (lds > 64 * 1024 && lds > lds_set) {
         if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -57,7 +57,7 @@ static bool key_is(const EriKey &k, int lb, int lk, int nab, int ncd, bool gb)
 int eri_mfma_variants(const EriKey &k)
 {
     int n = 0;
-#define MDX_COUNT(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe) \
+#define MDX_COUNT(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp) \
     if (key_is(k, lb, lk, nab, ncd, gb)) ++n;
     MDX_MFMA_INSTANCES(MDX_COUNT)
 #undef MDX_COUNT
@@ -69,9 +69,9 @@ bool eri_mfma_has(const EriKey &k) { return eri_mfma_variants(k) > 0; }
 bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s)
 {
     int n = 0;
-#define MDX_TRY(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe)                     \
+#define MDX_TRY(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp)                     \
     if (key_is(k, lb, lk, nab, ncd, gb) && ++n == variant)                             \
-        return launch_mfma<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe>(a, nblocks, s);
+        return launch_mfma<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe, lay, kp>(a, nblocks, s);
     MDX_MFMA_INSTANCES(MDX_TRY)
 #undef MDX_TRY
     return false;

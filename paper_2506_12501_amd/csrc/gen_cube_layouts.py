@@ -1,0 +1,120 @@
+"""Writes cube_layouts.h: compact LDS layouts for the [r]^(0) tables of the
+matrix-core kernels.
+
+A table holds [t u v]^(0) for t + u + v <= L at offset a*t + b*u + v, and the
+tables of successive primitive quartets start C doubles apart.  For each L the
+script searches (a, b, C) such that every entry of up to QMAX tables has its
+own address (the map is injective on the simplex and the shifted copies are
+disjoint), so tables may interleave with each other's unused corners.  Among
+the layouts whose block of QREF tables, (QREF-1)*C + span, is within 8% of the
+smallest it keeps the one with the fewest modelled LDS bank conflicts for the
+MFMA operand gather (64 banks of 4 bytes, 32 lanes per pass, doubles as two
+consecutive dwords).
+
+Run:  python gen_cube_layouts.py   (rewrites cube_layouts.h beside it)
+"""
+import os
+
+import numpy as np
+
+QMAX = 32          # tables per interleaved block the layouts are valid for
+QREF = 18          # block size the footprint is minimised for
+LMAX = 17
+
+
+def herm(L):
+    return [(t, u, n - t - u) for n in range(L + 1) for t in range(n, -1, -1) for u in range(n - t, -1, -1)]
+
+
+def simplex(L):
+    return np.array([(t, u, v) for t in range(L + 1) for u in range(L + 1 - t) for v in range(L + 1 - t - u)])
+
+
+def min_shift(img, rng):
+    """smallest C such that img + k*C (k < QMAX) are pairwise disjoint"""
+    idx = np.flatnonzero(np.bincount(img, minlength=rng))
+    diff = np.zeros(rng, bool)
+    for x in idx:
+        diff[idx[idx > x] - x] = True
+    for C in range(len(img), rng + 1):
+        if all(not diff[k * C] for k in range(1, QMAX) if k * C < rng):
+            return C
+    return rng
+
+
+def candidates(L):
+    pts = simplex(L)
+    out = []
+    for b in range(L + 1, 2 * (L + 1) + 3):
+        for a in range(b * (L // 2), (L + 1) * b + 9):
+            img = pts[:, 0] * a + pts[:, 1] * b + pts[:, 2]
+            if len(np.unique(img)) != len(img):
+                continue
+            rng = int(img.max()) + 1
+            C = min_shift(img, rng)
+            out.append(((QREF - 1) * C + rng, C, a, b))
+    return out
+
+
+def gather_cost(L, a, b, C):
+    """modelled LDS cycles of the A-operand gathers of one (L/2 | L/2) chunk"""
+    LB = (L + 1) // 2
+    LK = L - LB
+    HB, KH = herm(LB), herm(LK)
+    NHB, NKN = len(HB), len(herm(LK - 1)) if LK > 0 else 0
+    nq = max(1, min(9, 320 // NHB))
+    rows = nq * NHB
+    cyc = 0
+    for T in range((rows + 15) // 16):
+        for s in range(max(1, (NKN + 3) // 4)):
+            addr = []
+            for lane in range(64):
+                g, c = divmod(lane, 16)
+                kb, h = divmod(min(16 * T + c, rows - 1), NHB)
+                qt, qu, qv = KH[4 * s + g] if 4 * s + g < NKN else (0, 0, 0)
+                t, u, v = HB[h]
+                addr.append(kb * C + (t + qt) * a + (u + qu) * b + v + qv)
+            for p in range(0, 64, 32):
+                banks = {}
+                for x in addr[p:p + 32]:
+                    for dw in (2 * x, 2 * x + 1):
+                        banks.setdefault(dw % 64, set()).add(dw)
+                cyc += max(len(s_) for s_ in banks.values())
+    return cyc
+
+
+def choose(L):
+    if L == 0:
+        return 1, 1, 1
+    cand = candidates(L)
+    fmin = min(c[0] for c in cand)
+    near = [c for c in cand if c[0] <= 1.08 * fmin]
+    F, C, a, b = min(near, key=lambda c: (gather_cost(L, c[2], c[3], c[1]), c[0]))
+    return b, a, C
+
+
+def main():
+    rows = []
+    for L in range(LMAX + 1):
+        su, st, size = choose(L)
+        rows.append((L + 1, su, st, size))
+        print("L", L, "SU", su, "ST", st, "C", size, "dense", (L + 1) ** 3, flush=True)
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cube_layouts.h")
+    with open(path, "w") as f:
+        f.write("// cube_layouts.h -- written by gen_cube_layouts.py; do not edit.\n")
+        f.write("// Compact [r]^(0) table layouts: entry (t, u, v), t + u + v <= D - 1, at\n")
+        f.write("// t*ST + u*SU + v; tables of successive quartets SIZE doubles apart; valid\n")
+        f.write(f"// (every entry of up to {QMAX} tables at its own address) for D = 1..{LMAX + 1}.\n")
+        f.write("#pragma once\n\nnamespace mdx {\n\n")
+        f.write(f"constexpr int CUBE_COMPACT_QMAX = {QMAX};\n")
+        f.write(f"constexpr int CUBE_COMPACT_DMAX = {LMAX + 1};\n")
+        f.write("// {D, SU, ST, SIZE}\n")
+        f.write(f"constexpr int CUBE_COMPACT[{LMAX + 1}][4] = {{\n")
+        for r in rows:
+            f.write("    {%d, %d, %d, %d},\n" % r)
+        f.write("};\n\n}  // namespace mdx\n")
+    print(path)
+
+
+if __name__ == "__main__":
+    main()

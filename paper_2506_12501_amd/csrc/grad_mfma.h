@@ -28,12 +28,13 @@ namespace mdx {
 
 constexpr int GRAD_NWP_MAX = 48;   // other side's column stride bound (36 Cartesian functions)
 
-template <int LD, int LW, int NTN, int MTW, int NW, int WPE>
+template <int LD, int LW, int NTN, int MTW, int NW, int WPE, int LAY>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 eri_grad_kernel(GradArgs a)
 {
     constexpr int L = LD + LW + 1;   // the derivative side reaches order LD + 1
-    constexpr int D = L + 1, CUBE = D * D * D;
+    typedef Cube<L + 1, LAY> CB;
+    constexpr int D = L + 1, CUBE = CB::SIZE;
     constexpr int NH = nherm(L);
     constexpr int NHD = nherm(LD + 1);   // derivative-side rows per primitive pair
     constexpr int NKN = nherm(LW - 1);
@@ -66,8 +67,8 @@ eri_grad_kernel(GradArgs a)
     const int nw = a.nw, nwq = (nw + 3) & ~3, nwp = a.nwp;
 
     extern __shared__ double smem[];
-    double *cube = smem;                       // [nqmax][CUBE]
-    double *S = cube + nqmax * CUBE;           // [kkmax][nqmax][D]
+    double *cube = smem;                       // nqmax tables
+    double *S = cube + CB::words(nqmax);       // [kkmax][nqmax][D]
     double *PQ = S + kkmax * nqmax * D;        // [kkmax][nqmax][4]
     double *Wt = PQ + kkmax * nqmax * 4;       // [kkmax]
     double *Hk = Wt + kkmax;                   // [NTPAD][NP]   adjoint-folded ket block
@@ -83,8 +84,8 @@ eri_grad_kernel(GradArgs a)
         const Tuv r = herm_tuv(k);
         tuvt[k] = r.t | (r.u << 8) | (r.v << 16);
     }
-    for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? cube_off<D>(k) : 0;
-    for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? cube_off<D>(NKN + k) : 0;
+    for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? CB::off(k) : 0;
+    for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? CB::off(NKN + k) : 0;
     {
         const double *Wg = a.W + (int64_t)I * a.wsI + (int64_t)J * a.wsJ;
         for (int e = tid; e < NP * nwq; e += NT) {
@@ -127,7 +128,7 @@ eri_grad_kernel(GradArgs a)
             if (row < nrows) {
                 const int kb = row / NHD, h = row - kb * NHD;
                 const int pk = tuvt[h];
-                off = (kb - kb_lo) * CUBE + ((pk & 255) * D + ((pk >> 8) & 255)) * D + (pk >> 16);
+                off = (kb - kb_lo) * CUBE + CB::off(pk & 255, (pk >> 8) & 255, pk >> 16);
             }
             abase[tt] = off;
         }
@@ -179,9 +180,9 @@ eri_grad_kernel(GradArgs a)
             }
             {
                 const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
-                ysweeps<D, NW, YSER>(cube, Sk, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
+                ysweeps<CB, NW, YSER>(cube, Sk, PQk, NQ, NQ, nqmax, w, lane, std::make_integer_sequence<int, NW>{});
                 __syncthreads();
-                xsweeps<D, NW, NQCT, YSER>(cube, PQk, NQ, w, lane, std::make_integer_sequence<int, NW>{});
+                xsweeps<CB, NW, NQCT, YSER>(cube, PQk, NQ, NQ, nqmax, w, lane, std::make_integer_sequence<int, NW>{});
             }
 #pragma unroll
             for (int i = 0; i < HKR; ++i) {
@@ -285,28 +286,28 @@ eri_grad_kernel(GradArgs a)
     }
 }
 
-template <int LD, int LW, int NTN, int MTW, int NW>
+template <int LD, int LW, int NTN, int MTW, int NW, int LAY>
 static size_t grad_lds_bytes(int nqmax, int kkmax, int nwq, int nwp)
 {
-    constexpr int L = LD + LW + 1, D = L + 1, CUBE = D * D * D, NH = nherm(L);
+    constexpr int L = LD + LW + 1, D = L + 1, NH = nherm(L);
     constexpr int NTPAD = round_up(nherm(LW - 1), 4);
     constexpr int KT = round_up(ncart(LW), 4) / 4;
     constexpr int NP = NTN * 16;
-    const size_t dbl = (size_t)nqmax * CUBE + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)NTPAD * NP +
+    const size_t dbl = (size_t)Cube<D, LAY>::words(nqmax) + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)NTPAD * NP +
                        (size_t)4 * KT * NP + (size_t)NP * nwq + (size_t)NTPAD * nwp + (size_t)NW * 6;
     return dbl * 8 + (size_t)(NH + NTPAD + 4 * KT) * 4;
 }
 
-template <int LD, int LW, int NTN, int MTW, int NW, int WPE>
+template <int LD, int LW, int NTN, int MTW, int NW, int WPE, int LAY>
 static bool launch_grad(const GradArgs &a0, int nblocks, hipStream_t s)
 {
     GradArgs a = a0;
     constexpr int NHD = nherm(LD + 1);
     if (a.nwp > GRAD_NWP_MAX || a.nd > NTN * 16) return false;
     a.nqmax = std::min(a.dside.kmax, (NW * MTW * 16) / NHD + 2);
-    const size_t lds = grad_lds_bytes<LD, LW, NTN, MTW, NW>(a.nqmax, a.wside.kmax, (a.nw + 3) & ~3, a.nwp);
+    const size_t lds = grad_lds_bytes<LD, LW, NTN, MTW, NW, LAY>(a.nqmax, a.wside.kmax, (a.nw + 3) & ~3, a.nwp);
     if (lds > 160 * 1024) return false;
-    auto kern = eri_grad_kernel<LD, LW, NTN, MTW, NW, WPE>;
+    auto kern = eri_grad_kernel<LD, LW, NTN, MTW, NW, WPE, LAY>;
     static size_t lds_set = 0;   // largest dynamic LDS granted to this instance so far
     if (lds > 64 * 1024 && lds > lds_set) {
         if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -317,8 +318,9 @@ static bool launch_grad(const GradArgs &a0, int nblocks, hipStream_t s)
     return true;
 }
 
-// Dispatch over an instance list X(LD, LW, NTN, MTW, NW, WPE); several tile
-// shapes for one key are variants 1, 2, ... in listing order.
+// Dispatch over an instance list X(LD, LW, NTN, MTW, NW, WPE, LAY); several
+// tile shapes or table layouts for one key are variants 1, 2, ... in listing
+// order.
 #define MDX_GRAD_DISPATCH(SUFFIX, LIST)                                                          \
     int eri_grad_variants_##SUFFIX(const GradKey &k)                                             \
     {                                                                                            \
@@ -333,10 +335,10 @@ static bool launch_grad(const GradArgs &a0, int nblocks, hipStream_t s)
         LIST(MDX_GRAD_TRY)                                                                       \
         return false;                                                                            \
     }
-#define MDX_GRAD_COUNT(ld, lw, ntn, mtw, nw, wpe) \
+#define MDX_GRAD_COUNT(ld, lw, ntn, mtw, nw, wpe, lay) \
     if (k.LD == ld && k.LW == lw && k.NTN == ntn) ++n;
-#define MDX_GRAD_TRY(ld, lw, ntn, mtw, nw, wpe)                                 \
+#define MDX_GRAD_TRY(ld, lw, ntn, mtw, nw, wpe, lay)                            \
     if (k.LD == ld && k.LW == lw && k.NTN == ntn && ++n == variant)             \
-        return launch_grad<ld, lw, ntn, mtw, nw, wpe>(a, nblocks, s);
+        return launch_grad<ld, lw, ntn, mtw, nw, wpe, lay>(a, nblocks, s);
 
 }  // namespace mdx

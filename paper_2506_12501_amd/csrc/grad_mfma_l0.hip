@@ -1,17 +1,17 @@
 // grad_mfma_l0.hip -- backward kernel instances whose derivative side
-// has total Hermite order 0; X(LD, LW, NTN, MTW, NW, WPE).
+// has total Hermite order 0; X(LD, LW, NTN, MTW, NW, WPE, LAY).
 #include "grad_mfma.h"
 
 namespace mdx {
 
 #define MDX_GRAD_LIST_0(X) \
-    X(0, 0, 1, 2, 4, 2) \
-    X(0, 1, 1, 2, 4, 2) \
-    X(0, 2, 1, 2, 4, 2) \
-    X(0, 3, 1, 2, 4, 2) \
-    X(0, 4, 1, 2, 4, 2) \
-    X(0, 5, 1, 2, 4, 2) \
-    X(0, 6, 1, 2, 4, 2)
+    X(0, 0, 1, 2, 4, 2, 0) \
+    X(0, 1, 1, 2, 4, 2, 0) \
+    X(0, 2, 1, 2, 4, 2, 0) \
+    X(0, 3, 1, 2, 4, 2, 0) \
+    X(0, 4, 1, 2, 4, 2, 0) \
+    X(0, 5, 1, 2, 4, 2, 0) \
+    X(0, 6, 1, 2, 4, 2, 0)
 
 MDX_GRAD_DISPATCH(l0, MDX_GRAD_LIST_0)
 

@@ -1,17 +1,17 @@
 // grad_mfma_l2.hip -- backward kernel instances whose derivative side
-// has total Hermite order 2; X(LD, LW, NTN, MTW, NW, WPE).
+// has total Hermite order 2; X(LD, LW, NTN, MTW, NW, WPE, LAY).
 #include "grad_mfma.h"
 
 namespace mdx {
 
 #define MDX_GRAD_LIST_2(X) \
-    X(2, 0, 1, 3, 4, 2) \
-    X(2, 1, 1, 3, 4, 2) \
-    X(2, 2, 1, 3, 4, 2) \
-    X(2, 3, 1, 3, 4, 2) \
-    X(2, 4, 1, 3, 4, 2) \
-    X(2, 5, 1, 3, 4, 2) \
-    X(2, 6, 1, 3, 4, 2)
+    X(2, 0, 1, 3, 4, 2, 0) \
+    X(2, 1, 1, 3, 4, 2, 0) \
+    X(2, 2, 1, 3, 4, 2, 0) \
+    X(2, 3, 1, 3, 4, 2, 0) \
+    X(2, 4, 1, 3, 4, 2, 0) \
+    X(2, 5, 1, 3, 4, 2, 0) \
+    X(2, 6, 1, 3, 4, 2, 0)
 
 MDX_GRAD_DISPATCH(l2, MDX_GRAD_LIST_2)
 

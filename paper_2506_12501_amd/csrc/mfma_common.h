@@ -1,10 +1,11 @@
 // mfma_common.h -- pieces shared by the matrix-core integral kernels:
 // the FP64 MFMA wrapper and the one-axis sweeps of the Hermite recursion
-// (Eq. (31)) over a dense (L+1)^3 cube in LDS.
+// (Eq. (31)) over an (L+1)^3 cube in LDS with bank-padded strides.
 #pragma once
 
 #include <utility>
 
+#include "cube_layouts.h"
 #include "eri_common.h"
 #include "kernels.h"
 
@@ -17,40 +18,52 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// cube offset of Hermite k (t*D*D + u*D + v)
-template <int D>
-__host__ __device__ constexpr int cube_off(int k)
-{
-    const Tuv r = herm_tuv(k);
-    return (r.t * D + r.u) * D + r.v;
-}
+// LDS layout of the [r]^(0) tables, D = L+1 per axis: entry (t, u, v) of a
+// table at t*ST + u*SU + v, the tables of successive primitive quartets SIZE
+// doubles apart.  Only entries with t + u + v <= L exist.
+//  LAY < 1000: a D^3 cube padded by LAY = 100*pu + 10*pt + pc (u stride D+pu,
+//              t stride D*SU+pt, size D*ST+pc); padding spreads the rows of an
+//              MFMA operand gather and the lanes of a sweep over LDS banks.
+//  LAY = CUBE_LAY_COMPACT: the generated compact layout, whose tables fill each
+//              other's unused corners (at most QMAX tables per block).
+// The best choice depends on D and on the access mix, so kernel instances
+// carry it as a parameter and the autotuner chooses among them.
+constexpr int CUBE_LAY_COMPACT = 1000;
 
-template <int L, int LK>
-struct KetOffsets {
-    static constexpr int D = L + 1;
-    static constexpr int NKN = nherm(LK - 1);
-    static constexpr int NTPAD = round_up(NKN, 4);
-    static constexpr int NKT = ncart(LK);
-    static constexpr int NKTP = round_up(NKT, 4);
-    int q[NTPAD > 0 ? NTPAD : 1];   // non-terminal ket Hermites (0 for padding)
-    int t[NKTP];                    // terminal ket Hermites (0 for padding)
-    constexpr KetOffsets() : q{}, t{}
+template <int D_, int LAY>
+struct Cube {
+    static constexpr int D = D_;
+    static constexpr bool COMPACT = LAY == CUBE_LAY_COMPACT;
+    static_assert(COMPACT ? (D >= 1 && D <= CUBE_COMPACT_DMAX) : (LAY >= 0 && LAY < 1000), "table layout");
+    static constexpr int SU = COMPACT ? CUBE_COMPACT[D - 1][1] : D + LAY / 100;
+    static constexpr int ST = COMPACT ? CUBE_COMPACT[D - 1][2] : D * SU + (LAY / 10) % 10;
+    static constexpr int SIZE = COMPACT ? CUBE_COMPACT[D - 1][3] : D * ST + LAY % 10;
+    static constexpr int QMAX = COMPACT ? CUBE_COMPACT_QMAX : 1 << 20;
+    static_assert(ST >= SU && SU >= 1, "largest entry of a table is (D-1, 0, 0)");
+    static constexpr int SPAN = (D - 1) * ST + 1;   // extent of one table
+    // doubles spanned by n consecutive tables
+    __host__ __device__ static constexpr int words(int n) { return n > 0 ? (n - 1) * SIZE + SPAN : 0; }
+    __host__ __device__ static constexpr int off(int t, int u, int v) { return t * ST + u * SU + v; }
+    // offset of Hermite k
+    __host__ __device__ static constexpr int off(int k)
     {
-        for (int k = 0; k < NTPAD; ++k) q[k] = k < NKN ? cube_off<D>(k) : 0;
-        for (int k = 0; k < NKTP; ++k) t[k] = k < NKT ? cube_off<D>(NKN + k) : 0;
+        const Tuv r = herm_tuv(k);
+        return off(r.t, r.u, r.v);
     }
 };
 
-template <int N>
-__device__ __forceinline__ int pick4(const int (&v)[N], int base, int g)
+// Sweep slots: the tables of a sweep round are KP consecutive blocks of nqmax
+// slots, one block per ket primitive; slot Q holds a quartet when its index
+// within the block is below NQ (the chunk's bra primitives).
+__device__ __forceinline__ bool slot_live(int Q, int NQT, int NQ, int nqmax)
 {
-    // v[base + g] for a wave-varying g in 0..3 with compile-time base
-    const int a0 = v[base], a1 = v[base + 1], a2 = v[base + 2], a3 = v[base + 3];
-    return (g & 2) ? ((g & 1) ? a3 : a2) : ((g & 1) ? a1 : a0);
+    if (Q >= NQT) return false;
+    while (Q >= nqmax) Q -= nqmax;
+    return Q < NQ;
 }
 
 // [r]^(0) of one primitive quartet, Eq. (31), as three one-axis sweeps over
-// the table cube[(t*D + u)*D + v] (D = L+1).  Each sweep handles columns of a
+// the table CB (a Cube, D = L+1).  Each sweep handles columns of a
 // compile-time length, so it is fully unrolled: no predication, no wasted
 // work on short columns, recursion state in registers.
 //   z, y sweep: per v, raise z to v in registers, then y:
@@ -58,12 +71,12 @@ __device__ __forceinline__ int pick4(const int (&v)[N], int base, int g)
 //   x sweep:  per (u, v), [t u v]^(0), t <= M (M = L-u-v) -> (t, u, v)
 // Intermediate columns are stored at (m, u, v) and overwritten in place by
 // the lane that owns them.
-template <int D, int M>
-__device__ __forceinline__ void ysweep(double *__restrict__ cv /* cube + v */, const double *__restrict__ S, double Y,
+template <class CB, int M>
+__device__ __forceinline__ void ysweep(double *__restrict__ cv /* table + (0, 0, v) */, const double *__restrict__ S, double Y,
                                        double Z)
 {
     // z first: [0 0 v]^(m), m <= M, for v = L - M, from [0]^(m) (registers only)
-    constexpr int L = D - 1, V = L - M;
+    constexpr int D = CB::D, L = D - 1, V = L - M, SU = CB::SU, ST = CB::ST;
     double c[D], p[D];
 #pragma unroll
     for (int m = 0; m < D; ++m) {
@@ -85,7 +98,7 @@ __device__ __forceinline__ void ysweep(double *__restrict__ cv /* cube + v */, c
     // then y: [0 u v]^(m), m <= M - u
 #pragma unroll
     for (int m = 0; m <= M; ++m) {
-        cv[(m * D) * D] = c[m];
+        cv[m * ST] = c[m];
         p[m] = 0.0;
     }
 #pragma unroll
@@ -94,7 +107,7 @@ __device__ __forceinline__ void ysweep(double *__restrict__ cv /* cube + v */, c
 #pragma unroll
         for (int m = 0; m <= M - u; ++m) n[m] = u > 1 ? fma((double)(u - 1), p[m + 1], Y * c[m + 1]) : Y * c[m + 1];
 #pragma unroll
-        for (int m = 0; m <= M - u; ++m) cv[(m * D + u) * D] = n[m];
+        for (int m = 0; m <= M - u; ++m) cv[m * ST + u * SU] = n[m];
 #pragma unroll
         for (int m = 0; m <= M - u; ++m) {
             p[m] = c[m];
@@ -104,13 +117,14 @@ __device__ __forceinline__ void ysweep(double *__restrict__ cv /* cube + v */, c
     }
 }
 
-template <int D, int M>
-__device__ __forceinline__ void xsweep(double *__restrict__ cuv /* cube + u*D + v */, double X)
+template <class CB, int M>
+__device__ __forceinline__ void xsweep(double *__restrict__ cuv /* table + (0, u, v) */, double X)
 {
+    constexpr int ST = CB::ST;
     double c[M + 1], p[M + 1];
 #pragma unroll
     for (int m = 0; m <= M; ++m) {
-        c[m] = cuv[(m * D) * D];
+        c[m] = cuv[m * ST];
         p[m] = 0.0;
     }
 #pragma unroll
@@ -118,7 +132,7 @@ __device__ __forceinline__ void xsweep(double *__restrict__ cuv /* cube + u*D + 
         double n[M + 1];
 #pragma unroll
         for (int m = 0; m <= M - t; ++m) n[m] = t > 1 ? fma((double)(t - 1), p[m + 1], X * c[m + 1]) : X * c[m + 1];
-        cuv[(t * D) * D] = n[0];
+        cuv[t * ST] = n[0];
 #pragma unroll
         for (int m = 0; m <= M - t; ++m) {
             p[m] = c[m];
@@ -134,107 +148,112 @@ __device__ __forceinline__ void xsweep(double *__restrict__ cuv /* cube + u*D + 
 // under a single lane guard, so the scheduler can interleave their independent
 // recursion chains; idle lanes stay masked (a fully masked 16-lane group costs
 // no FP64 pipe time).  Requires NQ <= 64.
-template <int D, int NW, int W, int M>
+template <class CB, int NW, int W, int M>
 __device__ __forceinline__ void ycol(double *cq, const double *Sq, double Y, double Z)
 {
-    constexpr int v = D - 1 - M;
-    if constexpr (v % NW == W) ysweep<D, M>(cq + v, Sq, Y, Z);
+    constexpr int v = CB::D - 1 - M;
+    if constexpr (v % NW == W) ysweep<CB, M>(cq + v, Sq, Y, Z);
 }
 
-template <int D, int NW, int W, int... Ms>
-__device__ __forceinline__ void ywave(double *cube, const double *S, const double *PQ, int NQ, int lane,
-                                      std::integer_sequence<int, Ms...>)
+template <class CB, int NW, int W, int... Ms>
+__device__ __forceinline__ void ywave(double *cube, const double *S, const double *PQ, int NQ, int NQT, int nqmax,
+                                      int lane, std::integer_sequence<int, Ms...>)
 {
-    constexpr int CUBE = D * D * D;
-    if (lane >= NQ) return;
-    double *cq = cube + lane * CUBE;
-    const double *Sq = S + lane * D;
+    if (!slot_live(lane, NQT, NQ, nqmax)) return;
+    double *cq = cube + lane * CB::SIZE;
+    const double *Sq = S + lane * CB::D;
     const double Y = PQ[lane * 4 + 1], Z = PQ[lane * 4 + 2];
-    (ycol<D, NW, W, Ms>(cq, Sq, Y, Z), ...);
+    (ycol<CB, NW, W, Ms>(cq, Sq, Y, Z), ...);
 }
 
-template <int D, int NW, int W, int NQCT, int M>
-__device__ __forceinline__ void xcols(double *cube, const double *PQ, int NQ, int lane)
+template <class CB, int NW, int W, int NQCT, int M>
+__device__ __forceinline__ void xcols(double *cube, const double *PQ, int NQ, int NQT, int nqmax, int lane)
 {
-    constexpr int L = D - 1, s = L - M, CUBE = D * D * D;
+    constexpr int L = CB::D - 1, s = L - M;
     if constexpr (M > 0 && s % NW == W) {   // order 0 columns are complete after the y sweep
         constexpr int R = (NQCT * (s + 1) + 63) / 64;
-        const int n = NQ * (s + 1);
+        const int n = NQT * (s + 1);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             const int e = lane + 64 * r;
-            if (e < n) {
-                const int q = e / (s + 1), v = e - q * (s + 1), u = s - v;
-                xsweep<D, M>(cube + q * CUBE + u * D + v, PQ[q * 4]);
-            }
+            const int q = e / (s + 1), v = e - q * (s + 1), u = s - v;
+            if (e < n && slot_live(q, NQT, NQ, nqmax)) xsweep<CB, M>(cube + q * CB::SIZE + CB::off(0, u, v), PQ[q * 4]);
         }
     }
 }
 
-template <int D, int NW, int W, int NQCT, int... Ms>
-__device__ __forceinline__ void xwave(double *cube, const double *PQ, int NQ, int lane,
+template <class CB, int NW, int W, int NQCT, int... Ms>
+__device__ __forceinline__ void xwave(double *cube, const double *PQ, int NQ, int NQT, int nqmax, int lane,
                                       std::integer_sequence<int, Ms...>)
 {
-    (xcols<D, NW, W, NQCT, Ms>(cube, PQ, NQ, lane), ...);
+    (xcols<CB, NW, W, NQCT, Ms>(cube, PQ, NQ, NQT, nqmax, lane), ...);
 }
 
 // One z/y column per branch region: the chains of a wave run one after the
 // other, which keeps fewer registers live next to a large accumulator set.
-template <int D, int NW, int M>
-__device__ __forceinline__ void ycol_branch(double *cube, const double *S, const double *PQ, int NQ, int w, int lane)
+template <class CB, int NW, int M>
+__device__ __forceinline__ void ycol_branch(double *cube, const double *S, const double *PQ, int NQ, int NQT,
+                                            int nqmax, int w, int lane)
 {
-    constexpr int v = D - 1 - M, CUBE = D * D * D;
-    if (w == v % NW && lane < NQ)
-        ysweep<D, M>(cube + lane * CUBE + v, S + lane * D, PQ[lane * 4 + 1], PQ[lane * 4 + 2]);
+    constexpr int v = CB::D - 1 - M;
+    if (w == v % NW && slot_live(lane, NQT, NQ, nqmax))
+        ysweep<CB, M>(cube + lane * CB::SIZE + v, S + lane * CB::D, PQ[lane * 4 + 1], PQ[lane * 4 + 2]);
 }
 
-template <int D, int NW, int... Ms>
-__device__ __forceinline__ void ysweeps_serial(double *cube, const double *S, const double *PQ, int NQ, int w,
-                                               int lane, std::integer_sequence<int, Ms...>)
+template <class CB, int NW, int... Ms>
+__device__ __forceinline__ void ysweeps_serial(double *cube, const double *S, const double *PQ, int NQ, int NQT,
+                                               int nqmax, int w, int lane, std::integer_sequence<int, Ms...>)
 {
-    (ycol_branch<D, NW, Ms>(cube, S, PQ, NQ, w, lane), ...);
+    (ycol_branch<CB, NW, Ms>(cube, S, PQ, NQ, NQT, nqmax, w, lane), ...);
 }
 
-// z/y sweeps of all live quartets (every wave calls this; wave w does its
-// share).  SER selects the column-per-branch form for register-heavy kernels.
-template <int D, int NW, bool SER, int... Ws>
-__device__ __forceinline__ void ysweeps(double *cube, const double *S, const double *PQ, int NQ, int w,
-                                        int lane, std::integer_sequence<int, Ws...>)
+// z/y sweeps of the live slots Q < NQT (every wave calls this; wave w does its
+// share); S and PQ are indexed by slot.  Requires NQT <= 64.  SER selects the
+// column-per-branch form for register-heavy kernels.
+template <class CB, int NW, bool SER, int... Ws>
+__device__ __forceinline__ void ysweeps(double *cube, const double *S, const double *PQ, int NQ, int NQT, int nqmax,
+                                        int w, int lane, std::integer_sequence<int, Ws...>)
 {
     if constexpr (SER)
-        ysweeps_serial<D, NW>(cube, S, PQ, NQ, w, lane, std::make_integer_sequence<int, D>{});
+        ysweeps_serial<CB, NW>(cube, S, PQ, NQ, NQT, nqmax, w, lane, std::make_integer_sequence<int, CB::D>{});
     else
-        ((w == Ws ? ywave<D, NW, Ws>(cube, S, PQ, NQ, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
+        ((w == Ws ? ywave<CB, NW, Ws>(cube, S, PQ, NQ, NQT, nqmax, lane, std::make_integer_sequence<int, CB::D>{})
+                  : void()),
+         ...);
 }
 
 // x sweep of all columns of order M in a branch region of its own
-template <int D, int NW, int M>
-__device__ __forceinline__ void xorder_branch(double *cube, const double *PQ, int NQ, int w, int lane)
+template <class CB, int NW, int M>
+__device__ __forceinline__ void xorder_branch(double *cube, const double *PQ, int NQ, int NQT, int nqmax, int w,
+                                              int lane)
 {
-    constexpr int L = D - 1, s = L - M, CUBE = D * D * D;
+    constexpr int L = CB::D - 1, s = L - M;
     if (M > 0 && w == s % NW)
-        for (int e = lane; e < NQ * (s + 1); e += 64) {
+        for (int e = lane; e < NQT * (s + 1); e += 64) {
             const int q = e / (s + 1), v = e - q * (s + 1), u = s - v;
-            xsweep<D, M>(cube + q * CUBE + u * D + v, PQ[q * 4]);
+            if (slot_live(q, NQT, NQ, nqmax)) xsweep<CB, M>(cube + q * CB::SIZE + CB::off(0, u, v), PQ[q * 4]);
         }
 }
 
-template <int D, int NW, int... Ms>
-__device__ __forceinline__ void xsweeps_serial(double *cube, const double *PQ, int NQ, int w, int lane,
-                                               std::integer_sequence<int, Ms...>)
+template <class CB, int NW, int... Ms>
+__device__ __forceinline__ void xsweeps_serial(double *cube, const double *PQ, int NQ, int NQT, int nqmax, int w,
+                                               int lane, std::integer_sequence<int, Ms...>)
 {
-    (xorder_branch<D, NW, Ms>(cube, PQ, NQ, w, lane), ...);
+    (xorder_branch<CB, NW, Ms>(cube, PQ, NQ, NQT, nqmax, w, lane), ...);
 }
 
-// x sweeps (after the z/y sweeps of all waves are visible); SER as for ysweeps
-template <int D, int NW, int NQCT, bool SER, int... Ws>
-__device__ __forceinline__ void xsweeps(double *cube, const double *PQ, int NQ, int w, int lane,
+// x sweeps (after the z/y sweeps of all waves are visible); NQCT bounds NQT;
+// SER as for ysweeps
+template <class CB, int NW, int NQCT, bool SER, int... Ws>
+__device__ __forceinline__ void xsweeps(double *cube, const double *PQ, int NQ, int NQT, int nqmax, int w, int lane,
                                         std::integer_sequence<int, Ws...>)
 {
     if constexpr (SER)
-        xsweeps_serial<D, NW>(cube, PQ, NQ, w, lane, std::make_integer_sequence<int, D>{});
+        xsweeps_serial<CB, NW>(cube, PQ, NQ, NQT, nqmax, w, lane, std::make_integer_sequence<int, CB::D>{});
     else
-        ((w == Ws ? xwave<D, NW, Ws, NQCT>(cube, PQ, NQ, lane, std::make_integer_sequence<int, D>{}) : void()), ...);
+        ((w == Ws ? xwave<CB, NW, Ws, NQCT>(cube, PQ, NQ, NQT, nqmax, lane, std::make_integer_sequence<int, CB::D>{})
+                  : void()),
+         ...);
 }
 
 }  // namespace mdx

@@ -9,8 +9,10 @@ from tests.gpu_util import assert_close
 
 pytestmark = pytest.mark.gpu
 
-CASES = [("(dd|dd)", 3), ("(pd|dd)", 3), ("(ff|ff)", 1), ("(gg|gg)", 1), ("(pp|pp)", 1), ("(dd|ps)", 2),
-         ("(f|dd)", 2)]
+# contraction degrees K give 9 (odd) or 4 ket primitives per pair, so the
+# two-primitive sweep rounds meet a partial last round and full ones
+CASES = [("(dd|dd)", 3), ("(pd|dd)", 3), ("(ff|ff)", 1), ("(gg|gg)", 1), ("(pp|pp)", 2), ("(dd|ps)", 2),
+         ("(dd|pp)", 3), ("(dp|dp)", 2), ("(dp|ds)", 3), ("(f|dd)", 2)]
 
 
 @pytest.mark.parametrize("name,K", CASES)

@@ -80,7 +80,11 @@ def tune(ctx, shells, ncentre, bra, ket, call, cartesian=False, reps=3, cache=Tr
     for v in variants(ctx, ncentre, la, lb, lc, ld, cartesian, gradient):
         native.check(L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), fl, v),
                      "mdx_set_variant")
-        times[v] = time_call(call, reps)
+        try:
+            times[v] = time_call(call, reps)
+        except native.MdxError as e:
+            if e.status != native.MDX_EUNSUPPORTED:   # a variant that does not serve this batch
+                raise
     best = min(times, key=times.get)
     native.check(L.mdx_set_variant(ctx.handle, ncentre, la, max(lb, 0), lc, max(ld, 0), fl, best),
                  "mdx_set_variant")

@@ -164,6 +164,9 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
         return fail(MDX_EUNSUPPORTED, "no kernel compiled for class (%d %d|%d %d) ncentre %d %s", cp.la, cp.lb, cp.lc,
                     cp.ld, ncentre, cart ? "Cartesian" : "spherical");
     if (cp.kind == K_MFMA && cp.variant == 0) cp.variant = 1;
+    if (cp.kind == K_MFMA && eri_mfma_variant_prim(cp.key, cp.variant) && (cp.bra.g.kmax != 1 || cp.ket.g.kmax != 1))
+        return fail(MDX_EUNSUPPORTED, "variant %d of class (%d %d|%d %d) serves single-primitive pairs only", cp.variant,
+                    cp.la, cp.lb, cp.lc, cp.ld);
 
     // terminal ket matrix
     const int kl0 = cp.ket.g.la, kl1 = cp.ket.g.lb;

@@ -56,6 +56,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     constexpr int GW = NTG * 16;
     constexpr int NT = 64 * NW;
     constexpr int HKR = (NTPAD * GW + NT - 1) / NT;   // staged ket values per thread
+    constexpr int TKR = (4 * KT * GW + NT - 1) / NT;  // staged terminal-matrix values per thread
     constexpr bool YSER = MTW * NTG * 4 + MTW * KT > 48;   // large accumulator set: sweep columns one branch each
     constexpr int NQCT = GB ? 1 : (NW * MTW * 16) / NHB + 2;   // bound on quartets per chunk (host: nqmax)
     static_assert(NTCD % NTG == 0, "cd tiles must split into groups");
@@ -92,6 +93,8 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     int *tuvt = (int *)(Tk + 4 * KT * GW);               // [NH] packed t | u<<8 | v<<16
     int *kq = tuvt + NH;                                 // [NTPAD] cube offsets, non-terminal ket
     int *kt = kq + NTPAD;                                // [4*KT] cube offsets, terminal ket
+    int *oab = kt + 4 * KT;                              // [NABP] output offsets (copies of a.om)
+    int *ocd = oab + NABP;                               // [NCDP]
 
     for (int k = tid; k < NH; k += NT) {
         const Tuv r = herm_tuv(k);
@@ -99,6 +102,10 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     }
     for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? CB::off(k) : 0;
     for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? CB::off(NKN + k) : 0;
+    if constexpr (NW > 1) {   // the cross-wave epilogues look output offsets up in LDS
+        for (int k = tid; k < NABP; k += NT) oab[k] = k < a.nab ? a.om.oab[k] : 0;
+        for (int k = tid; k < NCDP; k += NT) ocd[k] = k < a.ncd ? a.om.ocd[k] : 0;
+    }
 
     const PrimRec *bp = a.bra.prim + (int64_t)I * a.bra.kmax;
     const PrimRec *kp = a.ket.prim + (int64_t)J * a.ket.kmax;
@@ -119,7 +126,16 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
             const int NQ = kb_hi - kb_lo + 1;
 
             __syncthreads();   // Hermite table visible; previous users of LDS done
-            for (int e = tid; e < 4 * KT * GW; e += NT) Tk[e] = a.Tket[(e / GW) * NCDP + grp * GW + (e % GW)];
+            // terminal ket matrix of this column group; with several groups the
+            // loads are issued now and stored after [0]^(m), hiding their latency
+            double tv[TKR];
+#pragma unroll
+            for (int i = 0; i < TKR; ++i) {
+                const int e = tid + i * NT;
+                tv[i] = e < 4 * KT * GW ? a.Tket[(e / GW) * NCDP + grp * GW + (e % GW)] : 0.0;
+                if constexpr (NG == 1)
+                    if (e < 4 * KT * GW) Tk[e] = tv[i];
+            }
             int abase[MTW];
 #pragma unroll
             for (int tt = 0; tt < MTW; ++tt) {
@@ -180,6 +196,14 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                     pq4[1] = Yv;
                     pq4[2] = Z;
                     if (q == 0) Wt[kk] = K.wt;
+                }
+            }
+
+            if constexpr (NG > 1) {
+#pragma unroll
+                for (int i = 0; i < TKR; ++i) {
+                    const int e = tid + i * NT;
+                    if (e < 4 * KT * GW) Tk[e] = tv[i];
                 }
             }
 
@@ -307,7 +331,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                         for (int r = 0; r < 4; ++r) {
                             const int ab = 16 * mm + 4 * r + g;
                             const int cd = grp * GW + 16 * n + c;
-                            if (ab < a.nab && cd < a.ncd) {
+                            if (ab < a.nab && cd < a.ncd) {   // one wave: offsets from the arguments
                                 double *dst = a.om.out + obase + (int64_t)I * a.om.sI +
                                               omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd]);
                                 *dst = ch == 0 ? O[mm][n][r] : *dst + O[mm][n][r];
@@ -330,7 +354,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                     const int ab = 16 * mm + 4 * r + g;
                     const int cd = grp * GW + 16 * n + c;
                     if (ab < a.nab && cd < a.ncd) {
-                        double *dst = a.om.out + obase + (int64_t)I * a.om.sI + omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd]);
+                        double *dst = a.om.out + obase + (int64_t)I * a.om.sI + omult * (int64_t)(oab[ab] + ocd[cd]);
                         *dst = ch == 0 ? v : *dst + v;
                     }
                 }
@@ -356,7 +380,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                             const int cd = grp * GW + 16 * n + c;
                             if (ab < a.nab && cd < a.ncd) {
                                 double *dst = a.om.out + obase + (int64_t)I * a.om.sI +
-                                              omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd]);
+                                              omult * (int64_t)(oab[ab] + ocd[cd]);
                                 *dst = ch == 0 ? v : *dst + v;
                             }
                         }
@@ -382,7 +406,7 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     const size_t tabs = (size_t)Cube<D, LAY>::words(KP * nqmax);
     const size_t cube_words = SEPRED ? tabs + RED : std::max(tabs, RED);
     return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(KP * NTPAD + 4 * KT) * NTG * 16) * 8 +
-           (size_t)(NH + NTPAD + 4 * KT) * 4;
+           (size_t)(NH + NTPAD + 4 * KT + (NTAB + NTCD) * 16) * 4;
 }
 
 // Instances: class key (LB, LK, NAB, NCD, GB), tile shape

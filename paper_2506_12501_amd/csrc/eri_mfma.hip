@@ -8,25 +8,8 @@ template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB,
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 eri_mfma_kernel(EriArgs a)
 {
-    int J, I;
-    if (a.diag) {   // diagonal shellsets (I = J) only
-        J = blockIdx.x;
-        I = J;
-    } else if (a.tile_off) {   // ragged batch: one shellset per tile
-        ragged_tile(a.tile_off, a.nket, blockIdx.x, J, I);
-    } else {
-        // blocks of 8 bra x 16 ket pairs, dealt to the XCDs in contiguous
-        // ranges: the workgroups resident on an XCD share 8 bra and 16 ket H
-        // blocks in its L2 (bra blocks run fastest, so the ket H stays), and 8
-        // consecutive bra pairs fill output lines
-        const int t = xcd_tile(blockIdx.x, gridDim.x);
-        const int blk = t >> 7, e = t & 127;
-        I = (blk % a.tiles_per_J) * 8 + (e & 7);
-        J = (blk / a.tiles_per_J) * 16 + (e >> 3);
-    }
-    if (J >= a.nket) return;   // whole workgroup
-    const int nI = a.diag ? J + 1 : (a.om.count ? a.om.count[J] : a.nbra);
-    if (I >= nI) return;       // whole workgroup
+    int I, J, nI;
+    if (!mfma_block_shellset(a, I, J, nI)) return;   // whole workgroup
     eri_mfma_shellset<LB, LK, NTAB, NTCD, NTG, MTW, NW, GB, LAY, KP>(a, I, J, nI);
 }
 
@@ -54,7 +37,7 @@ static bool key_is(const EriKey &k, int lb, int lk, int nab, int ncd, bool gb)
     return !k.GK && k.LB == lb && k.LK == lk && k.NAB == nab && k.NCD == ncd && k.GB == gb;
 }
 
-int eri_mfma_variants(const EriKey &k)
+static int eri_mfma_only_variants(const EriKey &k)
 {
     int n = 0;
 #define MDX_COUNT(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp) \
@@ -64,7 +47,11 @@ int eri_mfma_variants(const EriKey &k)
     return n;
 }
 
+int eri_mfma_variants(const EriKey &k) { return eri_mfma_only_variants(k) + eri_prim_variants(k); }
+
 bool eri_mfma_has(const EriKey &k) { return eri_mfma_variants(k) > 0; }
+
+bool eri_mfma_variant_prim(const EriKey &k, int variant) { return variant > eri_mfma_only_variants(k); }
 
 bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s)
 {
@@ -74,7 +61,7 @@ bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant
         return launch_mfma<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe, lay, kp>(a, nblocks, s);
     MDX_MFMA_INSTANCES(MDX_TRY)
 #undef MDX_TRY
-    return false;
+    return eri_prim_launch(k, a, nblocks, variant - n, s);
 }
 
 }  // namespace mdx

@@ -70,6 +70,11 @@ bool eri_valu_has(const EriKey &k);
 bool eri_valu_launch(const EriKey &k, const EriArgs &a, int nblocks, hipStream_t s);
 bool eri_mfma_has(const EriKey &k);
 int eri_mfma_variants(const EriKey &k);
+// true: the variant is a single-primitive kernel (bra and ket pairs with one
+// primitive pair each); those follow the other matrix-core variants of a key
+bool eri_mfma_variant_prim(const EriKey &k, int variant);
+int eri_prim_variants(const EriKey &k);
+bool eri_prim_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
 bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
 
 // Backward kernel arguments.  The derivative side (pair data in the

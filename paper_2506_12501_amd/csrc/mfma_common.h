@@ -52,6 +52,30 @@ struct Cube {
     }
 };
 
+// Shellset (I, J) of this workgroup in a plain matrix-core launch, and nI, the
+// bra pairs of ket J; false: the workgroup has no shellset.
+__device__ __forceinline__ bool mfma_block_shellset(const EriArgs &a, int &I, int &J, int &nI)
+{
+    if (a.diag) {   // diagonal shellsets (I = J) only
+        J = blockIdx.x;
+        I = J;
+    } else if (a.tile_off) {   // ragged batch: one shellset per tile
+        ragged_tile(a.tile_off, a.nket, blockIdx.x, J, I);
+    } else {
+        // blocks of 8 bra x 16 ket pairs, dealt to the XCDs in contiguous
+        // ranges: the workgroups resident on an XCD share 8 bra and 16 ket H
+        // blocks in its L2 (bra blocks run fastest, so the ket H stays), and 8
+        // consecutive bra pairs fill output lines
+        const int t = xcd_tile(blockIdx.x, gridDim.x);
+        const int blk = t >> 7, e = t & 127;
+        I = (blk % a.tiles_per_J) * 8 + (e & 7);
+        J = (blk / a.tiles_per_J) * 16 + (e >> 3);
+    }
+    if (J >= a.nket) return false;
+    nI = a.diag ? J + 1 : (a.om.count ? a.om.count[J] : a.nbra);
+    return I < nI;
+}
+
 // Sweep slots: the tables of a sweep round are KP consecutive blocks of nqmax
 // slots, one block per ket primitive; slot Q holds a quartet when its index
 // within the block is below NQ (the chunk's bra primitives).

@@ -40,3 +40,21 @@ def test_unknown_variant_rejected():
     ctx = native.Context.get(0)
     st = native.lib().mdx_set_variant(ctx.handle, 4, 0, 0, 0, 0, 0, 17)
     assert st == native.MDX_EINVAL
+
+
+def test_single_primitive_variants_reject_contracted_pairs():
+    """the single-primitive kernels are variants of their class that serve only
+    uncontracted pairs; a contracted batch under one of them is refused"""
+    from paper_2506_12501_amd import autotune, native
+    b = W.make_class_batch("(ff|ff)", 3, 2, 2, 6.0, 0.05, 30.0, 0.1, 1.0, seed=32)
+    ctx = native.Context.get(0)
+    vs = autotune.variants(ctx, 4, 3, 3, 3, 3, False)
+    sh = native.DeviceShells(b.basis)
+    L = native.lib()
+    try:
+        native.check(L.mdx_set_variant(ctx.handle, 4, 3, 3, 3, 3, 0, vs[-1]), "variant")
+        with pytest.raises(native.MdxError) as e:
+            native.eri(sh, 4, b.bra, b.ket)
+        assert e.value.status == native.MDX_EUNSUPPORTED
+    finally:
+        L.mdx_set_variant(ctx.handle, 4, 3, 3, 3, 3, 0, -1)

@@ -187,11 +187,13 @@ __host__ __device__ inline size_t prim_lds_bytes()
 // key in the variant numbering and serve only batches whose pairs are single
 // primitive pairs.
 #define MDX_PRIM_INSTANCES(X)                                                                      \
-    X(6, 6, 49, 49, 4, 4, 2, 3, CUBE_LAY_COMPACT)              /* (ff|ff)                   */    \
-    X(6, 6, 49, 49, 4, 4, 4, 3, CUBE_LAY_COMPACT)                                                  \
-    X(8, 8, 81, 81, 6, 6, 6, 3, CUBE_LAY_COMPACT)              /* (gg|gg)                   */    \
-    X(8, 8, 81, 81, 6, 6, 6, 2, CUBE_LAY_COMPACT)                                                  \
-    X(8, 8, 81, 81, 6, 6, 2, 2, CUBE_LAY_COMPACT)                                                  \
-    X(8, 8, 81, 81, 6, 6, 3, 2, CUBE_LAY_COMPACT)
+    X(6, 6, 49, 49, 4, 4, 4, 3, CUBE_LAY_COMPACT)              /* (ff|ff)                   */    \
+    X(6, 6, 49, 49, 4, 4, 2, 3, CUBE_LAY_COMPACT)                                                  \
+    X(6, 6, 49, 49, 4, 4, 2, 4, CUBE_LAY_COMPACT)                                                  \
+    X(6, 6, 49, 49, 4, 4, 1, 3, CUBE_LAY_COMPACT)                                                  \
+    X(8, 8, 81, 81, 6, 6, 2, 2, CUBE_LAY_COMPACT)              /* (gg|gg)                   */    \
+    X(8, 8, 81, 81, 6, 6, 3, 2, CUBE_LAY_COMPACT)                                                  \
+    X(8, 8, 81, 81, 6, 6, 6, 3, CUBE_LAY_COMPACT)                                                  \
+    X(8, 8, 81, 81, 6, 6, 1, 2, CUBE_LAY_COMPACT)
 
 }  // namespace mdx

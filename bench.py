@@ -369,8 +369,8 @@ def load_traffic(kernel_tag):
     return d.get("bytes_per_launch")
 
 
-KERNEL_SOURCES = ["eri_mfma.hip", "eri_mfma.h", "mfma_common.h", "eri_common.h", "kernels.h", "mdx_internal.h", "boys_device.h",
-                  "eri.cpp"]
+KERNEL_SOURCES = ["eri_mfma.hip", "eri_mfma.h", "mfma_common.h", "cube_layouts.h", "eri_common.h", "kernels.h",
+                  "mdx_internal.h", "boys_device.h", "eri.cpp"]
 
 
 def kernel_source_hash():

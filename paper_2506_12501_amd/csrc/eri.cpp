@@ -164,9 +164,16 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
         return fail(MDX_EUNSUPPORTED, "no kernel compiled for class (%d %d|%d %d) ncentre %d %s", cp.la, cp.lb, cp.lc,
                     cp.ld, ncentre, cart ? "Cartesian" : "spherical");
     if (cp.kind == K_MFMA && cp.variant == 0) cp.variant = 1;
-    if (cp.kind == K_MFMA && eri_mfma_variant_prim(cp.key, cp.variant) && (cp.bra.g.kmax != 1 || cp.ket.g.kmax != 1))
-        return fail(MDX_EUNSUPPORTED, "variant %d of class (%d %d|%d %d) serves single-primitive pairs only", cp.variant,
-                    cp.la, cp.lb, cp.lc, cp.ld);
+    if (cp.kind == K_MFMA) {
+        const int kind = eri_mfma_variant_kind(cp.key, cp.variant);
+        if (kind == MFMA_PRIM && (cp.bra.g.kmax != 1 || cp.ket.g.kmax != 1))
+            return fail(MDX_EUNSUPPORTED, "variant %d of class (%d %d|%d %d) serves single-primitive pairs only",
+                        cp.variant, cp.la, cp.lb, cp.lc, cp.ld);
+        if (kind == MFMA_MULTI && cp.ket.g.kmax != 1)
+            return fail(MDX_EUNSUPPORTED, "variant %d of class (%d %d|%d %d) serves single-primitive ket pairs only",
+                        cp.variant, cp.la, cp.lb, cp.lc, cp.ld);
+        cp.bra_per_tile = eri_mfma_bra_per_tile(cp.key, cp.variant);
+    }
 
     // terminal ket matrix
     const int kl0 = cp.ket.g.la, kl1 = cp.ket.g.lb;
@@ -197,7 +204,7 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
         cp.count.resize(nket);
         cp.obase.resize(nket);
         cp.tile_off.resize(nket + 1);
-        const int rows = cp.kind == K_VALU ? 64 : 1;   // bra pairs per tile
+        const int rows = cp.kind == K_VALU ? 64 : cp.bra_per_tile;   // bra pairs per tile
         int64_t off = 0, ntile = 0;
         for (int32_t k = 0; k < nket; ++k) {
             const int32_t n = bra_count[k];
@@ -325,8 +332,9 @@ mdx_status class_args(mdx_ctx *c, const ClassPlan &cp, const ClassDev &d, double
         if (cp.kind == K_VALU) {   // 64 bra pairs (one per lane) per ket pair
             a.tiles_per_J = (int)((nb + 63) / 64);
             nbl = (int64_t)a.tiles_per_J * (int64_t)nk;
-        } else {                   // blocks of 8 bra x 16 ket pairs
-            a.tiles_per_J = (int)((nb + 7) / 8);
+        } else {                   // blocks of 8 bra tiles x 16 ket pairs
+            const size_t units = (nb + cp.bra_per_tile - 1) / cp.bra_per_tile;
+            a.tiles_per_J = (int)((units + 7) / 8);
             nbl = (int64_t)a.tiles_per_J * (int64_t)((nk + 15) / 16) * 128;
         }
         if (nbl > INT32_MAX) return fail(MDX_EUNSUPPORTED, "%lld workgroups in one launch (split the batch)", (long long)nbl);

@@ -41,7 +41,6 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     constexpr int L = LB + LK;
     typedef Cube<L + 1, LAY> CB;
     constexpr int D = L + 1, CUBE = CB::SIZE;
-    constexpr int NH = nherm(L);
     constexpr int NUV = (L + 1) * (L + 2) / 2;
     constexpr int NHB = GB ? ncart(LB) : nherm(LB);
     constexpr int HB0 = GB ? nherm(LB - 1) : 0;
@@ -90,16 +89,13 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     double *Wt = PQ + kkmax * nqmax * 4;                 // [kkmax] terminal weights
     double *Hk = Wt + kkmax;                             // [KP][NTPAD][GW]
     double *Tk = Hk + KP * NTPAD * GW;                   // [4*KT][GW]
-    int *tuvt = (int *)(Tk + 4 * KT * GW);               // [NH] packed t | u<<8 | v<<16
-    int *kq = tuvt + NH;                                 // [NTPAD] cube offsets, non-terminal ket
-    int *kt = kq + NTPAD;                                // [4*KT] cube offsets, terminal ket
+    int *kq = (int *)(Tk + 4 * KT * GW);                 // [NTPAD] table offsets, non-terminal ket
+    int *kt = kq + NTPAD;                                // [4*KT] table offsets, terminal ket
     int *oab = kt + 4 * KT;                              // [NABP] output offsets (copies of a.om)
     int *ocd = oab + NABP;                               // [NCDP]
+    int *rowt = ocd + NCDP;                              // [NHB] table offsets of the bra Hermite rows
 
-    for (int k = tid; k < NH; k += NT) {
-        const Tuv r = herm_tuv(k);
-        tuvt[k] = r.t | (r.u << 8) | (r.v << 16);
-    }
+    for (int k = tid; k < NHB; k += NT) rowt[k] = CB::off(HB0 + k);
     for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? CB::off(k) : 0;
     for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? CB::off(NKN + k) : 0;
     if constexpr (NW > 1) {   // the cross-wave epilogues look output offsets up in LDS
@@ -144,8 +140,7 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                 if (row < nrows) {
                     const int kb = GB ? 0 : row / NHB;
                     const int h = GB ? row : row - kb * NHB;
-                    const int pk = tuvt[HB0 + h];
-                    off = (kb - kb_lo) * CUBE + CB::off(pk & 255, (pk >> 8) & 255, pk >> 16);
+                    off = (kb - kb_lo) * CUBE + rowt[h];
                 }
                 abase[tt] = off;
             }
@@ -398,7 +393,7 @@ struct MfmaShape {
 template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int LAY, int KP>
 __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
 {
-    constexpr int L = LB + LK, D = L + 1, NH = nherm(L);
+    constexpr int L = LB + LK, D = L + 1;
     constexpr int NTPAD = round_up(nherm(LK - 1), 4);
     constexpr int KT = round_up(ncart(LK), 4) / 4;
     constexpr bool SEPRED = NTCD / NTG > 1;
@@ -406,7 +401,7 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     const size_t tabs = (size_t)Cube<D, LAY>::words(KP * nqmax);
     const size_t cube_words = SEPRED ? tabs + RED : std::max(tabs, RED);
     return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(KP * NTPAD + 4 * KT) * NTG * 16) * 8 +
-           (size_t)(NH + NTPAD + 4 * KT + (NTAB + NTCD) * 16) * 4;
+           (size_t)(NTPAD + 4 * KT + (NTAB + NTCD) * 16 + (GB ? ncart(LB) : nherm(LB))) * 4;
 }
 
 // Instances: class key (LB, LK, NAB, NCD, GB), tile shape

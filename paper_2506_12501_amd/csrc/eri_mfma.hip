@@ -47,11 +47,25 @@ static int eri_mfma_only_variants(const EriKey &k)
     return n;
 }
 
-int eri_mfma_variants(const EriKey &k) { return eri_mfma_only_variants(k) + eri_prim_variants(k); }
+int eri_mfma_variants(const EriKey &k)
+{
+    return eri_mfma_only_variants(k) + eri_prim_variants(k) + eri_multi_variants(k);
+}
 
 bool eri_mfma_has(const EriKey &k) { return eri_mfma_variants(k) > 0; }
 
-bool eri_mfma_variant_prim(const EriKey &k, int variant) { return variant > eri_mfma_only_variants(k); }
+int eri_mfma_variant_kind(const EriKey &k, int variant)
+{
+    variant -= eri_mfma_only_variants(k);
+    if (variant <= 0) return MFMA_GENERAL;
+    return variant <= eri_prim_variants(k) ? MFMA_PRIM : MFMA_MULTI;
+}
+
+int eri_mfma_bra_per_tile(const EriKey &k, int variant)
+{
+    if (eri_mfma_variant_kind(k, variant) != MFMA_MULTI) return 1;
+    return eri_multi_bra_per_tile(k, variant - eri_mfma_only_variants(k) - eri_prim_variants(k));
+}
 
 bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s)
 {
@@ -61,7 +75,9 @@ bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant
         return launch_mfma<lb, lk, ntab, ntcd, ntg, mtw, nw, gb, wpe, lay, kp>(a, nblocks, s);
     MDX_MFMA_INSTANCES(MDX_TRY)
 #undef MDX_TRY
-    return eri_prim_launch(k, a, nblocks, variant - n, s);
+    variant -= n;
+    const int np = eri_prim_variants(k);
+    return variant <= np ? eri_prim_launch(k, a, nblocks, variant, s) : eri_multi_launch(k, a, nblocks, variant - np, s);
 }
 
 }  // namespace mdx

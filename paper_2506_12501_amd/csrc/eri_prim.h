@@ -20,23 +20,6 @@
 
 namespace mdx {
 
-// table offsets of the ket rows as the pair data stores them: non-terminal
-// Hermites, padding to a multiple of 4, terminal Hermites, padding (0)
-template <class CB, int LK, int N>
-struct KetRowOffsets {
-    int o[N];
-    constexpr KetRowOffsets() : o{}
-    {
-        constexpr int NKN = nherm(LK - 1), NTPAD = round_up(NKN, 4), RPB = NTPAD + ncart(LK);
-        for (int k = 0; k < N; ++k) o[k] = k < NKN ? CB::off(k) : (k >= NTPAD && k < RPB ? CB::off(NKN + k - NTPAD) : 0);
-    }
-};
-
-__device__ __forceinline__ int sel4(int a0, int a1, int a2, int a3, int g)
-{
-    return (g & 2) ? ((g & 1) ? a3 : a2) : ((g & 1) ? a1 : a0);
-}
-
 template <int LB, int LK, int NTAB, int NTCD, int NW, int LAY>
 __device__ __forceinline__ void eri_prim_shellset(const EriArgs &a, const int I, const int J, const int nI)
 {

@@ -35,7 +35,6 @@ eri_grad_kernel(GradArgs a)
     constexpr int L = LD + LW + 1;   // the derivative side reaches order LD + 1
     typedef Cube<L + 1, LAY> CB;
     constexpr int D = L + 1, CUBE = CB::SIZE;
-    constexpr int NH = nherm(L);
     constexpr int NHD = nherm(LD + 1);   // derivative-side rows per primitive pair
     constexpr int NKN = nherm(LW - 1);
     constexpr int NTPAD = round_up(NKN, 4);
@@ -76,14 +75,11 @@ eri_grad_kernel(GradArgs a)
     double *Wl = Tk + 4 * KT * NP;             // [NP][nwq]     adjoint block W[i][j]
     double *Hr = Wl + NP * nwq;                // [NTPAD][nwp]  raw ket block
     double *red = Hr + NTPAD * nwp;            // [NW][6]
-    int *tuvt = (int *)(red + NW * 6);         // [NH]
-    int *kq = tuvt + NH;                       // [NTPAD]
+    int *kq = (int *)(red + NW * 6);           // [NTPAD]
     int *kt = kq + NTPAD;                      // [4*KT]
+    int *rowt = kt + 4 * KT;                   // [NHD] table offsets of the derivative-side rows
 
-    for (int k = tid; k < NH; k += NT) {
-        const Tuv r = herm_tuv(k);
-        tuvt[k] = r.t | (r.u << 8) | (r.v << 16);
-    }
+    for (int k = tid; k < NHD; k += NT) rowt[k] = CB::off(k);
     for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? CB::off(k) : 0;
     for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? CB::off(NKN + k) : 0;
     {
@@ -127,8 +123,7 @@ eri_grad_kernel(GradArgs a)
             int off = 0;
             if (row < nrows) {
                 const int kb = row / NHD, h = row - kb * NHD;
-                const int pk = tuvt[h];
-                off = (kb - kb_lo) * CUBE + CB::off(pk & 255, (pk >> 8) & 255, pk >> 16);
+                off = (kb - kb_lo) * CUBE + rowt[h];
             }
             abase[tt] = off;
         }
@@ -289,13 +284,13 @@ eri_grad_kernel(GradArgs a)
 template <int LD, int LW, int NTN, int MTW, int NW, int LAY>
 static size_t grad_lds_bytes(int nqmax, int kkmax, int nwq, int nwp)
 {
-    constexpr int L = LD + LW + 1, D = L + 1, NH = nherm(L);
+    constexpr int L = LD + LW + 1, D = L + 1;
     constexpr int NTPAD = round_up(nherm(LW - 1), 4);
     constexpr int KT = round_up(ncart(LW), 4) / 4;
     constexpr int NP = NTN * 16;
     const size_t dbl = (size_t)Cube<D, LAY>::words(nqmax) + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)NTPAD * NP +
                        (size_t)4 * KT * NP + (size_t)NP * nwq + (size_t)NTPAD * nwp + (size_t)NW * 6;
-    return dbl * 8 + (size_t)(NH + NTPAD + 4 * KT) * 4;
+    return dbl * 8 + (size_t)(NTPAD + 4 * KT + nherm(LD + 1)) * 4;
 }
 
 template <int LD, int LW, int NTN, int MTW, int NW, int WPE, int LAY>

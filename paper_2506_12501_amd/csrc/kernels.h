@@ -70,11 +70,19 @@ bool eri_valu_has(const EriKey &k);
 bool eri_valu_launch(const EriKey &k, const EriArgs &a, int nblocks, hipStream_t s);
 bool eri_mfma_has(const EriKey &k);
 int eri_mfma_variants(const EriKey &k);
-// true: the variant is a single-primitive kernel (bra and ket pairs with one
-// primitive pair each); those follow the other matrix-core variants of a key
-bool eri_mfma_variant_prim(const EriKey &k, int variant);
+// Variant kinds of a matrix-core class, numbered in this order: the general
+// kernel's instances, then single-primitive kernels (bra and ket pairs of one
+// primitive pair each), then 3-centre kernels taking several bra functions per
+// workgroup (ket pairs of one primitive pair).
+enum { MFMA_GENERAL = 0, MFMA_PRIM = 1, MFMA_MULTI = 2 };
+int eri_mfma_variant_kind(const EriKey &k, int variant);
+// bra functions per tile of a variant (1 but for the 3-centre multi kernels)
+int eri_mfma_bra_per_tile(const EriKey &k, int variant);
 int eri_prim_variants(const EriKey &k);
 bool eri_prim_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
+int eri_multi_variants(const EriKey &k);
+int eri_multi_bra_per_tile(const EriKey &k, int variant);
+bool eri_multi_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
 bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
 
 // Backward kernel arguments.  The derivative side (pair data in the

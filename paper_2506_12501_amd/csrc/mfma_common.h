@@ -52,6 +52,24 @@ struct Cube {
     }
 };
 
+// table offsets of the ket rows as the pair data stores them: non-terminal
+// Hermites, padding to a multiple of 4, terminal Hermites, padding (0)
+template <class CB, int LK, int N>
+struct KetRowOffsets {
+    int o[N];
+    constexpr KetRowOffsets() : o{}
+    {
+        constexpr int NKN = nherm(LK - 1), NTPAD = round_up(NKN, 4), RPB = NTPAD + ncart(LK);
+        for (int k = 0; k < N; ++k) o[k] = k < NKN ? CB::off(k) : (k >= NTPAD && k < RPB ? CB::off(NKN + k - NTPAD) : 0);
+    }
+};
+
+// a[g] for a lane group g in 0..3 (compile-time a)
+__device__ __forceinline__ int sel4(int a0, int a1, int a2, int a3, int g)
+{
+    return (g & 2) ? ((g & 1) ? a3 : a2) : ((g & 1) ? a1 : a0);
+}
+
 // Shellset (I, J) of this workgroup in a plain matrix-core launch, and nI, the
 // bra pairs of ket J; false: the workgroup has no shellset.
 __device__ __forceinline__ bool mfma_block_shellset(const EriArgs &a, int &I, int &J, int &nI)

@@ -62,6 +62,7 @@ struct ClassPlan {
     EriKey key{};
     KernelKind kind = K_VALU;
     int variant = 0;
+    int bra_per_tile = 1;                 // matrix-core tile: bra pairs / functions per workgroup
     OutMap om{};
     // ragged output (plans): per kernel-ket bra counts and bases
     std::vector<int32_t> count;

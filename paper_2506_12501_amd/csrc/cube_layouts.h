@@ -1,12 +1,12 @@
 // cube_layouts.h -- written by gen_cube_layouts.py; do not edit.
 // Compact [r]^(0) table layouts: entry (t, u, v), t + u + v <= D - 1, at
 // t*ST + u*SU + v; tables of successive quartets SIZE doubles apart; valid
-// (every entry of up to 32 tables at its own address) for D = 1..18.
+// (every entry of up to 48 tables at its own address) for D = 1..18.
 #pragma once
 
 namespace mdx {
 
-constexpr int CUBE_COMPACT_QMAX = 32;
+constexpr int CUBE_COMPACT_QMAX = 48;
 constexpr int CUBE_COMPACT_DMAX = 18;
 // {D, SU, ST, SIZE}
 constexpr int CUBE_COMPACT[18][4] = {

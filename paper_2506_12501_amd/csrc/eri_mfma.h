@@ -409,32 +409,37 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
 // and ket primitives per sweep round KP.  Several instances per key are
 // variants 1, 2, ... in listing order; the autotuner picks one per class.
 #define MDX_MFMA_INSTANCES(X)                                                                      \
-    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 2, CUBE_LAY_COMPACT, 2)/* (dd|dd)                   */   \
+    X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 2, CUBE_LAY_COMPACT, 2)  /* (dd|dd)                 */   \
     X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 2, 141, 1)                                               \
     X(4, 4, 25, 25, false, 2, 2, 2, 3, 4, 2, 141, 1)                                               \
     X(4, 4, 25, 25, false, 2, 2, 2, 5, 4, 1, 141, 1)                                               \
     X(4, 4, 25, 25, false, 2, 2, 1, 5, 4, 2, 141, 1)                                               \
     X(4, 4, 25, 25, false, 2, 2, 2, 3, 2, 3, 141, 1)                                               \
-    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 2)/* (dd|dp), (pd|dd) swapped  */   \
+    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 3)  /* (dd|dp), (pd|dd) swapped*/   \
+    X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 2)                                  \
     X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 2, 141, 1)                                               \
     X(4, 3, 25, 15, false, 2, 1, 1, 3, 4, 2, 141, 1)                                               \
     X(4, 3, 25, 15, false, 2, 1, 1, 5, 4, 1, 141, 1)                                               \
     X(4, 3, 25, 15, false, 2, 1, 1, 3, 2, 3, 141, 1)                                               \
     X(4, 2, 25, 9, false, 2, 1, 1, 5, 4, 2, 141, 1)             /* (dd|pp)                   */    \
     X(4, 2, 25, 9, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 2)                                   \
+    X(4, 2, 25, 9, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 3)                                   \
     X(4, 2, 25, 5, false, 2, 1, 1, 5, 4, 2, 141, 1)             /* (dd|ds)                   */    \
     X(4, 2, 25, 5, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 2)                                   \
+    X(4, 2, 25, 5, false, 2, 1, 1, 5, 4, 2, CUBE_LAY_COMPACT, 3)                                   \
     X(3, 3, 15, 15, false, 1, 1, 1, 5, 4, 2, 141, 1)            /* (dp|dp)                   */    \
     X(3, 3, 15, 15, false, 1, 1, 1, 3, 4, 2, CUBE_LAY_COMPACT, 2)                                  \
+    X(3, 3, 15, 15, false, 1, 1, 1, 3, 4, 2, CUBE_LAY_COMPACT, 3)                                  \
     X(3, 2, 15, 9, false, 1, 1, 1, 5, 4, 2, 141, 1)             /* (dp|pp)                   */    \
     X(3, 2, 15, 9, false, 1, 1, 1, 3, 4, 2, CUBE_LAY_COMPACT, 2)                                   \
+    X(3, 2, 15, 9, false, 1, 1, 1, 3, 4, 2, CUBE_LAY_COMPACT, 3)                                   \
     X(3, 2, 15, 5, false, 1, 1, 1, 5, 4, 2, 141, 1)             /* (dp|ds)                   */    \
     X(3, 2, 15, 5, false, 1, 1, 1, 3, 4, 2, CUBE_LAY_COMPACT, 2)                                   \
     X(2, 2, 9, 9, false, 1, 1, 1, 5, 4, 2, 141, 1)              /* (pp|pp)                   */    \
     X(2, 2, 9, 9, false, 1, 1, 1, 2, 4, 2, CUBE_LAY_COMPACT, 2)                                    \
-    X(4, 4, 36, 36, false, 3, 3, 3, 5, 4, 2, CUBE_LAY_COMPACT, 2)/* (dd|dd) Cartesian         */   \
+    X(4, 4, 36, 36, false, 3, 3, 3, 5, 4, 2, CUBE_LAY_COMPACT, 2)  /* (dd|dd) Cartesian       */   \
     X(4, 4, 36, 36, false, 3, 3, 3, 5, 4, 2, 141, 1)                                               \
-    X(4, 3, 36, 18, false, 3, 2, 2, 5, 4, 2, CUBE_LAY_COMPACT, 2)/* (dd|dp) Cartesian         */   \
+    X(4, 3, 36, 18, false, 3, 2, 2, 5, 4, 2, CUBE_LAY_COMPACT, 2)  /* (dd|dp) Cartesian       */   \
     X(4, 3, 36, 18, false, 3, 2, 2, 5, 4, 2, 141, 1)                                               \
     X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 2, 10, 1)             /* (ff|ff)                   */    \
     X(6, 6, 49, 49, false, 4, 4, 2, 2, 3, 2, 141, 1)                                               \

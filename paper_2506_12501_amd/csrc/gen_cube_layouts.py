@@ -17,7 +17,7 @@ import os
 
 import numpy as np
 
-QMAX = 32          # tables per interleaved block the layouts are valid for
+QMAX = 48          # tables per interleaved block the layouts are valid for
 QREF = 18          # block size the footprint is minimised for
 LMAX = 17
 

@@ -163,7 +163,20 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
     else
         return fail(MDX_EUNSUPPORTED, "no kernel compiled for class (%d %d|%d %d) ncentre %d %s", cp.la, cp.lb, cp.lc,
                     cp.ld, ncentre, cart ? "Cartesian" : "spherical");
-    if (cp.kind == K_MFMA && cp.variant == 0) cp.variant = 1;
+    if (cp.kind == K_MFMA && cp.variant == 0) {
+        // untuned: the general kernel, or for batches of single primitive pairs
+        // the first kernel written for them
+        cp.variant = 1;
+        const int n = eri_mfma_variants(cp.key);
+        for (int v = 2; v <= n; ++v) {
+            const int kind = eri_mfma_variant_kind(cp.key, v);
+            if ((kind == MFMA_PRIM && cp.bra.g.kmax == 1 && cp.ket.g.kmax == 1) ||
+                (kind == MFMA_MULTI && cp.ket.g.kmax == 1)) {
+                cp.variant = v;
+                break;
+            }
+        }
+    }
     if (cp.kind == K_MFMA) {
         const int kind = eri_mfma_variant_kind(cp.key, cp.variant);
         if (kind == MFMA_PRIM && (cp.bra.g.kmax != 1 || cp.ket.g.kmax != 1))

@@ -20,8 +20,6 @@ namespace mdx {
     X(4, 4, 2, 5, 4, 2, 0) \
     X(4, 4, 2, 3, 4, 2, 0) \
     X(4, 4, 2, 4, 4, 1, 0) \
-    X(4, 4, 2, 4, 8, 2, 0) \
-    X(4, 4, 2, 4, 8, 2, CUBE_LAY_COMPACT) \
     X(4, 5, 2, 4, 4, 2, 0) \
     X(4, 6, 2, 4, 4, 2, 0) \
     X(4, 0, 3, 3, 4, 2, 0) \

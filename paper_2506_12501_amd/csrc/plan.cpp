@@ -345,7 +345,9 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
                 int nt = 0;
                 if (!eri_mfma_config(cp.key, cp.variant, cp.bra.g.kmax, cp.ket.g.kmax, pb.nqmax, lds, nt)) {
                     delete p;
-                    return fail(MDX_EUNSUPPORTED, "batch %d: kernel instance missing", i);
+                    return fail(MDX_EUNSUPPORTED,
+                                "batch %d: variant %d of its class has no persistent form (fused plans take the "
+                                "general matrix-core variants)", i, cp.variant);
                 }
             }
             const auto k = std::make_tuple(cp.key.LB, cp.key.LK, cp.key.NAB, cp.key.NCD, (int)cp.key.GB,

@@ -63,8 +63,12 @@ int eri_mfma_variant_kind(const EriKey &k, int variant)
 
 int eri_mfma_bra_per_tile(const EriKey &k, int variant)
 {
-    if (eri_mfma_variant_kind(k, variant) != MFMA_MULTI) return 1;
-    return eri_multi_bra_per_tile(k, variant - eri_mfma_only_variants(k) - eri_prim_variants(k));
+    const int v = variant - eri_mfma_only_variants(k);
+    switch (eri_mfma_variant_kind(k, variant)) {
+    case MFMA_PRIM: return eri_prim_bra_per_tile(k, v);
+    case MFMA_MULTI: return eri_multi_bra_per_tile(k, v - eri_prim_variants(k));
+    default: return 1;
+    }
 }
 
 bool eri_mfma_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s)

@@ -20,27 +20,6 @@
 
 namespace mdx {
 
-// Bra unit U (NBI consecutive bra functions from I0 = U*NBI) and ket pair J of
-// this workgroup: dense batches in the XCD-aware block order of the other
-// matrix-core launches, ragged batches one unit per tile.
-template <int NBI>
-__device__ __forceinline__ bool multi_block_unit(const EriArgs &a, int &I0, int &J, int &nI)
-{
-    int U;
-    if (a.tile_off) {
-        ragged_tile(a.tile_off, a.nket, blockIdx.x, J, U);
-    } else {
-        const int t = xcd_tile(blockIdx.x, gridDim.x);
-        const int blk = t >> 7, e = t & 127;
-        U = (blk % a.tiles_per_J) * 8 + (e & 7);
-        J = (blk / a.tiles_per_J) * 16 + (e >> 3);
-    }
-    if (J >= a.nket) return false;
-    nI = a.om.count ? a.om.count[J] : a.nbra;
-    I0 = U * NBI;
-    return I0 < nI;
-}
-
 template <int LB, int LK, int NTAB, int NTCD, int NW, int SPW, int LAY>
 __device__ __forceinline__ void eri_multi_unit(const EriArgs &a, const int I0, const int J, const int nI)
 {

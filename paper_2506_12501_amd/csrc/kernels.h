@@ -76,9 +76,10 @@ int eri_mfma_variants(const EriKey &k);
 // workgroup (ket pairs of one primitive pair).
 enum { MFMA_GENERAL = 0, MFMA_PRIM = 1, MFMA_MULTI = 2 };
 int eri_mfma_variant_kind(const EriKey &k, int variant);
-// bra functions per tile of a variant (1 but for the 3-centre multi kernels)
+// bra pairs / functions per tile of a variant (one workgroup)
 int eri_mfma_bra_per_tile(const EriKey &k, int variant);
 int eri_prim_variants(const EriKey &k);
+int eri_prim_bra_per_tile(const EriKey &k, int variant);
 bool eri_prim_launch(const EriKey &k, const EriArgs &a, int nblocks, int variant, hipStream_t s);
 int eri_multi_variants(const EriKey &k);
 int eri_multi_bra_per_tile(const EriKey &k, int variant);

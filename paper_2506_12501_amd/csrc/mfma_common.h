@@ -94,6 +94,27 @@ __device__ __forceinline__ bool mfma_block_shellset(const EriArgs &a, int &I, in
     return I < nI;
 }
 
+// Bra unit U (NBI consecutive bra pairs or functions from I0 = U*NBI) and ket
+// pair J of this workgroup: dense batches in the XCD-aware block order of the other
+// matrix-core launches, ragged batches one unit per tile.
+template <int NBI>
+__device__ __forceinline__ bool multi_block_unit(const EriArgs &a, int &I0, int &J, int &nI)
+{
+    int U;
+    if (a.tile_off) {
+        ragged_tile(a.tile_off, a.nket, blockIdx.x, J, U);
+    } else {
+        const int t = xcd_tile(blockIdx.x, gridDim.x);
+        const int blk = t >> 7, e = t & 127;
+        U = (blk % a.tiles_per_J) * 8 + (e & 7);
+        J = (blk / a.tiles_per_J) * 16 + (e >> 3);
+    }
+    if (J >= a.nket) return false;
+    nI = a.om.count ? a.om.count[J] : a.nbra;
+    I0 = U * NBI;
+    return I0 < nI;
+}
+
 // Sweep slots: the tables of a sweep round are KP consecutive blocks of nqmax
 // slots, one block per ket primitive; slot Q holds a quartet when its index
 // within the block is below NQ (the chunk's bra primitives).

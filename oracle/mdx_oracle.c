@@ -574,6 +574,55 @@ void EXPORT(overlap)(int la, int lb, const double *A, const double *B, int Ka, i
         }
 }
 
+/* Cartesian (or solid) kinetic-energy integrals of two contracted shells,
+ * T_ab = -1/2 <a| nabla^2 |b>.  The Laplacian acts on the ket Gaussian: along
+ * one axis d^2/dx^2 of x_B^j exp(-b x_B^2) is
+ *   j(j-1) x_B^{j-2} - 2b(2j+1) x_B^j + 4b^2 x_B^{j+2}   (times the Gaussian),
+ * so each 1-D factor is a combination of 1-D overlaps E^{i,j'}_0 (Eq. (8)),
+ * T_ab = sum_prims c_a c_b (pi/p)^{3/2} (t_x s_y s_z + s_x t_y s_z + s_x s_y t_z). */
+void EXPORT(kinetic)(int la, int lb, const double *A, const double *B, int Ka, int Kb,
+                     const double *za, const double *ca, const double *zb, const double *cb,
+                     int cartesian, double *out)
+{
+    int na = ncart(la), nb = ncart(lb);
+    int qa[OR_MAXCART][3], qb[OR_MAXCART][3];
+    cart_list(la, qa); cart_list(lb, qb);
+    REAL T[OR_MAXCART * OR_MAXCART];
+    for (int i = 0; i < na * nb; ++i) T[i] = 0;
+    for (int ka = 0; ka < Ka; ++ka)
+        for (int kb = 0; kb < Kb; ++kb) {
+            Etab E[3];
+            REAL a = za[ka], b = zb[kb], p = a + b;
+            for (int ax = 0; ax < 3; ++ax) ecoef(la, lb + 2, a, b, A[ax], B[ax], E[ax]);
+            REAL f = (REAL)ca[ka] * (REAL)cb[kb] * R_PI / p * R_SQRT(R_PI / p);
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                    REAL s1[3], t1[3];
+                    for (int ax = 0; ax < 3; ++ax) {
+                        int ia = qa[i][ax], jb = qb[j][ax];
+                        s1[ax] = E[ax][ia][jb][0];
+                        REAL d2 = 4 * b * b * E[ax][ia][jb + 2][0] - 2 * b * (2 * jb + 1) * E[ax][ia][jb][0];
+                        if (jb >= 2) d2 += (REAL)(jb * (jb - 1)) * E[ax][ia][jb - 2][0];
+                        t1[ax] = -d2 / 2;
+                    }
+                    T[i * nb + j] += f * (t1[0] * s1[1] * s1[2] + s1[0] * t1[1] * s1[2] + s1[0] * s1[1] * t1[2]);
+                }
+        }
+    if (cartesian) {
+        for (int i = 0; i < na * nb; ++i) out[i] = (double)T[i];
+        return;
+    }
+    double Ca[2 * OR_LMAX + 1][OR_MAXCART], Cb[2 * OR_LMAX + 1][OR_MAXCART];
+    solid_coefs(la, Ca); solid_coefs(lb, Cb);
+    for (int m = 0; m < nsph(la); ++m)
+        for (int n = 0; n < nsph(lb); ++n) {
+            REAL s = 0;
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) s += (REAL)Ca[m][i] * (REAL)Cb[n][j] * T[i * nb + j];
+            out[m * nsph(lb) + n] = (double)s;
+        }
+}
+
 /*
  * Batched shell quartets.
  *   ncentre = 4: bra[2*ij], bra[2*ij+1] shell indices; same for ket.

@@ -55,6 +55,10 @@ def _load(quad: bool = False):
     f.argtypes = [_c_int, _c_int, _p_d, _p_d, _c_int, _c_int, _p_d, _p_d, _p_d, _p_d, _c_int, _p_d]
     f.restype = None
     fns["overlap"] = f
+    f = getattr(lib, pre + "kinetic")
+    f.argtypes = [_c_int, _c_int, _p_d, _p_d, _c_int, _c_int, _p_d, _p_d, _p_d, _p_d, _c_int, _p_d]
+    f.restype = None
+    fns["kinetic"] = f
     f = getattr(lib, pre + "eri")
     f.argtypes = [_c_int, _c_int, _p_d, _p_i, _p_i, _p_i, _p_d, _p_d, _c_int, _p_i, _c_int, _p_i,
                   _c_int, _p_i, _c_int, _c_int, _p_d]
@@ -113,6 +117,37 @@ def overlap(la, lb, A, B, za, ca, zb, cb, cartesian=True, quad=False) -> np.ndar
     _load(quad)["overlap"](la, lb, _dp(A), _dp(B), za.size, zb.size, _dp(za), _dp(ca), _dp(zb),
                            _dp(cb), int(cartesian), _dp(out))
     return out
+
+
+def kinetic(la, lb, A, B, za, ca, zb, cb, cartesian=True, quad=False) -> np.ndarray:
+    """-1/2 <a|nabla^2|b> of two contracted shells (Laplacian on the ket)."""
+    A = _f64(A); B = _f64(B)
+    za = _f64(np.atleast_1d(za)); ca = _f64(np.atleast_1d(ca))
+    zb = _f64(np.atleast_1d(zb)); cb = _f64(np.atleast_1d(cb))
+    na = (la + 1) * (la + 2) // 2 if cartesian else 2 * la + 1
+    nb = (lb + 1) * (lb + 2) // 2 if cartesian else 2 * lb + 1
+    out = np.zeros((na, nb))
+    _load(quad)["kinetic"](la, lb, _dp(A), _dp(B), za.size, zb.size, _dp(za), _dp(ca), _dp(zb),
+                           _dp(cb), int(cartesian), _dp(out))
+    return out
+
+
+def one_body(basis, pairs, cartesian: bool = False, quad: bool = False):
+    """Overlap and kinetic integrals of a batch of shell pairs (same class),
+    out[ij + npair*ab] with ab = a*nfunc(lb) + b (the library's layout)."""
+    pairs = np.asarray(pairs)
+    la, lb = int(basis.l[pairs[0, 0]]), int(basis.l[pairs[0, 1]])
+    na, nb = nfunc(la, cartesian), nfunc(lb, cartesian)
+    S = np.zeros((na * nb, len(pairs)))
+    T = np.zeros((na * nb, len(pairs)))
+    for ij, (a, b) in enumerate(pairs):
+        sa = slice(basis.poff[a], basis.poff[a] + basis.nprim[a])
+        sb = slice(basis.poff[b], basis.poff[b] + basis.nprim[b])
+        args = (la, lb, basis.xyz[a], basis.xyz[b], basis.exps[sa], basis.coefs[sa], basis.exps[sb],
+                basis.coefs[sb])
+        S[:, ij] = overlap(*args, cartesian=cartesian, quad=quad).reshape(-1)
+        T[:, ij] = kinetic(*args, cartesian=cartesian, quad=quad).reshape(-1)
+    return S.reshape(-1), T.reshape(-1)
 
 
 def nfunc(l: int, cartesian: bool) -> int:

@@ -92,6 +92,34 @@ class ClassRun:
         return self.out.view(nk, self.ncd, self.nab, nb).permute(3, 2, 1, 0)
 
 
+class OneBodyRun:
+    """Preallocated buffers for repeated mdx_one_body_batch calls on one class."""
+
+    def __init__(self, native, basis, pairs, ctx, torch):
+        self.native, self.ctx, self.torch = native, ctx, torch
+        self.sh = native.DeviceShells(basis)
+        self.pairs = native._pairs(pairs)
+        self.n = self.pairs.shape[0]
+        L = native.lib()
+        self.wsz = L.mdx_one_body_workspace_size(ctx.handle, ctypes.byref(self.sh.struct), self.n,
+                                                 native._i32p(self.pairs), 0)
+        if self.wsz == 0:
+            native.check(native.MDX_EINVAL, "workspace size")
+        self.ws = torch.empty(self.wsz // 8 + 64, dtype=torch.float64, device="cuda")
+        self.wsp = (self.ws.data_ptr() + 255) // 256 * 256
+        la, lb = int(basis.l[pairs[0, 0]]), int(basis.l[pairs[0, 1]])
+        self.nf = native.nfunc(la, False) * native.nfunc(lb, False)
+        self.S = torch.empty(self.n * self.nf, dtype=torch.float64, device="cuda")
+        self.T = torch.empty_like(self.S)
+
+    def __call__(self):
+        n = self.native
+        n.check(n.lib().mdx_one_body_batch(self.ctx.handle, ctypes.byref(self.sh.struct), self.n,
+                                           n._i32p(self.pairs), 0, ctypes.c_void_p(self.S.data_ptr()),
+                                           ctypes.c_void_p(self.T.data_ptr()), ctypes.c_void_p(self.wsp),
+                                           self.wsz, n._stream(self.torch)), "mdx_one_body_batch")
+
+
 class GradRun:
     """Preallocated buffers for repeated mdx_eri_grad_batch calls on one class."""
 
@@ -185,6 +213,7 @@ def extra_legs(native, ctx, torch, tune, reps):
         fl = kfl(r.batch) * r.n
         hl[name] = {"shellsets": r.n, "ms_per_call": ms, "kernel_ms": kms[0],
                     "shellsets_per_s": r.n / (ms * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
+                    "out_write_GB_per_s": r.out.numel() * 8 / (kms[0] * 1e-3) / 1e9,
                     "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": v,
                     "tuning_ms": vt}
         del r
@@ -198,6 +227,42 @@ def extra_legs(native, ctx, torch, tune, reps):
         sp[name] = {"shellsets": r.n, "us_per_call": ms * 1e3, "kernel_us": kms[0] * 1e3,
                     "shellsets_per_s": r.n / (ms * 1e-3)}
     out["sp_classes"] = sp
+
+    # the same classes at 4,096 x 4,096 pairs (16.8 M shellsets): these are
+    # bound by writing the output, so the evidence is HBM bandwidth
+    hb = {}
+    for name in W.C1_CLASSES:
+        r = ClassRun(native, W.config1(name, npair=4096, seed=0), ctx, torch)
+        ms, kms = measure(r, 1, 3, native, ctx, torch)
+        nbytes = r.out.numel() * 8
+        hb[name] = {"shellsets": r.n, "out_GB": nbytes / 1e9, "ms_per_call": ms, "kernel_ms": kms[0],
+                    "shellsets_per_s": r.n / (ms * 1e-3), "out_write_GB_per_s": nbytes / (kms[0] * 1e-3) / 1e9,
+                    "hbm_frac": nbytes / (kms[0] * 1e-3) / (PEAK_HBM_GBS * 1e9)}
+        del r
+        torch.cuda.empty_cache()
+    out["sp_hbm"] = hb
+    log("s/p HBM leg done")
+
+    # overlap + kinetic energy, spherical, K=3: 1024 x 1024 shell pairs per
+    # class.  ms_per_call includes the upload of the host pair list.
+    ob = {}
+    for la, lb in [(0, 0), (1, 1), (2, 1), (2, 2)]:
+        basis, pairs = W.one_body_pairs(la, lb, 1024, 1024, 3, seed=la * 3 + lb)
+        r = OneBodyRun(native, basis, pairs, ctx, torch)
+        ms, kms = measure(r, 1, 5, native, ctx, torch)
+        nbytes = 2 * r.n * r.nf * 8
+        fl = F.one_body_flops(la, lb, 3, 3) * r.n
+        ob["(%s|%s)" % ("spd"[la], "spd"[lb])] = {
+            "pairs": r.n, "ms_per_call": ms, "kernel_ms": kms[0], "pairs_per_s": r.n / (kms[0] * 1e-3),
+            "out_write_GB_per_s": nbytes / (kms[0] * 1e-3) / 1e9,
+            "hbm_frac": nbytes / (kms[0] * 1e-3) / (PEAK_HBM_GBS * 1e9),
+            "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
+            "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+            "flop_model": "flops.one_body_flops"}
+        del r
+        torch.cuda.empty_cache()
+    out["one_body"] = ob
+    log("one-body leg done")
     return out
 
 

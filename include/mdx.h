@@ -150,6 +150,29 @@ mdx_status mdx_eri_grad_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentr
                               mdx_stream_t stream);
 
 /*
+ * Overlap and kinetic-energy integrals of npair shell pairs of one class
+ * (pairs[2i] = a, pairs[2i+1] = b, the same (l_a, l_b) for all) -- the
+ * 1-particle integrals of Sec. 2.1: the 1-D overlaps of Eq. (8) from the E
+ * coefficients of Eqs. (10)-(11) and (14), and
+ *   T_ab = -1/2 <a| nabla^2 |b>
+ * from the same 1-D overlaps with the ket's exponent raised and lowered by 2.
+ * One shell pair per lane (the paper assigns one pair to one SIMD lane).
+ *   pairs HOST int32[2*npair].
+ *   S, T  DEVICE double, [ij, ab] column-major: S[ij + npair*ab], ab = a*nb + b,
+ *         nb = functions of shell b; either may be NULL (not computed).
+ *   ws    DEVICE, at least mdx_one_body_workspace_size bytes, 256-byte aligned.
+ *   flags MDX_SPHERICAL or MDX_CARTESIAN.
+ * Limits: l_a, l_b <= 2 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
+ * bad arguments, shell indices or mixed classes; MDX_EWORKSPACE for a short
+ * workspace; MDX_EDEVICE for a HIP error.  The size query returns 0 on any
+ * error (mdx_last_error says why).
+ */
+size_t mdx_one_body_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
+                                   int flags);
+mdx_status mdx_one_body_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
+                              int flags, double *S, double *T, void *ws, size_t ws_bytes, mdx_stream_t stream);
+
+/*
  * Schwarz factors Q_ij = sqrt(max_ab |(ab|ab)|) of npair shell pairs of one
  * class (pairs[2i], pairs[2i+1], same (l_a, l_b) for all), from the diagonal
  * 4-centre shellsets (ab|ab) computed by the integral kernels.  |(ab|cd)| <=

@@ -81,3 +81,16 @@ def grad_shellset_flops(la: int, lb: int, lc: int, ld: int, Ka: int = 1, Kb: int
         per_w = 2 * nh(lw - 1) * nw * nd
         total += Kd_ * Kw * per_q + Kd_ * per_d + Kw * per_w + 2 * nc(lw) * nw * nd
     return float(total)
+
+
+def one_body_flops(la: int, lb: int, Ka: int = 1, Kb: int = 1, cartesian: bool = False) -> float:
+    """Overlap + kinetic energy of one contracted shell pair (Sec. 2.1, Eq. (8)).
+    Per primitive pair: 40 for zeta_p, P, X_PA, X_PB and the prefactor; 5 per
+    1-D E coefficient E^{ij}_t (i <= l_a, j <= l_b + 2, t <= i + j) on 3 axes;
+    32 per Cartesian function pair (S product, three 1-D kinetic terms, T
+    combination, both accumulations).  Per pair: the factorised Cartesian-to-
+    solid transform of S and T."""
+    ne = sum(i + j + 1 for i in range(la + 1) for j in range(lb + 3)) - 1
+    prim = 40 + 3 * 5 * ne + 32 * nc(la) * nc(lb)
+    sph = 0 if cartesian else 2 * 2 * (nc(la) * nc(lb) * (2 * lb + 1) + (2 * lb + 1) * nc(la) * (2 * la + 1))
+    return Ka * Kb * prim + sph

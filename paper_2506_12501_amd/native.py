@@ -57,6 +57,9 @@ EXPORTS = {
                                                       _pi32, _i32, _pi32, ctypes.c_int]),
     "mdx_eri_grad_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32,
                                           _pi32, ctypes.c_int, _p, _p, _p, ctypes.c_size_t, _p]),
+    "mdx_one_body_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
+    "mdx_one_body_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int, _p, _p, _p,
+                                          ctypes.c_size_t, _p]),
     "mdx_schwarz_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
     "mdx_schwarz": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int, _p, _p,
                                    ctypes.c_size_t, _p]),
@@ -237,6 +240,41 @@ def eri_grad(shells: DeviceShells, ncentre: int, bra, ket, adjoint, cartesian: b
                                _i32p(ket), flags, _ptr(W), _ptr(grad), ctypes.c_void_p(aligned), wsz,
                                _stream(torch)), "mdx_eri_grad_batch")
     return grad.view(nket, 12, nbra).permute(2, 1, 0)
+
+
+def one_body(shells: DeviceShells, pairs, cartesian: bool = False, ctx: Context | None = None,
+             overlap: bool = True, kinetic: bool = True):
+    """Overlap and kinetic-energy integrals of a batch of shell pairs of one
+    class; returns (S, T), each a view of shape [npair, na, nb] over the
+    library's [ij, ab] column-major buffer (None for a matrix not asked for)."""
+    import torch
+    dev = shells.center.device
+    ctx = ctx or Context.get(dev.index or 0)
+    pairs = _pairs(pairs)
+    npair = pairs.shape[0]
+    flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
+    L = lib()
+    sp = ctypes.byref(shells.struct)
+    wsz = L.mdx_one_body_workspace_size(ctx.handle, sp, npair, _i32p(pairs), flags)
+    if wsz == 0:
+        check(L.mdx_one_body_batch(ctx.handle, sp, npair, _i32p(pairs), flags, None, None, None, 0,
+                                   _stream(torch)), "mdx_one_body_batch")
+    if npair:
+        la, lb = int(shells.l[pairs[0, 0]]), int(shells.l[pairs[0, 1]])
+        na, nb = nfunc(la, cartesian), nfunc(lb, cartesian)
+    else:
+        na = nb = 0
+    ws = torch.empty(wsz // 8 + 32, dtype=torch.float64, device=dev)
+    aligned = (_ptr(ws) + 255) // 256 * 256
+    S = torch.empty(npair * na * nb, dtype=torch.float64, device=dev) if overlap else None
+    T = torch.empty(npair * na * nb, dtype=torch.float64, device=dev) if kinetic else None
+    check(L.mdx_one_body_batch(ctx.handle, sp, npair, _i32p(pairs), flags, _ptr(S) if S is not None else None,
+                               _ptr(T) if T is not None else None, ctypes.c_void_p(aligned), wsz,
+                               _stream(torch)), "mdx_one_body_batch")
+
+    def view(x):
+        return None if x is None else x.view(na, nb, npair).permute(2, 0, 1)
+    return view(S), view(T)
 
 
 def schwarz(shells: DeviceShells, pairs, cartesian: bool = False, ctx: Context | None = None):

@@ -147,6 +147,20 @@ def make_class_batch(name: str, nbra: int, nket: int, K: int, box_A: float, zeta
     return ClassBatch(name, ncentre, sb.basis(), bra, ket)
 
 
+def one_body_pairs(la: int, lb: int, na: int, nb: int, K: int, seed: int = 0):
+    """Shell pairs for the overlap/kinetic batches: na shells of l_a and nb of
+    l_b, each with its own centre in a 10 A box, K exponents log-uniform in
+    [0.05, 50] and coefficients in [0.1, 1]; all na x nb pairs (a outer,
+    b inner).  Returns (basis, pairs [na*nb, 2])."""
+    rng = np.random.default_rng(seed)
+    sb = ShellBuilder()
+    box = 10.0 * ANGSTROM
+    A = [random_shell(rng, sb, la, K, box, 0.05, 50.0, 0.1, 1.0) for _ in range(na)]
+    B = [random_shell(rng, sb, lb, K, box, 0.05, 50.0, 0.1, 1.0) for _ in range(nb)]
+    pairs = np.stack(np.meshgrid(np.asarray(A, np.int32), np.asarray(B, np.int32), indexing="ij"), -1)
+    return sb.basis(), np.ascontiguousarray(pairs.reshape(-1, 2))
+
+
 # ---------------------------------------------------------------------------
 # The five measured configurations
 # ---------------------------------------------------------------------------

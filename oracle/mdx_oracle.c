@@ -20,6 +20,9 @@
  *   Eq. (25)         [p|q] = (-1)^{l_q} [p+q]^(0)
  *   Eqs. (32),(33)   ket transform, then bra transform (here with the plain
  *                    Cartesian E matrices in place of H)
+ *   Eqs. (24),(26),(30),(34)  1-particle Coulomb integrals of point charges,
+ *                    transformed charge by charge (no early summation)
+ *   Eq. (8)          overlap; kinetic energy from the same 1-D overlaps
  *   Eq. (5) / Sec. 2.1 text: primitives are accumulated into contracted ints
  *   Eqs. (18),(19)   Cartesian -> real solid harmonics, with the coefficient
  *                    C^a_{lm} built from the closed-form expansion of the
@@ -221,6 +224,47 @@ static void rints(int L, REAL p, REAL q, const REAL P[3], const REAL Q[3], REAL 
     }
     /* Eq. (31): raise one index at a time, level by level */
     for (int n = 1; n <= L; ++n)
+        for (int t = 0; t <= n; ++t)
+            for (int u = 0; u <= n - t; ++u) {
+                int v = n - t - u;
+                for (int m = 0; m <= L - n; ++m) {
+                    REAL val;
+                    if (t > 0)
+                        val = (t > 1 ? (t - 1) * RM(m + 1, t - 2, u, v) : 0) + X[0] * RM(m + 1, t - 1, u, v);
+                    else if (u > 0)
+                        val = (u > 1 ? (u - 1) * RM(m + 1, t, u - 2, v) : 0) + X[1] * RM(m + 1, t, u - 1, v);
+                    else
+                        val = (v > 1 ? (v - 1) * RM(m + 1, t, u, v - 2) : 0) + X[2] * RM(m + 1, t, u, v - 1);
+                    RM(m, t, u, v) = val;
+                }
+            }
+    memcpy(R0, Rm, cube * sizeof(REAL));
+#undef RM
+    free(Rm);
+}
+
+/* ------------------------------------------------------------------ */
+/* 1-particle Hermite auxiliary integrals of one point I, Eqs. (26),   */
+/* (30): [0]_I^(m) = (2 pi/p) (-2p)^m F_m(p |P-I|^2), then the same     */
+/* one-index raising as Eq. (31) with P - I in place of P - Q.          */
+/* R0[(t*(L+1)+u)*(L+1)+v] = [tuv]_I^(0), t+u+v <= L                    */
+/* ------------------------------------------------------------------ */
+static void rints_point(int L, REAL p, const REAL P[3], const REAL I[3], REAL *R0)
+{
+    int D = L + 1;
+    REAL X[3] = {P[0] - I[0], P[1] - I[1], P[2] - I[2]};
+    REAL T = p * (X[0] * X[0] + X[1] * X[1] + X[2] * X[2]);
+    REAL F[64];
+    boys_all(L, T, F);
+    size_t cube = (size_t)D * D * D;
+    REAL *Rm = (REAL *)calloc((size_t)D * cube, sizeof(REAL));
+#define RM(m, t, u, v) Rm[(size_t)(m) * cube + ((size_t)(t) * D + (u)) * D + (v)]
+    REAL fac = 2 * R_PI / p;
+    for (int m = 0; m <= L; ++m) {                 /* Eq. (26) */
+        RM(m, 0, 0, 0) = fac * F[m];
+        fac *= -2 * p;
+    }
+    for (int n = 1; n <= L; ++n)                    /* Eq. (30) */
         for (int t = 0; t <= n; ++t)
             for (int u = 0; u <= n - t; ++u) {
                 int v = n - t - u;
@@ -619,6 +663,62 @@ void EXPORT(kinetic)(int la, int lb, const double *A, const double *B, int Ka, i
             REAL s = 0;
             for (int i = 0; i < na; ++i)
                 for (int j = 0; j < nb; ++j) s += (REAL)Ca[m][i] * (REAL)Cb[n][j] * T[i * nb + j];
+            out[m * nsph(lb) + n] = (double)s;
+        }
+}
+
+/* Cartesian (or solid) 1-particle Coulomb integrals of two contracted
+ * shells in the field of ncharge point charges (charges[4I..4I+2] = position,
+ * charges[4I+3] = q_I):
+ *   V_ab = - sum_I q_I sum_p [p]_I^(0) H^p_ab                 Eqs. (24), (34)
+ * with H^p_ab = c_a c_b E^{ab}_p (Eqs. (10)-(11), (14)), evaluated charge by
+ * charge -- the order before the early summation of Eq. (37). */
+void EXPORT(nuclear)(int la, int lb, const double *A, const double *B, int Ka, int Kb,
+                     const double *za, const double *ca, const double *zb, const double *cb,
+                     int ncharge, const double *charges, int cartesian, double *out)
+{
+    int na = ncart(la), nb = ncart(lb), L = la + lb, D = L + 1;
+    int qa[OR_MAXCART][3], qb[OR_MAXCART][3];
+    cart_list(la, qa); cart_list(lb, qb);
+    REAL V[OR_MAXCART * OR_MAXCART];
+    REAL *R0 = (REAL *)malloc((size_t)D * D * D * sizeof(REAL));
+    for (int i = 0; i < na * nb; ++i) V[i] = 0;
+    for (int ka = 0; ka < Ka; ++ka)
+        for (int kb = 0; kb < Kb; ++kb) {
+            Etab E[3];
+            REAL a = za[ka], b = zb[kb], p = a + b, P[3];
+            for (int ax = 0; ax < 3; ++ax) {
+                ecoef(la, lb, a, b, A[ax], B[ax], E[ax]);
+                P[ax] = (a * (REAL)A[ax] + b * (REAL)B[ax]) / p;
+            }
+            REAL cc = (REAL)ca[ka] * (REAL)cb[kb];
+            for (int I = 0; I < ncharge; ++I) {
+                REAL C[3] = {charges[4 * I], charges[4 * I + 1], charges[4 * I + 2]};
+                rints_point(L, p, P, C, R0);
+                for (int i = 0; i < na; ++i)
+                    for (int j = 0; j < nb; ++j) {
+                        REAL s = 0;
+                        for (int t = 0; t <= qa[i][0] + qb[j][0]; ++t)
+                            for (int u = 0; u <= qa[i][1] + qb[j][1]; ++u)
+                                for (int v = 0; v <= qa[i][2] + qb[j][2]; ++v)
+                                    s += E[0][qa[i][0]][qb[j][0]][t] * E[1][qa[i][1]][qb[j][1]][u] *
+                                         E[2][qa[i][2]][qb[j][2]][v] * R0[((size_t)t * D + u) * D + v];
+                        V[i * nb + j] -= (REAL)charges[4 * I + 3] * cc * s;
+                    }
+            }
+        }
+    free(R0);
+    if (cartesian) {
+        for (int i = 0; i < na * nb; ++i) out[i] = (double)V[i];
+        return;
+    }
+    double Ca[2 * OR_LMAX + 1][OR_MAXCART], Cb[2 * OR_LMAX + 1][OR_MAXCART];
+    solid_coefs(la, Ca); solid_coefs(lb, Cb);
+    for (int m = 0; m < nsph(la); ++m)
+        for (int n = 0; n < nsph(lb); ++n) {
+            REAL s = 0;
+            for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) s += (REAL)Ca[m][i] * (REAL)Cb[n][j] * V[i * nb + j];
             out[m * nsph(lb) + n] = (double)s;
         }
 }

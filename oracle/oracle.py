@@ -59,6 +59,11 @@ def _load(quad: bool = False):
     f.argtypes = [_c_int, _c_int, _p_d, _p_d, _c_int, _c_int, _p_d, _p_d, _p_d, _p_d, _c_int, _p_d]
     f.restype = None
     fns["kinetic"] = f
+    f = getattr(lib, pre + "nuclear")
+    f.argtypes = [_c_int, _c_int, _p_d, _p_d, _c_int, _c_int, _p_d, _p_d, _p_d, _p_d, _c_int, _p_d, _c_int,
+                  _p_d]
+    f.restype = None
+    fns["nuclear"] = f
     f = getattr(lib, pre + "eri")
     f.argtypes = [_c_int, _c_int, _p_d, _p_i, _p_i, _p_i, _p_d, _p_d, _c_int, _p_i, _c_int, _p_i,
                   _c_int, _p_i, _c_int, _c_int, _p_d]
@@ -130,6 +135,36 @@ def kinetic(la, lb, A, B, za, ca, zb, cb, cartesian=True, quad=False) -> np.ndar
     _load(quad)["kinetic"](la, lb, _dp(A), _dp(B), za.size, zb.size, _dp(za), _dp(ca), _dp(zb),
                            _dp(cb), int(cartesian), _dp(out))
     return out
+
+
+def nuclear(la, lb, A, B, za, ca, zb, cb, charges, cartesian=True, quad=False) -> np.ndarray:
+    """-sum_I q_I <a| 1/|r - I| |b> of two contracted shells; charges [n, 4]
+    rows (x, y, z, q) -- Eqs. (24), (26), (30), (34), charge by charge."""
+    A = _f64(A); B = _f64(B)
+    za = _f64(np.atleast_1d(za)); ca = _f64(np.atleast_1d(ca))
+    zb = _f64(np.atleast_1d(zb)); cb = _f64(np.atleast_1d(cb))
+    ch = _f64(np.asarray(charges, dtype=np.float64).reshape(-1, 4))
+    na = (la + 1) * (la + 2) // 2 if cartesian else 2 * la + 1
+    nb = (lb + 1) * (lb + 2) // 2 if cartesian else 2 * lb + 1
+    out = np.zeros((na, nb))
+    _load(quad)["nuclear"](la, lb, _dp(A), _dp(B), za.size, zb.size, _dp(za), _dp(ca), _dp(zb), _dp(cb),
+                           ch.shape[0], _dp(ch), int(cartesian), _dp(out))
+    return out
+
+
+def nuclear_batch(basis, pairs, charges, cartesian: bool = False, quad: bool = False):
+    """1-particle Coulomb integrals of a batch of shell pairs (same class) in
+    the field of the point charges, out[ij + npair*ab] (the library's layout)."""
+    pairs = np.asarray(pairs)
+    la, lb = int(basis.l[pairs[0, 0]]), int(basis.l[pairs[0, 1]])
+    na, nb = nfunc(la, cartesian), nfunc(lb, cartesian)
+    V = np.zeros((na * nb, len(pairs)))
+    for ij, (a, b) in enumerate(pairs):
+        sa = slice(basis.poff[a], basis.poff[a] + basis.nprim[a])
+        sb = slice(basis.poff[b], basis.poff[b] + basis.nprim[b])
+        V[:, ij] = nuclear(la, lb, basis.xyz[a], basis.xyz[b], basis.exps[sa], basis.coefs[sa], basis.exps[sb],
+                           basis.coefs[sb], charges, cartesian=cartesian, quad=quad).reshape(-1)
+    return V.reshape(-1)
 
 
 def one_body(basis, pairs, cartesian: bool = False, quad: bool = False):

@@ -161,6 +161,16 @@ def one_body_pairs(la: int, lb: int, na: int, nb: int, K: int, seed: int = 0):
     return sb.basis(), np.ascontiguousarray(pairs.reshape(-1, 2))
 
 
+def point_charges(n: int = 100, box_A: float = 10.0, q_lo: float = 1.0, q_hi: float = 8.0, seed: int = 0):
+    """n point charges, positions uniform in a box_A Angstrom cube, charges
+    uniform in [q_lo, q_hi]: rows (x, y, z, q) in bohr, the layout the
+    1-particle Coulomb entry point takes."""
+    rng = np.random.default_rng(seed)
+    xyz = rng.uniform(0.0, box_A * ANGSTROM, (n, 3))
+    q = rng.uniform(q_lo, q_hi, n)
+    return np.ascontiguousarray(np.c_[xyz, q], dtype=np.float64)
+
+
 # ---------------------------------------------------------------------------
 # The five measured configurations
 # ---------------------------------------------------------------------------

@@ -69,3 +69,37 @@ def eri_prim_cart(la, lb, lc, ld, za, zb, zc, zd, A, B, C, D):
                         f = f * tabs[i][a[i], b[i], c[i], d[i]]
                     out[ia, ib, ic, id_] = 2.0 / math.sqrt(math.pi) * np.sum(wu * jac * f)
     return out
+
+
+def nuclear_prim_cart(la, lb, za, zb, A, B, C, nu=96):
+    """Primitive Cartesian <a| 1/|r - C| |b> (unnormalised monomials, no sign),
+    array [na, nb].  1/r = (2/sqrt(pi)) int_0^inf exp(-s^2 r^2) ds; for fixed s
+    each axis is a 1-D integral of a polynomial times exp(-za x_A^2 - zb x_B^2
+    - s^2 x_C^2), exact by Gauss-Hermite after completing the square.  The
+    s-integral uses Gauss-Legendre in u with s = sqrt(p) u / sqrt(1 - u^2)."""
+    y, w = _GH
+    p = za + zb
+    u, wu = np.polynomial.legendre.leggauss(nu)
+    u = 0.5 * (u + 1.0)
+    wu = 0.5 * wu
+    s2 = p * u * u / (1 - u * u)
+    jac = math.sqrt(p) * (1 - u * u) ** -1.5
+    tabs = []
+    for i in range(3):
+        t = np.zeros((la + 1, lb + 1, nu))
+        for k in range(nu):
+            e = p + s2[k]
+            M = (za * A[i] + zb * B[i] + s2[k] * C[i]) / e
+            const = math.exp(-(za * A[i] ** 2 + zb * B[i] ** 2 + s2[k] * C[i] ** 2 - e * M * M)) / math.sqrt(e)
+            x = M + y / math.sqrt(e)
+            for a in range(la + 1):
+                for b in range(lb + 1):
+                    t[a, b, k] = const * np.sum(w * (x - A[i]) ** a * (x - B[i]) ** b)
+        tabs.append(t)
+    ca, cb = cart_list(la), cart_list(lb)
+    out = np.zeros((len(ca), len(cb)))
+    for ia, a in enumerate(ca):
+        for ib, b in enumerate(cb):
+            f = tabs[0][a[0], b[0]] * tabs[1][a[1], b[1]] * tabs[2][a[2], b[2]]
+            out[ia, ib] = 2.0 / math.sqrt(math.pi) * np.sum(wu * jac * f)
+    return out

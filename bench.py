@@ -120,6 +120,23 @@ class OneBodyRun:
                                            self.wsz, n._stream(self.torch)), "mdx_one_body_batch")
 
 
+class NuclearRun(OneBodyRun):
+    """Preallocated buffers for repeated mdx_nuclear_batch calls on one class."""
+
+    def __init__(self, native, basis, pairs, charges, ctx, torch):
+        super().__init__(native, basis, pairs, ctx, torch)
+        self.charges = torch.as_tensor(charges, device="cuda")
+        self.nch = int(self.charges.shape[0])
+        del self.T
+
+    def __call__(self):
+        n = self.native
+        n.check(n.lib().mdx_nuclear_batch(self.ctx.handle, ctypes.byref(self.sh.struct), self.n,
+                                          n._i32p(self.pairs), self.nch, ctypes.c_void_p(self.charges.data_ptr()),
+                                          0, ctypes.c_void_p(self.S.data_ptr()), ctypes.c_void_p(self.wsp),
+                                          self.wsz, n._stream(self.torch)), "mdx_nuclear_batch")
+
+
 class GradRun:
     """Preallocated buffers for repeated mdx_eri_grad_batch calls on one class."""
 
@@ -263,6 +280,26 @@ def extra_legs(native, ctx, torch, tune, reps):
         torch.cuda.empty_cache()
     out["one_body"] = ob
     log("one-body leg done")
+
+    # 1-particle Coulomb integrals of 100 point charges (the paper's Table 2
+    # setting), early summation over charges; 256 x 256 = 65,536 pairs per
+    # class, K = 1 and K = 5
+    nu = {}
+    charges = W.point_charges(100, 10.0, seed=0)
+    for K in (1, 5):
+        for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]:
+            basis, pairs = W.one_body_pairs(la, lb, 256, 256, K, seed=10 * K + la * 3 + lb)
+            r = NuclearRun(native, basis, pairs, charges, ctx, torch)
+            ms, kms = measure(r, 1, 5, native, ctx, torch)
+            fl = F.nuclear_flops(la, lb, K, K, 100) * r.n
+            nu["(%s|%s) K=%d" % ("spd"[la], "spd"[lb], K)] = {
+                "pairs": r.n, "charges": 100, "ms_per_call": ms, "kernel_ms": kms[0],
+                "pairs_per_s": r.n / (kms[0] * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
+                "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                "flop_model": "flops.nuclear_flops"}
+            del r
+    out["nuclear"] = nu
+    log("nuclear-attraction leg done")
     return out
 
 

@@ -173,6 +173,30 @@ mdx_status mdx_one_body_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t np
                               int flags, double *S, double *T, void *ws, size_t ws_bytes, mdx_stream_t stream);
 
 /*
+ * 1-particle Coulomb (nuclear attraction) integrals of npair shell pairs of
+ * one class in the field of ncharge point charges,
+ *   V_ab = - sum_I q_I <a| 1/|r - I| |b>        (Eqs. (24), (26), (30), (34))
+ * with the sum over charges taken before the Hermite-to-AO transform
+ * (Eq. (37), Sec. 2.2.4): per primitive pair the kernel sums the charges'
+ * Hermite integrals [r]_I^(0), then transforms that sum once.
+ *   pairs   HOST int32[2*npair], as mdx_one_body_batch.
+ *   charges DEVICE double[4*ncharge]: x, y, z (bohr), q of charge I at
+ *           charges[4I .. 4I+3].  ncharge = 0 gives V = 0.
+ *   V       DEVICE double, [ij, ab] column-major: V[ij + npair*ab].
+ *   ws      DEVICE, at least mdx_nuclear_workspace_size bytes, 256-byte aligned.
+ *   flags   MDX_SPHERICAL or MDX_CARTESIAN.
+ * Limits: l_a, l_b <= 2 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
+ * bad arguments, shell indices, mixed classes, a negative charge count or a
+ * null charge array with ncharge > 0; MDX_EWORKSPACE for a short workspace;
+ * MDX_EDEVICE for a HIP error.  The size query returns 0 on any error.
+ */
+size_t mdx_nuclear_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
+                                  int flags);
+mdx_status mdx_nuclear_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
+                             int32_t ncharge, const double *charges, int flags, double *V, void *ws,
+                             size_t ws_bytes, mdx_stream_t stream);
+
+/*
  * Schwarz factors Q_ij = sqrt(max_ab |(ab|ab)|) of npair shell pairs of one
  * class (pairs[2i], pairs[2i+1], same (l_a, l_b) for all), from the diagonal
  * 4-centre shellsets (ab|ab) computed by the integral kernels.  |(ab|cd)| <=

@@ -12,6 +12,14 @@
 //   S_ab = sum_prims c_a c_b s_x s_y s_z,  T_ab = sum_prims c_a c_b (t_x s_y s_z + s_x t_y s_z + s_x s_y t_z),
 // and transforms both to real solid harmonics (Eq. (18)) unless Cartesian
 // components were asked for.
+//
+// The 1-particle Coulomb integrals of a set of point charges take the
+// Hermite route of Eqs. (24), (26), (30), (34), with the sum over charges
+// moved in front of the Hermite-to-AO transform (Eq. (37)): per primitive
+// pair the lane accumulates sum_I q_I [r]_I^(0) over all charges -- Boys
+// function and recursion per charge -- and only then contracts that one set
+// of Hermite integrals with the pair's E coefficients.
+#include "eri_common.h"
 #include "runtime.h"
 
 namespace mdx {
@@ -36,14 +44,11 @@ __host__ __device__ constexpr int cart_exp(int l, int idx, int axis)
     return axis == 0 ? x : (axis == 1 ? y : z);
 }
 
-// E^{ij}_0 for i <= LA, j <= LBP along one axis, Eqs. (10)-(11), with
-// E^{00}_0 = 1 (the Gaussian factor is applied by the caller)
-template <int LA, int LBP>
-__device__ __forceinline__ void e0_axis(double p, double XPA, double XPB, double (&E0)[LA + 1][LBP + 1])
+// E^{ij}_t for i <= LA, j <= LB, 0 <= t <= i + j along one axis, Eqs.
+// (10)-(11), with E^{00}_0 = 1 (the Gaussian factor is applied by the caller)
+template <int LA, int LB>
+__device__ __forceinline__ void e_axis(double i2p, double XPA, double XPB, double (&E)[LA + 1][LB + 1][LA + LB + 1])
 {
-    constexpr int TM = LA + LBP + 1;
-    const double i2p = 0.5 / p;
-    double E[LA + 1][LBP + 1][TM];
     auto get = [&](int i, int j, int t) -> double { return (t < 0 || t > i + j) ? 0.0 : E[i][j][t]; };
 #pragma unroll
     for (int i = 0; i <= LA; ++i) {
@@ -55,12 +60,58 @@ __device__ __forceinline__ void e0_axis(double p, double XPA, double XPB, double
                 E[i][0][t] = i2p * get(i - 1, 0, t - 1) + XPA * get(i - 1, 0, t) + (t + 1) * get(i - 1, 0, t + 1);
         }
 #pragma unroll
-        for (int j = 1; j <= LBP; ++j)
+        for (int j = 1; j <= LB; ++j)
 #pragma unroll
             for (int t = 0; t <= i + j; ++t)
                 E[i][j][t] = i2p * get(i, j - 1, t - 1) + XPB * get(i, j - 1, t) + (t + 1) * get(i, j - 1, t + 1);
+    }
+}
+
+// the t = 0 column of e_axis (the 1-D overlaps of Eq. (8) up to (pi/p)^{1/2})
+template <int LA, int LBP>
+__device__ __forceinline__ void e0_axis(double p, double XPA, double XPB, double (&E0)[LA + 1][LBP + 1])
+{
+    double E[LA + 1][LBP + 1][LA + LBP + 1];
+    e_axis<LA, LBP>(0.5 / p, XPA, XPB, E);
+#pragma unroll
+    for (int i = 0; i <= LA; ++i)
 #pragma unroll
         for (int j = 0; j <= LBP; ++j) E0[i][j] = E[i][j][0];
+}
+
+// Cartesian values X[NA][NB] of one lane -> out[ij + npair*ab], solid
+// (Eq. (18), factorised: ket index first) unless CART
+template <int LA, int LB, bool CART>
+__device__ __forceinline__ void store_pair(const double (&X)[ncart(LA)][ncart(LB)], const double *Ca,
+                                           const double *Cb, double *out, int ij, int npair)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB);
+    if constexpr (CART) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) out[ij + (int64_t)npair * (i * NB + j)] = X[i][j];
+    } else {
+        constexpr int MA = 2 * LA + 1, MB = 2 * LB + 1;
+        double U[NA][MB];
+#pragma unroll
+        for (int i = 0; i < NA; ++i)
+#pragma unroll
+            for (int n = 0; n < MB; ++n) {
+                double u = 0.0;
+#pragma unroll
+                for (int j = 0; j < NB; ++j) u = fma(Cb[n * NB + j], X[i][j], u);
+                U[i][n] = u;
+            }
+#pragma unroll
+        for (int m = 0; m < MA; ++m)
+#pragma unroll
+            for (int n = 0; n < MB; ++n) {
+                double v = 0.0;
+#pragma unroll
+                for (int i = 0; i < NA; ++i) v = fma(Ca[m * NA + i], U[i][n], v);
+                out[ij + (int64_t)npair * (m * MB + n)] = v;
+            }
     }
 }
 
@@ -111,40 +162,99 @@ __global__ void __launch_bounds__(64) onebody_kernel(OneBodyArgs a)
                 }
         }
     }
-    if constexpr (CART) {
+    if (a.S) store_pair<LA, LB, CART>(S, a.Ca, a.Cb, a.S, ij, a.npair);
+    if (a.T) store_pair<LA, LB, CART>(T, a.Ca, a.Cb, a.T, ij, a.npair);
+}
+
+struct NuclearArgs {
+    const PairRec *pairs;
+    int npair;
+    const double *center, *expo, *coef;
+    const double *charges;   // [4*ncharge]: x, y, z, q
+    int ncharge;
+    const double *boys;
+    const double *Ca, *Cb;
+    double *V;               // [ij + npair*ab]
+};
+
+template <int LA, int LB, bool CART>
+__global__ void __launch_bounds__(64) nuclear_kernel(NuclearArgs a)
+{
+    const int ij = blockIdx.x * 64 + (int)threadIdx.x;
+    if (ij >= a.npair) return;
+    constexpr int L = LA + LB, NH = nherm(L), NA = ncart(LA), NB = ncart(LB);
+    const PairRec pr = a.pairs[ij];
+    const double A[3] = {a.center[3 * pr.sa], a.center[3 * pr.sa + 1], a.center[3 * pr.sa + 2]};
+    const double B[3] = {a.center[3 * pr.sb], a.center[3 * pr.sb + 1], a.center[3 * pr.sb + 2]};
+    const double AB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+    double V[NA][NB];
 #pragma unroll
-        for (int i = 0; i < NA; ++i)
+    for (int i = 0; i < NA; ++i)
 #pragma unroll
-            for (int j = 0; j < NB; ++j) {
-                const int64_t o = ij + (int64_t)a.npair * (i * NB + j);
-                if (a.S) a.S[o] = S[i][j];
-                if (a.T) a.T[o] = T[i][j];
-            }
-    } else {
-        constexpr int MA = 2 * LA + 1, MB = 2 * LB + 1;
+        for (int j = 0; j < NB; ++j) V[i][j] = 0.0;
+
+    for (int ka = 0; ka < pr.ka; ++ka) {
+        const double za = a.expo[pr.offa + ka], ca = a.coef[pr.offa + ka];
+        for (int kb = 0; kb < pr.kb; ++kb) {
+            const double zb = a.expo[pr.offb + kb], cb = a.coef[pr.offb + kb];
+            const double p = za + zb, rp = 1.0 / p;
+            const double P[3] = {(za * A[0] + zb * B[0]) * rp, (za * A[1] + zb * B[1]) * rp,
+                                 (za * A[2] + zb * B[2]) * rp};
+            // sum_I q_I [r]_I^(0), Eqs. (26), (30), summed before any transform (Eq. (37))
+            double Rs[NH];
 #pragma unroll
-        for (int m = 0; m < MA; ++m)
+            for (int k = 0; k < NH; ++k) Rs[k] = 0.0;
+            const double g = 2.0 * M_PI * rp, m2p = -2.0 * p;
+            for (int I = 0; I < a.ncharge; ++I) {
+                const double *c = a.charges + 4 * I;   // the same charge in every lane
+                const double X = P[0] - c[0], Y = P[1] - c[1], Z = P[2] - c[2];
+                double F[L + 1];
+                boys_eval<L>(p * (X * X + Y * Y + Z * Z), F, a.boys);
+                double S[L + 1];
+                double f = c[3] * g;
 #pragma unroll
-            for (int n = 0; n < MB; ++n) {
-                double vs = 0.0, vt = 0.0;
-#pragma unroll
-                for (int i = 0; i < NA; ++i) {
-                    double us = 0.0, ut = 0.0;
-#pragma unroll
-                    for (int j = 0; j < NB; ++j) {
-                        const double cbj = a.Cb[n * NB + j];
-                        us = fma(cbj, S[i][j], us);
-                        ut = fma(cbj, T[i][j], ut);
-                    }
-                    const double cai = a.Ca[m * NA + i];
-                    vs = fma(cai, us, vs);
-                    vt = fma(cai, ut, vt);
+                for (int m = 0; m <= L; ++m) {
+                    S[m] = f * F[m];
+                    f *= m2p;
                 }
-                const int64_t o = ij + (int64_t)a.npair * (m * MB + n);
-                if (a.S) a.S[o] = vs;
-                if (a.T) a.T[o] = vt;
+                double R[(L + 1) * NH];
+                r_recursion<L>(S, X, Y, Z, R);
+#pragma unroll
+                for (int k = 0; k < NH; ++k) Rs[k] += R[k];
             }
+            // E coefficients of the pair and the bra transform, Eq. (34)
+            double E[3][LA + 1][LB + 1][L + 1];
+#pragma unroll
+            for (int ax = 0; ax < 3; ++ax) e_axis<LA, LB>(0.5 * rp, P[ax] - A[ax], P[ax] - B[ax], E[ax]);
+            const double f = -ca * cb * exp(-za * zb * rp * AB2);
+#pragma unroll
+            for (int i = 0; i < NA; ++i)
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                    const int ix = cart_exp(LA, i, 0), iy = cart_exp(LA, i, 1), iz = cart_exp(LA, i, 2);
+                    const int jx = cart_exp(LB, j, 0), jy = cart_exp(LB, j, 1), jz = cart_exp(LB, j, 2);
+                    double s = 0.0;
+#pragma unroll
+                    for (int t = 0; t <= ix + jx; ++t)
+#pragma unroll
+                        for (int u = 0; u <= iy + jy; ++u) {
+                            const double etu = E[0][ix][jx][t] * E[1][iy][jy][u];
+#pragma unroll
+                            for (int v = 0; v <= iz + jz; ++v) s = fma(etu * E[2][iz][jz][v], Rs[herm_index(t, u, v)], s);
+                        }
+                    V[i][j] = fma(f, s, V[i][j]);
+                }
+        }
     }
+    store_pair<LA, LB, CART>(V, a.Ca, a.Cb, a.V, ij, a.npair);
+}
+
+template <int LA, int LB>
+static void launch_nuclear(const NuclearArgs &a, bool cart, hipStream_t s)
+{
+    const int nblk = (a.npair + 63) / 64;
+    if (cart) hipLaunchKernelGGL((nuclear_kernel<LA, LB, true>), dim3(nblk), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((nuclear_kernel<LA, LB, false>), dim3(nblk), dim3(64), 0, s, a);
 }
 
 template <int LA, int LB>
@@ -193,16 +303,15 @@ extern "C" size_t mdx_one_body_workspace_size(mdx_ctx *c, const mdx_shells *sh, 
     return al256((size_t)npair * sizeof(PairRec)) + 256;
 }
 
-extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
-                                         int flags, double *S, double *T, void *ws, size_t ws_bytes,
-                                         mdx_stream_t stream)
+// the lane records of a validated batch, uploaded to the head of ws; then
+// the profiling hook's opening event.  *ev1 is the event to record after the
+// launch (null without the hook).
+static mdx_status stage_pairs(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, void *ws,
+                              size_t ws_bytes, hipStream_t s, const char *who, hipEvent_t *ev1)
 {
-    int l[2];
-    mdx_status st = check_pairs(c, sh, npair, pairs, flags, l);
-    if (st != MDX_OK) return st;
-    if (npair == 0 || (!S && !T)) return MDX_OK;
-    if (!ws) return fail(MDX_EINVAL, "mdx_one_body_batch: null workspace");
-    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_one_body_batch: workspace not 256-byte aligned");
+    *ev1 = nullptr;
+    if (!ws) return fail(MDX_EINVAL, "%s: null workspace", who);
+    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "%s: workspace not 256-byte aligned", who);
     const size_t need = al256((size_t)npair * sizeof(PairRec));
     if (ws_bytes < need) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
     std::vector<PairRec> pr((size_t)npair);
@@ -211,9 +320,41 @@ extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32
         pr[i] = PairRec{sa, sb, sh->nprim[sa], sh->nprim[sb], sh->prim_offset[sa], sh->prim_offset[sb]};
     }
     HIP_TRY2(hipSetDevice(c->device));
-    hipStream_t s = (hipStream_t)stream;
     HIP_TRY2(hipMemcpyAsync(ws, pr.data(), pr.size() * sizeof(PairRec), hipMemcpyHostToDevice, s));
-    const bool cart = (flags & MDX_CARTESIAN) != 0;
+    if (c->prof_events.size() >= 2) {   // profiling hook, as for the other integral kernels
+        const size_t np = c->prof_events.size() / 2, i = c->prof_count++ % np;
+        *ev1 = c->prof_events[2 * i + 1];
+        HIP_TRY2(hipEventRecord(c->prof_events[2 * i], s));
+    }
+    return MDX_OK;
+}
+
+// one case per (l_a, l_b), l <= 2
+#define MDX_ONEBODY_SWITCH(LAUNCH, la, lb, ...)          \
+    switch ((la) * 3 + (lb)) {                           \
+    case 0: LAUNCH<0, 0>(__VA_ARGS__); break;            \
+    case 1: LAUNCH<0, 1>(__VA_ARGS__); break;            \
+    case 2: LAUNCH<0, 2>(__VA_ARGS__); break;            \
+    case 3: LAUNCH<1, 0>(__VA_ARGS__); break;            \
+    case 4: LAUNCH<1, 1>(__VA_ARGS__); break;            \
+    case 5: LAUNCH<1, 2>(__VA_ARGS__); break;            \
+    case 6: LAUNCH<2, 0>(__VA_ARGS__); break;            \
+    case 7: LAUNCH<2, 1>(__VA_ARGS__); break;            \
+    default: LAUNCH<2, 2>(__VA_ARGS__); break;           \
+    }
+
+extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
+                                         int flags, double *S, double *T, void *ws, size_t ws_bytes,
+                                         mdx_stream_t stream)
+{
+    int l[2];
+    mdx_status st = check_pairs(c, sh, npair, pairs, flags, l);
+    if (st != MDX_OK) return st;
+    if (npair == 0 || (!S && !T)) return MDX_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev1;
+    st = stage_pairs(c, sh, npair, pairs, ws, ws_bytes, s, "mdx_one_body_batch", &ev1);
+    if (st != MDX_OK) return st;
     OneBodyArgs a{};
     a.pairs = (const PairRec *)ws;
     a.npair = npair;
@@ -224,23 +365,46 @@ extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32
     a.Cb = c->solid + c->solid_off[l[1]];
     a.S = S;
     a.T = T;
-    hipEvent_t ev1 = nullptr;
-    if (c->prof_events.size() >= 2) {   // profiling hook, as for the other integral kernels
-        const size_t np = c->prof_events.size() / 2, i = c->prof_count++ % np;
-        ev1 = c->prof_events[2 * i + 1];
-        HIP_TRY2(hipEventRecord(c->prof_events[2 * i], s));
-    }
-    switch (l[0] * 3 + l[1]) {
-    case 0: launch_onebody<0, 0>(a, cart, s); break;
-    case 1: launch_onebody<0, 1>(a, cart, s); break;
-    case 2: launch_onebody<0, 2>(a, cart, s); break;
-    case 3: launch_onebody<1, 0>(a, cart, s); break;
-    case 4: launch_onebody<1, 1>(a, cart, s); break;
-    case 5: launch_onebody<1, 2>(a, cart, s); break;
-    case 6: launch_onebody<2, 0>(a, cart, s); break;
-    case 7: launch_onebody<2, 1>(a, cart, s); break;
-    default: launch_onebody<2, 2>(a, cart, s); break;
-    }
+    MDX_ONEBODY_SWITCH(launch_onebody, l[0], l[1], a, (flags & MDX_CARTESIAN) != 0, s)
+    HIP_TRY2(hipGetLastError());
+    if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
+    return MDX_OK;
+}
+
+extern "C" size_t mdx_nuclear_workspace_size(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
+                                             int flags)
+{
+    return mdx_one_body_workspace_size(c, sh, npair, pairs, flags);
+}
+
+extern "C" mdx_status mdx_nuclear_batch(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
+                                        int32_t ncharge, const double *charges, int flags, double *V, void *ws,
+                                        size_t ws_bytes, mdx_stream_t stream)
+{
+    int l[2];
+    mdx_status st = check_pairs(c, sh, npair, pairs, flags, l);
+    if (st != MDX_OK) return st;
+    if (ncharge < 0) return fail(MDX_EINVAL, "negative charge count");
+    if (ncharge > 0 && !charges) return fail(MDX_EINVAL, "null charge array");
+    if (npair == 0) return MDX_OK;
+    if (!V) return fail(MDX_EINVAL, "mdx_nuclear_batch: null output");
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t ev1;
+    st = stage_pairs(c, sh, npair, pairs, ws, ws_bytes, s, "mdx_nuclear_batch", &ev1);
+    if (st != MDX_OK) return st;
+    NuclearArgs a{};
+    a.pairs = (const PairRec *)ws;
+    a.npair = npair;
+    a.center = sh->center;
+    a.expo = sh->exponent;
+    a.coef = sh->coef;
+    a.charges = charges;
+    a.ncharge = ncharge;
+    a.boys = c->boys;
+    a.Ca = c->solid + c->solid_off[l[0]];
+    a.Cb = c->solid + c->solid_off[l[1]];
+    a.V = V;
+    MDX_ONEBODY_SWITCH(launch_nuclear, l[0], l[1], a, (flags & MDX_CARTESIAN) != 0, s)
     HIP_TRY2(hipGetLastError());
     if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
     return MDX_OK;

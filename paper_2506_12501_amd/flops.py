@@ -94,3 +94,25 @@ def one_body_flops(la: int, lb: int, Ka: int = 1, Kb: int = 1, cartesian: bool =
     prim = 40 + 3 * 5 * ne + 32 * nc(la) * nc(lb)
     sph = 0 if cartesian else 2 * 2 * (nc(la) * nc(lb) * (2 * lb + 1) + (2 * lb + 1) * nc(la) * (2 * la + 1))
     return Ka * Kb * prim + sph
+
+
+def nuclear_flops(la: int, lb: int, Ka: int = 1, Kb: int = 1, ncharge: int = 100,
+                  cartesian: bool = False) -> float:
+    """1-particle Coulomb integrals of one contracted shell pair with early
+    summation over ncharge point charges (Eqs. (26), (30), (34), (37)).
+    Per primitive pair and charge: 8 (P - I, T), B(L) for the Boys function,
+    2 (L+1) for [0]_I^(m), R(L) for the recursion, N_H(L) to accumulate.
+    Per primitive pair: 40 setup, 5 per 1-D E coefficient on 3 axes, and per
+    Cartesian function pair 3 per Hermite term (t, u, v) plus 2.  Per pair:
+    the factorised solid transform."""
+    L = la + lb
+    B = 20 + 3 * (L + 1)
+    R = 3 * sum(nh(j) - 1 for j in range(1, L + 1))
+    per_charge = 8 + B + 2 * (L + 1) + R + nh(L)
+    ne = sum(i + j + 1 for i in range(la + 1) for j in range(lb + 1)) - 1
+    ca = [(la - s, s - v, v) for s in range(la + 1) for v in range(s + 1)]
+    cb = [(lb - s, s - v, v) for s in range(lb + 1) for v in range(s + 1)]
+    terms = sum((a[0] + b[0] + 1) * (a[1] + b[1] + 1) * (a[2] + b[2] + 1) for a in ca for b in cb)
+    prim = ncharge * per_charge + 40 + 15 * ne + 3 * terms + 2 * nc(la) * nc(lb)
+    sph = 0 if cartesian else 2 * (nc(la) * nc(lb) * (2 * lb + 1) + (2 * lb + 1) * nc(la) * (2 * la + 1))
+    return Ka * Kb * prim + sph

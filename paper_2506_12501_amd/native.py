@@ -60,6 +60,9 @@ EXPORTS = {
     "mdx_one_body_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
     "mdx_one_body_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int, _p, _p, _p,
                                           ctypes.c_size_t, _p]),
+    "mdx_nuclear_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
+    "mdx_nuclear_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, _i32, _p, ctypes.c_int, _p,
+                                         _p, ctypes.c_size_t, _p]),
     "mdx_schwarz_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
     "mdx_schwarz": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int, _p, _p,
                                    ctypes.c_size_t, _p]),
@@ -275,6 +278,37 @@ def one_body(shells: DeviceShells, pairs, cartesian: bool = False, ctx: Context 
     def view(x):
         return None if x is None else x.view(na, nb, npair).permute(2, 0, 1)
     return view(S), view(T)
+
+
+def nuclear(shells: DeviceShells, pairs, charges, cartesian: bool = False, ctx: Context | None = None):
+    """1-particle Coulomb integrals of a batch of shell pairs of one class in
+    the field of point charges (a [n, 4] device tensor of x, y, z, q rows);
+    returns a view of shape [npair, na, nb] over the library's [ij, ab]
+    column-major buffer."""
+    import torch
+    dev = shells.center.device
+    ctx = ctx or Context.get(dev.index or 0)
+    pairs = _pairs(pairs)
+    npair = pairs.shape[0]
+    charges = charges.reshape(-1, 4).contiguous()
+    flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
+    L = lib()
+    sp = ctypes.byref(shells.struct)
+    wsz = L.mdx_nuclear_workspace_size(ctx.handle, sp, npair, _i32p(pairs), flags)
+    if wsz == 0:
+        check(L.mdx_nuclear_batch(ctx.handle, sp, npair, _i32p(pairs), charges.shape[0], _ptr(charges), flags,
+                                  None, None, 0, _stream(torch)), "mdx_nuclear_batch")
+    if npair:
+        na = nfunc(int(shells.l[pairs[0, 0]]), cartesian)
+        nb = nfunc(int(shells.l[pairs[0, 1]]), cartesian)
+    else:
+        na = nb = 0
+    ws = torch.empty(wsz // 8 + 32, dtype=torch.float64, device=dev)
+    aligned = (_ptr(ws) + 255) // 256 * 256
+    V = torch.empty(npair * na * nb, dtype=torch.float64, device=dev)
+    check(L.mdx_nuclear_batch(ctx.handle, sp, npair, _i32p(pairs), charges.shape[0], _ptr(charges), flags,
+                              _ptr(V), ctypes.c_void_p(aligned), wsz, _stream(torch)), "mdx_nuclear_batch")
+    return V.view(na, nb, npair).permute(2, 0, 1)
 
 
 def schwarz(shells: DeviceShells, pairs, cartesian: bool = False, ctx: Context | None = None):

@@ -191,7 +191,10 @@ def measure(fn, nlaunch, reps, native, ctx, torch):
     return t0.elapsed_time(t1) / reps, [sum(ks[j::nlaunch]) / reps for j in range(nlaunch)]
 
 
-def extra_legs(native, ctx, torch, tune, reps):
+EXTRA_LEGS = ("gradient", "high_l", "sp_classes", "sp_hbm", "one_body", "nuclear")
+
+
+def extra_legs(native, ctx, torch, tune, reps, legs=EXTRA_LEGS):
     """The other measured workloads (not part of the headline step)."""
     from paper_2506_12501_amd import autotune, flops as F, workloads as W
     out = {}
@@ -202,104 +205,111 @@ def extra_legs(native, ctx, torch, tune, reps):
               int(batch.basis.nprim[batch.ket[0, 0]]), int(batch.basis.nprim[batch.ket[0, 1]]) if ld >= 0 else 1]
         return (F.grad_shellset_flops if grad else F.shellset_flops)(la, lb, lc, ld, *Ks)
 
-    # backward kernel: (dd|dd) K=3, 256 x 256 pairs, adjoint N(0,1) seed 1
-    g = GradRun(native, W.config2("(dd|dd)"), ctx, torch, seed=1)
-    variant, vt = None, None
-    if tune:
-        variant, vt = autotune.tune(ctx, g.sh, 4, g.bra, g.ket, g, reps=2, cache=False, gradient=True)
-    ms, kms = measure(g, 2, reps, native, ctx, torch)
-    fl = kfl(g.batch, grad=True) * g.n
-    log("gradient leg done")
-    out["gradient"] = {
-        "workload": "(dd|dd) backward, K=3, 256x256 pairs (65,536 shellsets), adjoint N(0,1) seed 1, "
-                    "12 centre derivatives per shellset",
-        "ms_per_call": ms, "shellsets_per_s": g.n / (ms * 1e-3), "kernel_ms_per_pass": kms,
-        "algorithmic_gflop": fl / 1e9, "kernel_tflops": fl / (sum(kms) * 1e-3) / 1e12,
-        "pct_fp64_peak": 100 * fl / (sum(kms) * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": variant,
-        "tuning_ms": vt, "flop_model": "flops.grad_shellset_flops"}
-    del g
-
-    # high-L primitive classes: (ff|ff), (gg|gg) 128 x 128; (X|dd) 256 x 256
-    hl = {}
-    for name in W.C4_CLASSES_4C + W.C4_CLASSES_3C:
-        r = ClassRun(native, W.config4(name, seed=0), ctx, torch)
-        v, vt = None, None
+    if "gradient" in legs:
+        # backward kernel: (dd|dd) K=3, 256 x 256 pairs, adjoint N(0,1) seed 1
+        g = GradRun(native, W.config2("(dd|dd)"), ctx, torch, seed=1)
+        variant, vt = None, None
         if tune:
-            v, vt = autotune.tune(ctx, r.sh, r.batch.ncentre, r.bra, r.ket, r, reps=2, cache=False)
-        ms, kms = measure(r, 1, reps, native, ctx, torch)
-        fl = kfl(r.batch) * r.n
-        hl[name] = {"shellsets": r.n, "ms_per_call": ms, "kernel_ms": kms[0],
-                    "shellsets_per_s": r.n / (ms * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
-                    "out_write_GB_per_s": r.out.numel() * 8 / (kms[0] * 1e-3) / 1e9,
-                    "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": v,
-                    "tuning_ms": vt}
-        del r
-    out["high_l"] = hl
+            variant, vt = autotune.tune(ctx, g.sh, 4, g.bra, g.ket, g, reps=2, cache=False, gradient=True)
+        ms, kms = measure(g, 2, reps, native, ctx, torch)
+        fl = kfl(g.batch, grad=True) * g.n
+        log("gradient leg done")
+        out["gradient"] = {
+            "workload": "(dd|dd) backward, K=3, 256x256 pairs (65,536 shellsets), adjoint N(0,1) seed 1, "
+                        "12 centre derivatives per shellset",
+            "ms_per_call": ms, "shellsets_per_s": g.n / (ms * 1e-3), "kernel_ms_per_pass": kms,
+            "algorithmic_gflop": fl / 1e9, "kernel_tflops": fl / (sum(kms) * 1e-3) / 1e12,
+            "pct_fp64_peak": 100 * fl / (sum(kms) * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": variant,
+            "tuning_ms": vt, "flop_model": "flops.grad_shellset_flops"}
+        del g
 
-    # plain s/p primitive classes: 16 x 16 pairs (256 shellsets) per class
-    sp = {}
-    for name in W.C1_CLASSES:
-        r = ClassRun(native, W.config1(name, seed=0), ctx, torch)
-        ms, kms = measure(r, 1, max(reps, 20), native, ctx, torch)
-        sp[name] = {"shellsets": r.n, "us_per_call": ms * 1e3, "kernel_us": kms[0] * 1e3,
-                    "shellsets_per_s": r.n / (ms * 1e-3)}
-    out["sp_classes"] = sp
-
-    # the same classes at 4,096 x 4,096 pairs (16.8 M shellsets): these are
-    # bound by writing the output, so the evidence is HBM bandwidth
-    hb = {}
-    for name in W.C1_CLASSES:
-        r = ClassRun(native, W.config1(name, npair=4096, seed=0), ctx, torch)
-        ms, kms = measure(r, 1, 3, native, ctx, torch)
-        nbytes = r.out.numel() * 8
-        hb[name] = {"shellsets": r.n, "out_GB": nbytes / 1e9, "ms_per_call": ms, "kernel_ms": kms[0],
-                    "shellsets_per_s": r.n / (ms * 1e-3), "out_write_GB_per_s": nbytes / (kms[0] * 1e-3) / 1e9,
-                    "hbm_frac": nbytes / (kms[0] * 1e-3) / (PEAK_HBM_GBS * 1e9)}
-        del r
-        torch.cuda.empty_cache()
-    out["sp_hbm"] = hb
-    log("s/p HBM leg done")
-
-    # overlap + kinetic energy, spherical, K=3: 1024 x 1024 shell pairs per
-    # class.  ms_per_call includes the upload of the host pair list.
-    ob = {}
-    for la, lb in [(0, 0), (1, 1), (2, 1), (2, 2)]:
-        basis, pairs = W.one_body_pairs(la, lb, 1024, 1024, 3, seed=la * 3 + lb)
-        r = OneBodyRun(native, basis, pairs, ctx, torch)
-        ms, kms = measure(r, 1, 5, native, ctx, torch)
-        nbytes = 2 * r.n * r.nf * 8
-        fl = F.one_body_flops(la, lb, 3, 3) * r.n
-        ob["(%s|%s)" % ("spd"[la], "spd"[lb])] = {
-            "pairs": r.n, "ms_per_call": ms, "kernel_ms": kms[0], "pairs_per_s": r.n / (kms[0] * 1e-3),
-            "out_write_GB_per_s": nbytes / (kms[0] * 1e-3) / 1e9,
-            "hbm_frac": nbytes / (kms[0] * 1e-3) / (PEAK_HBM_GBS * 1e9),
-            "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
-            "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
-            "flop_model": "flops.one_body_flops"}
-        del r
-        torch.cuda.empty_cache()
-    out["one_body"] = ob
-    log("one-body leg done")
-
-    # 1-particle Coulomb integrals of 100 point charges (the paper's Table 2
-    # setting), early summation over charges; 256 x 256 = 65,536 pairs per
-    # class, K = 1 and K = 5
-    nu = {}
-    charges = W.point_charges(100, 10.0, seed=0)
-    for K in (1, 5):
-        for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]:
-            basis, pairs = W.one_body_pairs(la, lb, 256, 256, K, seed=10 * K + la * 3 + lb)
-            r = NuclearRun(native, basis, pairs, charges, ctx, torch)
-            ms, kms = measure(r, 1, 5, native, ctx, torch)
-            fl = F.nuclear_flops(la, lb, K, K, 100) * r.n
-            nu["(%s|%s) K=%d" % ("spd"[la], "spd"[lb], K)] = {
-                "pairs": r.n, "charges": 100, "ms_per_call": ms, "kernel_ms": kms[0],
-                "pairs_per_s": r.n / (kms[0] * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
-                "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
-                "flop_model": "flops.nuclear_flops"}
+    if "high_l" in legs:
+        # high-L primitive classes: (ff|ff), (gg|gg) 128 x 128; (X|dd) 256 x 256
+        hl = {}
+        for name in W.C4_CLASSES_4C + W.C4_CLASSES_3C:
+            r = ClassRun(native, W.config4(name, seed=0), ctx, torch)
+            v, vt = None, None
+            if tune:
+                v, vt = autotune.tune(ctx, r.sh, r.batch.ncentre, r.bra, r.ket, r, reps=2, cache=False)
+            ms, kms = measure(r, 1, reps, native, ctx, torch)
+            fl = kfl(r.batch) * r.n
+            hl[name] = {"shellsets": r.n, "ms_per_call": ms, "kernel_ms": kms[0],
+                        "shellsets_per_s": r.n / (ms * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
+                        "out_write_GB_per_s": r.out.numel() * 8 / (kms[0] * 1e-3) / 1e9,
+                        "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, "variant": v,
+                        "tuning_ms": vt}
             del r
-    out["nuclear"] = nu
-    log("nuclear-attraction leg done")
+        out["high_l"] = hl
+
+    if "sp_classes" in legs:
+        # plain s/p primitive classes: 16 x 16 pairs (256 shellsets) per class
+        sp = {}
+        for name in W.C1_CLASSES:
+            r = ClassRun(native, W.config1(name, seed=0), ctx, torch)
+            ms, kms = measure(r, 1, max(reps, 20), native, ctx, torch)
+            sp[name] = {"shellsets": r.n, "us_per_call": ms * 1e3, "kernel_us": kms[0] * 1e3,
+                        "shellsets_per_s": r.n / (ms * 1e-3)}
+        out["sp_classes"] = sp
+
+    if "sp_hbm" in legs:
+        # the same classes at 4,096 x 4,096 pairs (16.8 M shellsets): these are
+        # bound by writing the output, so the evidence is HBM bandwidth
+        hb = {}
+        for name in W.C1_CLASSES:
+            r = ClassRun(native, W.config1(name, npair=4096, seed=0), ctx, torch)
+            ms, kms = measure(r, 1, 3, native, ctx, torch)
+            nbytes = r.out.numel() * 8
+            hb[name] = {"shellsets": r.n, "out_GB": nbytes / 1e9, "ms_per_call": ms, "kernel_ms": kms[0],
+                        "shellsets_per_s": r.n / (ms * 1e-3), "out_write_GB_per_s": nbytes / (kms[0] * 1e-3) / 1e9,
+                        "hbm_frac": nbytes / (kms[0] * 1e-3) / (PEAK_HBM_GBS * 1e9)}
+            del r
+            torch.cuda.empty_cache()
+        out["sp_hbm"] = hb
+        log("s/p HBM leg done")
+
+    if "one_body" in legs:
+        # overlap + kinetic energy, spherical, K=3: 1024 x 1024 shell pairs per
+        # class.  ms_per_call includes the upload of the host pair list.
+        ob = {}
+        for la, lb in [(0, 0), (1, 1), (2, 1), (2, 2)]:
+            basis, pairs = W.one_body_pairs(la, lb, 1024, 1024, 3, seed=la * 3 + lb)
+            r = OneBodyRun(native, basis, pairs, ctx, torch)
+            ms, kms = measure(r, 1, 5, native, ctx, torch)
+            nbytes = 2 * r.n * r.nf * 8
+            fl = F.one_body_flops(la, lb, 3, 3) * r.n
+            ob["(%s|%s)" % ("spd"[la], "spd"[lb])] = {
+                "pairs": r.n, "ms_per_call": ms, "kernel_ms": kms[0], "pairs_per_s": r.n / (kms[0] * 1e-3),
+                "out_write_GB_per_s": nbytes / (kms[0] * 1e-3) / 1e9,
+                "hbm_frac": nbytes / (kms[0] * 1e-3) / (PEAK_HBM_GBS * 1e9),
+                "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
+                "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                "flop_model": "flops.one_body_flops"}
+            del r
+            torch.cuda.empty_cache()
+        out["one_body"] = ob
+        log("one-body leg done")
+
+    if "nuclear" in legs:
+        # 1-particle Coulomb integrals of 100 point charges (the paper's Table 2
+        # setting), early summation over charges; 256 x 256 = 65,536 pairs per
+        # class, K = 1 and K = 5
+        nu = {}
+        charges = W.point_charges(100, 10.0, seed=0)
+        for K in (1, 5):
+            for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2)]:
+                basis, pairs = W.one_body_pairs(la, lb, 256, 256, K, seed=10 * K + la * 3 + lb)
+                r = NuclearRun(native, basis, pairs, charges, ctx, torch)
+                ms, kms = measure(r, 1, 5, native, ctx, torch)
+                fl = F.nuclear_flops(la, lb, K, K, 100) * r.n
+                nu["(%s|%s) K=%d" % ("spd"[la], "spd"[lb], K)] = {
+                    "pairs": r.n, "charges": 100, "ms_per_call": ms, "kernel_ms": kms[0],
+                    "pairs_per_s": r.n / (kms[0] * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
+                    "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
+                    "flop_model": "flops.nuclear_flops"}
+                del r
+        out["nuclear"] = nu
+        log("nuclear-attraction leg done")
+
     return out
 
 
@@ -493,6 +503,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=224)
     ap.add_argument("--no-extras", action="store_true", help="skip the gradient / high-L / s-p legs")
     ap.add_argument("--extra-reps", type=int, default=5)
+    ap.add_argument("--extras", default=",".join(EXTRA_LEGS),
+                    help="comma-separated extra legs to run (default: all of %s)" % ", ".join(EXTRA_LEGS))
     ap.add_argument("--no-cluster", action="store_true", help="skip the mixed-L cluster leg")
     ap.add_argument("--cluster-sample", type=int, default=48)
     ap.add_argument("--no-cpu", action="store_true")
@@ -587,7 +599,7 @@ def main():
 
     extras = None
     if not args.no_extras:
-        extras = extra_legs(native, ctx, torch, not args.no_tune, args.extra_reps)
+        extras = extra_legs(native, ctx, torch, not args.no_tune, args.extra_reps, args.extras.split(","))
         log("extra legs done")
     cluster = None
     if not args.no_cluster:

@@ -177,84 +177,166 @@ struct NuclearArgs {
     double *V;               // [ij + npair*ab]
 };
 
-template <int LA, int LB, bool CART>
-__global__ void __launch_bounds__(64) nuclear_kernel(NuclearArgs a)
+// F_m(x), m <= M: the evaluation of boys_eval (Taylor series about the
+// nearest 1/8 node, then downward recursion; asymptotic form for x >= 45)
+// with the node rows of order M .. M + BOYS_NTERM - 1 held in LDS,
+// rows[k * BOYS_NTERM + i].  Lanes of a wave read unrelated rows; from LDS
+// those gathers cost a few cycles instead of a trip through the vector cache.
+template <int M>
+__device__ __forceinline__ void boys_eval_rows(double x, double *__restrict__ F, const double *__restrict__ rows)
 {
-    const int ij = blockIdx.x * 64 + (int)threadIdx.x;
-    if (ij >= a.npair) return;
-    constexpr int L = LA + LB, NH = nherm(L), NA = ncart(LA), NB = ncart(LB);
-    const PairRec pr = a.pairs[ij];
-    const double A[3] = {a.center[3 * pr.sa], a.center[3 * pr.sa + 1], a.center[3 * pr.sa + 2]};
-    const double B[3] = {a.center[3 * pr.sb], a.center[3 * pr.sb + 1], a.center[3 * pr.sb + 2]};
-    const double AB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+    if (x < (double)BOYS_XMAX) {
+        const int k = __double2int_rn(x * (double)BOYS_STEP_INV);
+        const double d = (double)k * (1.0 / BOYS_STEP_INV) - x;
+        const double *row = rows + k * BOYS_NTERM;
+        double f = row[BOYS_NTERM - 1];
+#pragma unroll
+        for (int i = BOYS_NTERM - 2; i >= 0; --i) f = fma(f, d * (1.0 / (i + 1)), row[i]);
+        F[M] = f;
+        const double e = exp(-x);
+        const double x2 = x + x;
+#pragma unroll
+        for (int m = M - 1; m >= 0; --m) F[m] = fma(x2, F[m + 1], e) * (1.0 / (2 * m + 1));
+    } else {
+        const double rx = 1.0 / x;
+        F[0] = sqrt(0.78539816339744830962 * rx);
+        if (M > 0) {
+            const double e = exp(-x);
+            const double hrx = 0.5 * rx;
+#pragma unroll
+            for (int m = 0; m < M; ++m) F[m + 1] = fma((double)(2 * m + 1), F[m], -e) * hrx;
+        }
+    }
+}
+
+// A workgroup takes 64 shell pairs (one per lane) and G waves: wave w sums
+// the charges I = w, w + G, ... and transforms its partial Hermite sums itself
+// (the transform is linear); the partial integrals are added across waves
+// through LDS at the end.  Splitting the charges gives a batch of 65,536
+// pairs G waves per SIMD instead of one, at the price of G transforms per
+// primitive pair -- worth it where registers leave room for more waves
+// (measured: 4 waves up to L = 2, 2 for L = 3; (d|d) needs 256 VGPRs and
+// runs best with one).  LT: Boys rows staged in LDS (else read from the
+// global table; LDS was faster for every class).
+template <int LA, int LB>
+constexpr int nuclear_waves() { return LA + LB <= 2 ? 4 : (LA + LB == 3 ? 2 : 1); }
+template <int LA, int LB>
+constexpr bool nuclear_lds_rows() { return true; }
+
+template <int LA, int LB, bool CART, int G, bool LT>
+__global__ void __launch_bounds__(64 * G) nuclear_kernel(NuclearArgs a)
+{
+    constexpr int L = LA + LB, NH = nherm(L), NA = ncart(LA), NB = ncart(LB), NF = NA * NB;
+    constexpr int NROWT = BOYS_NROW * BOYS_NTERM;
+    constexpr int NLDS = LT ? NROWT : (G > 1 ? 64 * (G - 1) * (NF < 18 ? NF : 18) : 1);
+    __shared__ double lds[NLDS];   // Boys rows of order L; after the charge loop, the partial sums
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if constexpr (LT) {
+        for (int i = threadIdx.x; i < NROWT; i += 64 * G)
+            lds[i] = a.boys[(i / BOYS_NTERM) * BOYS_NCOL + L + i % BOYS_NTERM];
+        __syncthreads();
+    }
+
+    const int ij = blockIdx.x * 64 + lane;
     double V[NA][NB];
 #pragma unroll
     for (int i = 0; i < NA; ++i)
 #pragma unroll
         for (int j = 0; j < NB; ++j) V[i][j] = 0.0;
-
-    for (int ka = 0; ka < pr.ka; ++ka) {
-        const double za = a.expo[pr.offa + ka], ca = a.coef[pr.offa + ka];
-        for (int kb = 0; kb < pr.kb; ++kb) {
-            const double zb = a.expo[pr.offb + kb], cb = a.coef[pr.offb + kb];
-            const double p = za + zb, rp = 1.0 / p;
-            const double P[3] = {(za * A[0] + zb * B[0]) * rp, (za * A[1] + zb * B[1]) * rp,
-                                 (za * A[2] + zb * B[2]) * rp};
-            // sum_I q_I [r]_I^(0), Eqs. (26), (30), summed before any transform (Eq. (37))
-            double Rs[NH];
+    if (ij < a.npair) {
+        const PairRec pr = a.pairs[ij];
+        const double A[3] = {a.center[3 * pr.sa], a.center[3 * pr.sa + 1], a.center[3 * pr.sa + 2]};
+        const double B[3] = {a.center[3 * pr.sb], a.center[3 * pr.sb + 1], a.center[3 * pr.sb + 2]};
+        const double AB2 =
+            (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+        for (int ka = 0; ka < pr.ka; ++ka) {
+            const double za = a.expo[pr.offa + ka], ca = a.coef[pr.offa + ka];
+            for (int kb = 0; kb < pr.kb; ++kb) {
+                const double zb = a.expo[pr.offb + kb], cb = a.coef[pr.offb + kb];
+                const double p = za + zb, rp = 1.0 / p;
+                const double P[3] = {(za * A[0] + zb * B[0]) * rp, (za * A[1] + zb * B[1]) * rp,
+                                     (za * A[2] + zb * B[2]) * rp};
+                // sum_I q_I [r]_I^(0) over this wave's charges, Eqs. (26), (30),
+                // before any transform (Eq. (37))
+                double Rs[NH];
 #pragma unroll
-            for (int k = 0; k < NH; ++k) Rs[k] = 0.0;
-            const double g = 2.0 * M_PI * rp, m2p = -2.0 * p;
-            for (int I = 0; I < a.ncharge; ++I) {
-                const double *c = a.charges + 4 * I;   // the same charge in every lane
-                const double X = P[0] - c[0], Y = P[1] - c[1], Z = P[2] - c[2];
-                double F[L + 1];
-                boys_eval<L>(p * (X * X + Y * Y + Z * Z), F, a.boys);
-                double S[L + 1];
-                double f = c[3] * g;
+                for (int k = 0; k < NH; ++k) Rs[k] = 0.0;
+                const double g = 2.0 * M_PI * rp, m2p = -2.0 * p;
+                for (int I = w; I < a.ncharge; I += G) {
+                    const double *c = a.charges + 4 * I;   // the same charge in every lane of the wave
+                    const double X = P[0] - c[0], Y = P[1] - c[1], Z = P[2] - c[2];
+                    double F[L + 1];
+                    if constexpr (LT) boys_eval_rows<L>(p * (X * X + Y * Y + Z * Z), F, lds);
+                    else boys_eval<L>(p * (X * X + Y * Y + Z * Z), F, a.boys);
+                    double S[L + 1];
+                    double f = c[3] * g;
 #pragma unroll
-                for (int m = 0; m <= L; ++m) {
-                    S[m] = f * F[m];
-                    f *= m2p;
+                    for (int m = 0; m <= L; ++m) {
+                        S[m] = f * F[m];
+                        f *= m2p;
+                    }
+                    double R[(L + 1) * NH];
+                    r_recursion<L>(S, X, Y, Z, R);
+#pragma unroll
+                    for (int k = 0; k < NH; ++k) Rs[k] += R[k];
                 }
-                double R[(L + 1) * NH];
-                r_recursion<L>(S, X, Y, Z, R);
+                // E coefficients of the pair and the bra transform, Eq. (34)
+                double E[3][LA + 1][LB + 1][L + 1];
 #pragma unroll
-                for (int k = 0; k < NH; ++k) Rs[k] += R[k];
+                for (int ax = 0; ax < 3; ++ax) e_axis<LA, LB>(0.5 * rp, P[ax] - A[ax], P[ax] - B[ax], E[ax]);
+                const double f = -ca * cb * exp(-za * zb * rp * AB2);
+#pragma unroll
+                for (int i = 0; i < NA; ++i)
+#pragma unroll
+                    for (int j = 0; j < NB; ++j) {
+                        const int ix = cart_exp(LA, i, 0), iy = cart_exp(LA, i, 1), iz = cart_exp(LA, i, 2);
+                        const int jx = cart_exp(LB, j, 0), jy = cart_exp(LB, j, 1), jz = cart_exp(LB, j, 2);
+                        double s = 0.0;
+#pragma unroll
+                        for (int t = 0; t <= ix + jx; ++t)
+#pragma unroll
+                            for (int u = 0; u <= iy + jy; ++u) {
+                                const double etu = E[0][ix][jx][t] * E[1][iy][jy][u];
+#pragma unroll
+                                for (int v = 0; v <= iz + jz; ++v)
+                                    s = fma(etu * E[2][iz][jz][v], Rs[herm_index(t, u, v)], s);
+                            }
+                        V[i][j] = fma(f, s, V[i][j]);
+                    }
             }
-            // E coefficients of the pair and the bra transform, Eq. (34)
-            double E[3][LA + 1][LB + 1][L + 1];
-#pragma unroll
-            for (int ax = 0; ax < 3; ++ax) e_axis<LA, LB>(0.5 * rp, P[ax] - A[ax], P[ax] - B[ax], E[ax]);
-            const double f = -ca * cb * exp(-za * zb * rp * AB2);
-#pragma unroll
-            for (int i = 0; i < NA; ++i)
-#pragma unroll
-                for (int j = 0; j < NB; ++j) {
-                    const int ix = cart_exp(LA, i, 0), iy = cart_exp(LA, i, 1), iz = cart_exp(LA, i, 2);
-                    const int jx = cart_exp(LB, j, 0), jy = cart_exp(LB, j, 1), jz = cart_exp(LB, j, 2);
-                    double s = 0.0;
-#pragma unroll
-                    for (int t = 0; t <= ix + jx; ++t)
-#pragma unroll
-                        for (int u = 0; u <= iy + jy; ++u) {
-                            const double etu = E[0][ix][jx][t] * E[1][iy][jy][u];
-#pragma unroll
-                            for (int v = 0; v <= iz + jz; ++v) s = fma(etu * E[2][iz][jz][v], Rs[herm_index(t, u, v)], s);
-                        }
-                    V[i][j] = fma(f, s, V[i][j]);
-                }
         }
     }
-    store_pair<LA, LB, CART>(V, a.Ca, a.Cb, a.V, ij, a.npair);
+    // add the waves' partial integrals, CH function pairs at a time
+    if constexpr (G > 1) {
+    constexpr int CH = NLDS / (64 * (G - 1)) < NF ? NLDS / (64 * (G - 1)) : NF;
+    __syncthreads();   // every wave is past its charge loop: the rows are free
+#pragma unroll
+    for (int c0 = 0; c0 < NF; c0 += CH) {
+        if (w > 0) {
+#pragma unroll
+            for (int k = c0; k < c0 + CH && k < NF; ++k) lds[((w - 1) * CH + k - c0) * 64 + lane] = V[k / NB][k % NB];
+        }
+        __syncthreads();
+        if (w == 0) {
+#pragma unroll
+            for (int k = c0; k < c0 + CH && k < NF; ++k)
+#pragma unroll
+                for (int v = 0; v < G - 1; ++v) V[k / NB][k % NB] += lds[(v * CH + k - c0) * 64 + lane];
+        }
+        __syncthreads();
+    }
+    }
+    if (w == 0 && ij < a.npair) store_pair<LA, LB, CART>(V, a.Ca, a.Cb, a.V, ij, a.npair);
 }
 
 template <int LA, int LB>
 static void launch_nuclear(const NuclearArgs &a, bool cart, hipStream_t s)
 {
+    constexpr int G = nuclear_waves<LA, LB>();
+    constexpr bool LT = nuclear_lds_rows<LA, LB>();
     const int nblk = (a.npair + 63) / 64;
-    if (cart) hipLaunchKernelGGL((nuclear_kernel<LA, LB, true>), dim3(nblk), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((nuclear_kernel<LA, LB, false>), dim3(nblk), dim3(64), 0, s, a);
+    if (cart) hipLaunchKernelGGL((nuclear_kernel<LA, LB, true, G, LT>), dim3(nblk), dim3(64 * G), 0, s, a);
+    else hipLaunchKernelGGL((nuclear_kernel<LA, LB, false, G, LT>), dim3(nblk), dim3(64 * G), 0, s, a);
 }
 
 template <int LA, int LB>

@@ -167,6 +167,20 @@ def nuclear_batch(basis, pairs, charges, cartesian: bool = False, quad: bool = F
     return V.reshape(-1)
 
 
+def digest(basis, ncentre: int, bra, ket, Dbra, Dket, cartesian: bool = False, quad: bool = False):
+    """Contraction of a dense batch with pair-blocked densities (the "consume"
+    use of the integrals, Sec. 3.1):
+        Jbra[ij, ab] = sum_{kl, cd} (ab|cd)_{ij,kl} Dket[kl, cd]
+        Jket[kl, cd] = sum_{ij, ab} (ab|cd)_{ij,kl} Dbra[ij, ab]
+    Dbra [nbra, nab], Dket [nket, ncd] (row = pair); returns (Jbra, Jket) in
+    the same shapes.  The integrals are this module's eri(); the contraction
+    is a plain tensor sum."""
+    I = eri(basis, ncentre, bra, ket, cartesian=cartesian, quad=quad)   # [nbra, nab, ncd, nket]
+    Jbra = np.einsum("iack,kc->ia", I, np.asarray(Dket, dtype=np.float64))
+    Jket = np.einsum("iack,ia->kc", I, np.asarray(Dbra, dtype=np.float64))
+    return Jbra, Jket
+
+
 def one_body(basis, pairs, cartesian: bool = False, quad: bool = False):
     """Overlap and kinetic integrals of a batch of shell pairs (same class),
     out[ij + npair*ab] with ab = a*nfunc(lb) + b (the library's layout)."""

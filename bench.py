@@ -120,6 +120,30 @@ class OneBodyRun:
                                            self.wsz, n._stream(self.torch)), "mdx_one_body_batch")
 
 
+class DigestRun(ClassRun):
+    """Preallocated densities and J blocks for repeated mdx_eri_digest_batch
+    calls on one class (both sides contracted)."""
+
+    def __init__(self, native, batch, ctx, torch, seed=2):
+        super().__init__(native, batch, ctx, torch)
+        del self.out
+        g = torch.Generator(device="cuda").manual_seed(seed)
+        nb, nk = self.bra.shape[0], self.ket.shape[0]
+        self.Db = torch.randn(nb * self.nab, dtype=torch.float64, device="cuda", generator=g)
+        self.Dk = torch.randn(nk * self.ncd, dtype=torch.float64, device="cuda", generator=g)
+        self.Jb = torch.zeros(nb * self.nab, dtype=torch.float64, device="cuda")
+        self.Jk = torch.zeros(nk * self.ncd, dtype=torch.float64, device="cuda")
+
+    def __call__(self):
+        n = self.native
+        p = lambda t: ctypes.c_void_p(t.data_ptr())
+        n.check(n.lib().mdx_eri_digest_batch(self.ctx.handle, ctypes.byref(self.sh.struct), self.batch.ncentre,
+                                             self.bra.shape[0], n._i32p(self.bra), self.ket.shape[0],
+                                             n._i32p(self.ket), 0, p(self.Db), p(self.Dk), p(self.Jb), p(self.Jk),
+                                             ctypes.c_void_p(self.wsp), self.wsz, n._stream(self.torch)),
+                "mdx_eri_digest_batch")
+
+
 class NuclearRun(OneBodyRun):
     """Preallocated buffers for repeated mdx_nuclear_batch calls on one class."""
 
@@ -191,7 +215,7 @@ def measure(fn, nlaunch, reps, native, ctx, torch):
     return t0.elapsed_time(t1) / reps, [sum(ks[j::nlaunch]) / reps for j in range(nlaunch)]
 
 
-EXTRA_LEGS = ("gradient", "high_l", "sp_classes", "sp_hbm", "one_body", "nuclear")
+EXTRA_LEGS = ("gradient", "high_l", "sp_classes", "sp_hbm", "digest", "one_body", "nuclear")
 
 
 def extra_legs(native, ctx, torch, tune, reps, legs=EXTRA_LEGS):
@@ -266,6 +290,29 @@ def extra_legs(native, ctx, torch, tune, reps, legs=EXTRA_LEGS):
             torch.cuda.empty_cache()
         out["sp_hbm"] = hb
         log("s/p HBM leg done")
+
+    if "digest" in legs:
+        # the same batches contracted with densities in the kernels (Jbra and
+        # Jket) instead of storing the integrals: the s/p classes at 4,096 x
+        # 4,096 pairs and the two contracted d classes of the headline step
+        dg = {}
+        cases = [(name, W.config1(name, npair=4096, seed=0)) for name in W.C1_CLASSES] + \
+                [(name + " K=3", W.config2(name, seed=0)) for name in W.C2_CLASSES]
+        for key, b in cases:
+            r = DigestRun(native, b, ctx, torch)
+            ms, kms = measure(r, 1, 3, native, ctx, torch)
+            nbytes = r.n * r.nab * r.ncd * 8
+            ent = {"shellsets": r.n, "ms_per_call": ms, "kernel_ms": kms[0],
+                   "shellsets_per_s": r.n / (kms[0] * 1e-3),
+                   "output_GB_not_written": nbytes / 1e9}
+            if key in out.get("sp_hbm", {}):
+                ent["store_kernel_ms"] = out["sp_hbm"][key]["kernel_ms"]
+                ent["speedup_vs_store"] = ent["store_kernel_ms"] / kms[0]
+            dg[key] = ent
+            del r
+            torch.cuda.empty_cache()
+        out["digest"] = dg
+        log("digest leg done")
 
     if "one_body" in legs:
         # overlap + kinetic energy, spherical, K=3: 1024 x 1024 shell pairs per

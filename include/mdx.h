@@ -129,6 +129,32 @@ mdx_status mdx_eri_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, in
                          double *out, void *ws, size_t ws_bytes, mdx_stream_t stream);
 
 /*
+ * The "consume" use of a dense batch (Sec. 3.1: integrals feed a contraction
+ * and need not be stored): the batch of mdx_eri_batch contracted with
+ * pair-blocked densities inside the integral kernels, so the integrals never
+ * reach memory:
+ *   Jbra[ij + nbra*ab] += sum_{kl,cd} (ab|cd)_{ij,kl} Dket[kl + nket*cd]
+ *   Jket[kl + nket*cd] += sum_{ij,ab} (ab|cd)_{ij,kl} Dbra[ij + nbra*ab]
+ * With bra and ket drawn from one list of canonical pairs these are the
+ * Coulomb-matrix blocks J_ab = sum_cd (ab|cd) D_cd of the two pair sets; the
+ * caller gathers D into pair blocks and scatters J back, with its own
+ * symmetry factors.
+ *   Dbra, Dket DEVICE double[nbra*nab], [nket*ncd] (read)
+ *   Jbra, Jket DEVICE double, same shapes, ACCUMULATED (the caller zeroes
+ *              them); either may be NULL (not computed), and then its
+ *              density may be NULL too.  Accumulation uses atomic adds: the
+ *              order of the sums, and so the last bits, vary between calls.
+ * Same other arguments, limits and workspace (mdx_eri_workspace_size) as
+ * mdx_eri_batch.  Classes whose default kernel is a single-primitive or
+ * 3-centre matrix-core variant run on the general matrix-core kernel.
+ * Errors as mdx_eri_batch; MDX_EINVAL also for a J without its density.
+ */
+mdx_status mdx_eri_digest_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
+                                const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
+                                const double *Dbra, const double *Dket, double *Jbra, double *Jket,
+                                void *ws, size_t ws_bytes, mdx_stream_t stream);
+
+/*
  * Centre derivatives contracted with an adjoint (backward pass of
  * mdx_eri_batch; the paper has no derivatives -- they follow from
  * differentiating Eq. (1): d/dA_i phi_a = 2 zeta_a phi_{a+1_i} - a_i phi_{a-1_i}).

@@ -380,7 +380,7 @@ mdx_status launch_class(mdx_ctx *c, const ClassPlan &cp, const EriArgs &a, int n
 }
 
 mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
-                         double *out, hipStream_t s, bool upload)
+                         double *out, hipStream_t s, bool upload, const Digest *dig)
 {
     const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
     if (nb == 0 || nk == 0) return MDX_OK;
@@ -392,6 +392,7 @@ mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, 
     EriArgs a;
     int nblocks = 0;
     if ((st = class_args(c, cp, d, out, a, nblocks)) != MDX_OK) return st;
+    if (dig) a.dig = *dig;
     return launch_class(c, cp, a, nblocks, s);
 }
 
@@ -423,4 +424,40 @@ extern "C" mdx_status mdx_eri_batch(mdx_ctx *c, const mdx_shells *sh, int ncentr
     if (ws_bytes < L.total) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, L.total);
     HIP_TRY2(hipSetDevice(c->device));
     return enqueue_class(c, sh, cp, L, (char *)ws, out, (hipStream_t)stream, true);
+}
+
+extern "C" mdx_status mdx_eri_digest_batch(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra,
+                                           const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
+                                           const double *Dbra, const double *Dket, double *Jbra, double *Jket,
+                                           void *ws, size_t ws_bytes, mdx_stream_t stream)
+{
+    if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_digest_batch: MDX_FUSED applies to plans only");
+    ClassPlan cp;
+    mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp);
+    if (st != MDX_OK) return st;
+    if (Jbra && !Dket) return fail(MDX_EINVAL, "mdx_eri_digest_batch: Jbra needs Dket");
+    if (Jket && !Dbra) return fail(MDX_EINVAL, "mdx_eri_digest_batch: Jket needs Dbra");
+    if (nbra == 0 || nket == 0 || (!Jbra && !Jket)) return MDX_OK;
+    if (!ws) return fail(MDX_EINVAL, "mdx_eri_digest_batch: null workspace");
+    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_eri_digest_batch: workspace not 256-byte aligned");
+    // digestion is compiled for the first shape of the general matrix-core
+    // kernel of each class (the single-primitive and 3-centre variants store
+    // their tail rows in lane patterns of their own)
+    if (cp.kind == K_MFMA) {
+        cp.variant = 1;
+        cp.bra_per_tile = eri_mfma_bra_per_tile(cp.key, 1);
+    }
+    const WsLayout L = ws_layout(cp, 0);
+    if (ws_bytes < L.total) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, L.total);
+    Digest dg{};
+    dg.on = 1;
+    if (!cp.swapped) {
+        dg.Db = Dbra; dg.Dk = Dket; dg.Jb = Jbra; dg.Jk = Jket;
+        dg.nb = nbra; dg.nk = nket;
+    } else {   // the kernel runs with the caller's ket pairs as its bra pairs
+        dg.Db = Dket; dg.Dk = Dbra; dg.Jb = Jket; dg.Jk = Jbra;
+        dg.nb = nket; dg.nk = nbra;
+    }
+    HIP_TRY2(hipSetDevice(c->device));
+    return enqueue_class(c, sh, cp, L, (char *)ws, nullptr, (hipStream_t)stream, true, &dg);
 }

@@ -35,7 +35,7 @@ namespace mdx {
 
 // One shellset (bra pair I, ket pair J) per workgroup; every thread of the
 // workgroup calls this with the same (I, J); nI = bra pairs of ket J.
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int LAY, int KP>
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int LAY, int KP, bool DIG = false>
 __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I, const int J, const int nI)
 {
     constexpr int L = LB + LK;
@@ -94,7 +94,13 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
     int *oab = kt + 4 * KT;                              // [NABP] output offsets (copies of a.om)
     int *ocd = oab + NABP;                               // [NCDP]
     int *rowt = ocd + NCDP;                              // [NHB] table offsets of the bra Hermite rows
+    double *dgb = (double *)(rowt + round_up(NHB, 2));   // DIG: [NABP] Db of bra pair I, [NCDP] Dk of ket pair J
+    double *dgk = dgb + NABP;
 
+    if constexpr (DIG) {   // the densities of this shellset, read at the store (after many barriers)
+        for (int k = tid; k < NABP; k += NT) dgb[k] = (a.dig.Jk && k < a.nab) ? a.dig.Db[I + a.dig.nb * k] : 0.0;
+        for (int k = tid; k < NCDP; k += NT) dgk[k] = (a.dig.Jb && k < a.ncd) ? a.dig.Dk[J + a.dig.nk * k] : 0.0;
+    }
     for (int k = tid; k < NHB; k += NT) rowt[k] = CB::off(HB0 + k);
     for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? CB::off(k) : 0;
     for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? CB::off(NKN + k) : 0;
@@ -326,7 +332,9 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                         for (int r = 0; r < 4; ++r) {
                             const int ab = 16 * mm + 4 * r + g;
                             const int cd = grp * GW + 16 * n + c;
-                            if (ab < a.nab && cd < a.ncd) {   // one wave: offsets from the arguments
+                            if constexpr (DIG)
+                                digest_block(a.dig, I, J, ab, cd, ab < a.nab, cd < a.ncd, O[mm][n][r], g, c, dgk[cd], dgb[ab]);
+                            else if (ab < a.nab && cd < a.ncd) {   // one wave: offsets from the arguments
                                 double *dst = a.om.out + obase + (int64_t)I * a.om.sI +
                                               omult * (int64_t)(a.om.oab[ab] + a.om.ocd[cd]);
                                 *dst = ch == 0 ? O[mm][n][r] : *dst + O[mm][n][r];
@@ -348,7 +356,9 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                     for (int ww = 0; ww < NW; ++ww) v += red[(((ww * NTAB + mm) * NTG + n) * 4 + r) * 64 + lane];
                     const int ab = 16 * mm + 4 * r + g;
                     const int cd = grp * GW + 16 * n + c;
-                    if (ab < a.nab && cd < a.ncd) {
+                    if constexpr (DIG)
+                        digest_block(a.dig, I, J, ab, cd, ab < a.nab, cd < a.ncd, v, g, c, dgk[cd], dgb[ab]);
+                    else if (ab < a.nab && cd < a.ncd) {
                         double *dst = a.om.out + obase + (int64_t)I * a.om.sI + omult * (int64_t)(oab[ab] + ocd[cd]);
                         *dst = ch == 0 ? v : *dst + v;
                     }
@@ -373,7 +383,9 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                             for (int ww = 1; ww < NW; ++ww) v += red[(((ww - 1) * NTG + n) * 4 + r) * 64 + lane];
                             const int ab = 16 * mm + 4 * r + g;
                             const int cd = grp * GW + 16 * n + c;
-                            if (ab < a.nab && cd < a.ncd) {
+                            if constexpr (DIG)
+                                digest_block(a.dig, I, J, ab, cd, ab < a.nab, cd < a.ncd, v, g, c, dgk[cd], dgb[ab]);
+                            else if (ab < a.nab && cd < a.ncd) {
                                 double *dst = a.om.out + obase + (int64_t)I * a.om.sI +
                                               omult * (int64_t)(oab[ab] + ocd[cd]);
                                 *dst = ch == 0 ? v : *dst + v;
@@ -390,7 +402,7 @@ struct MfmaShape {
     int NTAB, NTCD, NTG, MTW, NW;
 };
 
-template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int LAY, int KP>
+template <int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int LAY, int KP, bool DIG = false>
 __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
 {
     constexpr int L = LB + LK, D = L + 1;
@@ -400,8 +412,10 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     constexpr size_t RED = SEPRED ? (size_t)(NW - 1) * NTG * 256 : (size_t)NW * NTAB * NTG * 256;
     const size_t tabs = (size_t)Cube<D, LAY>::words(KP * nqmax);
     const size_t cube_words = SEPRED ? tabs + RED : std::max(tabs, RED);
+    constexpr int NHB = GB ? ncart(LB) : nherm(LB);
     return (cube_words + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)(KP * NTPAD + 4 * KT) * NTG * 16) * 8 +
-           (size_t)(NTPAD + 4 * KT + (NTAB + NTCD) * 16 + (GB ? ncart(LB) : nherm(LB))) * 4;
+           (size_t)(NTPAD + 4 * KT + (NTAB + NTCD) * 16 + (DIG ? round_up(NHB, 2) : NHB)) * 4 +
+           (DIG ? (size_t)(NTAB + NTCD) * 16 * 8 : 0);
 }
 
 // Instances: class key (LB, LK, NAB, NCD, GB), tile shape

@@ -17,10 +17,10 @@
 
 namespace mdx {
 
-// Shellset (bra pair I, ket pair J) of the calling lane; J is the same for
-// the whole wave (its ket data are scalar loads), I < nI.
+// Shellset (bra pair I, ket pair J) of the calling lane into out[ab][cd];
+// J is the same for the whole wave (its ket data are scalar loads).
 template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
-__device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I, const int J, const int nI)
+__device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, const int J, double (&out)[NAB][NCD])
 {
     constexpr int L = LB + LK;
     constexpr int NH = nherm(L);
@@ -42,7 +42,6 @@ __device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I,
     const double *Hb = a.bra.H + (int64_t)I * a.bra.pair_stride;
     const double *HkP = a.ket.H + (int64_t)J * a.ket.pair_stride;
 
-    double out[NAB][NCD];
 #pragma unroll
     for (int i = 0; i < NAB; ++i)
 #pragma unroll
@@ -118,6 +117,14 @@ __device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I,
         }
     }
 
+}
+
+// Shellset (I, J) of the calling lane, stored in the caller's layout; I < nI.
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
+__device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I, const int J, const int nI)
+{
+    double out[NAB][NCD];
+    eri_valu_compute<LB, LK, NAB, NCD, GB, GK>(a, I, J, out);
     // store, [ij,ab,cd,kl] addressing of the caller
     const int64_t base = (a.om.count ? a.om.obase[J] : (int64_t)J * a.om.sJ) + (int64_t)I * a.om.sI;
     const int64_t mult = a.om.count ? (int64_t)nI : a.om.mult;

@@ -25,9 +25,74 @@ __global__ void __launch_bounds__(64) eri_valu_kernel(EriArgs a)
     eri_valu_shellset<LB, LK, NAB, NCD, GB, GK>(a, I, J, nI);
 }
 
+// Digestion (dense batches): a workgroup takes 64 bra pairs, one per lane,
+// and valu_dig_nj consecutive ket pairs; each lane keeps its Jb rows in
+// registers over those ket pairs and adds them once, while the Jk terms of
+// one ket pair are summed over groups of 8 lanes before their atomic adds.  Lanes past
+// the last bra pair compute a copy of it and contribute nothing.  Over its
+// 16 ket pairs a lane also keeps reusing its bra pair's data; shellsets of
+// more than 81 integrals take one ket pair per workgroup (their registers are
+// spent on the shellset itself).
+template <int NAB, int NCD>
+constexpr int valu_dig_nj() { return NAB * NCD > 81 ? 1 : 16; }
+
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
+__global__ void __launch_bounds__(64) eri_valu_digest_kernel(EriArgs a)
+{
+    constexpr int NJ = valu_dig_nj<NAB, NCD>();
+    const int tiles = (a.nbra + 63) / 64;
+    const int jc = blockIdx.x / tiles, lane = (int)threadIdx.x;
+    const int I0 = (blockIdx.x % tiles) * 64 + lane;
+    const bool live = I0 < a.nbra;
+    const int I = live ? I0 : a.nbra - 1;
+    const Digest &d = a.dig;
+    double jb[NAB];
+#pragma unroll
+    for (int ab = 0; ab < NAB; ++ab) jb[ab] = 0.0;
+    const int J1 = min(a.nket, (jc + 1) * NJ);
+    for (int J = jc * NJ; J < J1; ++J) {
+        int zo = 0;   // opaque zero: keeps the Db loads inside the loop (no NAB live registers)
+        asm volatile("" : "+v"(zo));
+        double out[NAB][NCD];
+        eri_valu_compute<LB, LK, NAB, NCD, GB, GK>(a, I, J, out);
+        if (d.Jb) {
+#pragma unroll
+            for (int ab = 0; ab < NAB; ++ab)
+#pragma unroll
+                for (int cd = 0; cd < NCD; ++cd) jb[ab] = fma(out[ab][cd], d.Dk[J + d.nk * cd], jb[ab]);
+        }
+        if (d.Jk) {
+#pragma unroll
+            for (int cd = 0; cd < NCD; ++cd) {
+                double v = 0.0;
+                if (live) {
+#pragma unroll
+                    for (int ab = 0; ab < NAB; ++ab) v = fma(out[ab][cd], d.Db[I + zo + d.nb * ab], v);
+                }
+                // sums over groups of 8 lanes; one atomic per group
+                v += __shfl_xor(v, 1);
+                v += __shfl_xor(v, 2);
+                v += __shfl_xor(v, 4);
+                if ((lane & 7) == 0) atomicAdd(d.Jk + J + d.nk * cd, v);
+            }
+        }
+    }
+    if (d.Jb && live) {
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab) atomicAdd(d.Jb + I + d.nb * ab, jb[ab]);
+    }
+}
+
 template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
 static void launch_valu(const EriArgs &a, int nblocks, hipStream_t s)
 {
+    if (a.dig.on) {
+        constexpr int NJ = valu_dig_nj<NAB, NCD>();
+        const int64_t nb = (int64_t)((a.nbra + 63) / 64) * ((a.nket + NJ - 1) / NJ);
+        if (nb > INT32_MAX) return;   // the host splits batches long before this
+        hipLaunchKernelGGL((eri_valu_digest_kernel<LB, LK, NAB, NCD, GB, GK>), dim3((unsigned)nb), dim3(64), 0, s, a);
+        return;
+    }
     hipLaunchKernelGGL((eri_valu_kernel<LB, LK, NAB, NCD, GB, GK>), dim3(nblocks), dim3(64), 0, s, a);
 }
 

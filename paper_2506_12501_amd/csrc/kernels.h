@@ -37,6 +37,17 @@ struct EriKey {
     bool GB, GK;    // single-function solid sides (primitives summed in [0]^(m))
 };
 
+// Contraction of a batch with pair-blocked densities in place of the output
+// store (kernel orientation; all zero when the integrals are stored):
+//   Jb[I + nb*ab] += sum_{J,cd} (ab|cd)_{I,J} Dk[J + nk*cd]
+//   Jk[J + nk*cd] += sum_{I,ab} (ab|cd)_{I,J} Db[I + nb*ab]
+struct Digest {
+    const double *Db, *Dk;
+    double *Jb, *Jk;   // either may be null
+    int64_t nb, nk;
+    int on;
+};
+
 struct EriArgs {
     SideDev bra, ket;
     int nbra, nket;
@@ -51,6 +62,7 @@ struct EriArgs {
     int nab, ncd;             // functions per bra / ket pair (kernel orientation)
     int *counter;             // work counter (persistent kernels)
     OutMap om;
+    Digest dig;               // dig.on: contract instead of storing (plain launches only)
 };
 
 struct PairDataArgs {

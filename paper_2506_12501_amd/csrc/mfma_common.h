@@ -7,6 +7,7 @@
 
 #include "cube_layouts.h"
 #include "eri_common.h"
+#include "digest.h"
 #include "kernels.h"
 
 namespace mdx {

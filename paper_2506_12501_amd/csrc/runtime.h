@@ -110,6 +110,7 @@ void enqueue_pairdata(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, con
 mdx_status class_args(mdx_ctx *c, const ClassPlan &cp, const ClassDev &d, double *out, EriArgs &a, int &nblocks);
 mdx_status launch_class(mdx_ctx *c, const ClassPlan &cp, const EriArgs &a, int nblocks, hipStream_t s);
 mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
-                         double *out, hipStream_t s, bool upload);
+                         double *out, hipStream_t s, bool upload,
+                         const Digest *dig = nullptr);
 
 }  // namespace mdx

@@ -53,6 +53,8 @@ EXPORTS = {
                                                  _i32, _pi32, ctypes.c_int]),
     "mdx_eri_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32, _pi32,
                                      ctypes.c_int, _p, _p, ctypes.c_size_t, _p]),
+    "mdx_eri_digest_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32, _pi32,
+                                            ctypes.c_int, _p, _p, _p, _p, _p, ctypes.c_size_t, _p]),
     "mdx_eri_grad_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32,
                                                       _pi32, _i32, _pi32, ctypes.c_int]),
     "mdx_eri_grad_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32,
@@ -214,6 +216,39 @@ def eri(shells: DeviceShells, ncentre: int, bra, ket, cartesian: bool = False, c
     check(L.mdx_eri_batch(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket, _i32p(ket),
                           flags, _ptr(out), ctypes.c_void_p(aligned), wsz, _stream(torch)), "mdx_eri_batch")
     return out.view(nket, ncd, nab, nbra).permute(3, 2, 1, 0)
+
+
+def eri_digest(shells: DeviceShells, ncentre: int, bra, ket, Dbra=None, Dket=None, cartesian: bool = False,
+               ctx: Context | None = None):
+    """Dense batch contracted with pair-blocked densities inside the kernels;
+    Dbra [nbra, nab] and Dket [nket, ncd] device tensors (row = pair).
+    Returns (Jbra, Jket), same shapes (None where the other side's density
+    is None)."""
+    import torch
+    dev = shells.center.device
+    ctx = ctx or Context.get(dev.index or 0)
+    bra = _pairs(bra)
+    ket = _pairs(ket)
+    nbra, nket = bra.shape[0], ket.shape[0]
+    nab, ncd = _class_sizes(shells, ncentre, bra, ket, cartesian)
+    flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
+    L = lib()
+    sp = ctypes.byref(shells.struct)
+    wsz = L.mdx_eri_workspace_size(ctx.handle, sp, ncentre, nbra, _i32p(bra), nket, _i32p(ket), flags)
+    if wsz == 0:
+        check(L.mdx_eri_digest_batch(ctx.handle, sp, ncentre, nbra, _i32p(bra), nket, _i32p(ket), flags, None,
+                                     None, None, None, None, 0, _stream(torch)), "mdx_eri_digest_batch")
+    ws = torch.empty(wsz // 8 + 32, dtype=torch.float64, device=dev)
+    aligned = (_ptr(ws) + 255) // 256 * 256
+    # library layout: D[pair + npair*f], i.e. the transpose of [pair, f]
+    Db = Dbra.t().contiguous() if Dbra is not None else None
+    Dk = Dket.t().contiguous() if Dket is not None else None
+    Jb = torch.zeros(nab, nbra, dtype=torch.float64, device=dev) if Dk is not None else None
+    Jk = torch.zeros(ncd, nket, dtype=torch.float64, device=dev) if Db is not None else None
+    check(L.mdx_eri_digest_batch(ctx.handle, sp, ncentre, nbra, _i32p(bra), nket, _i32p(ket), flags, _ptr(Db),
+                                 _ptr(Dk), _ptr(Jb), _ptr(Jk), ctypes.c_void_p(aligned), wsz, _stream(torch)),
+          "mdx_eri_digest_batch")
+    return (Jb.t() if Jb is not None else None), (Jk.t() if Jk is not None else None)
 
 
 def eri_grad(shells: DeviceShells, ncentre: int, bra, ket, adjoint, cartesian: bool = False,

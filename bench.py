@@ -250,7 +250,7 @@ def extra_legs(native, ctx, torch, tune, reps, legs=EXTRA_LEGS):
     if "high_l" in legs:
         # high-L primitive classes: (ff|ff), (gg|gg) 128 x 128; (X|dd) 256 x 256
         hl = {}
-        for name in W.C4_CLASSES_4C + W.C4_CLASSES_3C:
+        for name in W.C4_CLASSES_4C + W.C4_CLASSES_3C + W.HIGH_L_CLASSES_4C:
             r = ClassRun(native, W.config4(name, seed=0), ctx, torch)
             v, vt = None, None
             if tune:

@@ -1,15 +1,15 @@
 // cube_layouts.h -- written by gen_cube_layouts.py; do not edit.
 // Compact [r]^(0) table layouts: entry (t, u, v), t + u + v <= D - 1, at
 // t*ST + u*SU + v; tables of successive quartets SIZE doubles apart; valid
-// (every entry of up to 48 tables at its own address) for D = 1..18.
+// (every entry of up to 48 tables at its own address) for D = 1..21.
 #pragma once
 
 namespace mdx {
 
 constexpr int CUBE_COMPACT_QMAX = 48;
-constexpr int CUBE_COMPACT_DMAX = 18;
+constexpr int CUBE_COMPACT_DMAX = 21;
 // {D, SU, ST, SIZE}
-constexpr int CUBE_COMPACT[18][4] = {
+constexpr int CUBE_COMPACT[21][4] = {
     {1, 1, 1, 1},
     {2, 2, 3, 4},
     {3, 4, 6, 13},
@@ -28,6 +28,9 @@ constexpr int CUBE_COMPACT[18][4] = {
     {16, 20, 265, 2028},
     {17, 18, 299, 2537},
     {18, 19, 340, 2898},
+    {19, 22, 409, 3493},
+    {20, 22, 377, 3980},
+    {21, 22, 441, 4641},
 };
 
 }  // namespace mdx

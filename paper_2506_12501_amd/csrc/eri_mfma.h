@@ -462,6 +462,7 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     X(8, 8, 81, 81, false, 6, 6, 1, 3, 4, 2, 141, 1)            /* (gg|gg)                   */    \
     X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 2, 141, 1)                                               \
     X(8, 8, 81, 81, false, 6, 6, 2, 3, 4, 1, 141, 1)                                               \
+    X(10, 10, 121, 121, false, 8, 8, 1, 2, 4, 1, CUBE_LAY_COMPACT, 1)  /* (hh|hh)            */   \
     X(2, 4, 5, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (d|dd)                    */    \
     X(3, 4, 7, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (f|dd)                    */    \
     X(4, 4, 9, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (g|dd)                    */    \

@@ -253,6 +253,9 @@ __host__ __device__ inline size_t prim_lds_bytes()
     X(6, 6, 49, 49, 4, 4, 4, 3, 1, false, CUBE_LAY_COMPACT)                                        \
     X(8, 8, 81, 81, 6, 6, 2, 2, 1, false, CUBE_LAY_COMPACT)       /* (gg|gg)                 */    \
     X(8, 8, 81, 81, 6, 6, 3, 2, 1, false, CUBE_LAY_COMPACT)                                        \
-    X(8, 8, 81, 81, 6, 6, 6, 3, 1, false, CUBE_LAY_COMPACT)
+    X(8, 8, 81, 81, 6, 6, 6, 3, 1, false, CUBE_LAY_COMPACT)                                        \
+    X(10, 10, 121, 121, 8, 8, 2, 1, 1, false, CUBE_LAY_COMPACT)   /* (hh|hh)                 */    \
+    X(10, 10, 121, 121, 8, 8, 4, 1, 1, false, CUBE_LAY_COMPACT)                                    \
+    X(10, 10, 121, 121, 8, 8, 3, 1, 1, false, CUBE_LAY_COMPACT)
 
 }  // namespace mdx

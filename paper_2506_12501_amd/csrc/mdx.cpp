@@ -162,15 +162,15 @@ extern "C" mdx_status mdx_create(int device, mdx_ctx **out)
         e = hipMemcpy(c->solid + off, sol[l].data(), sol[l].size() * sizeof(double), hipMemcpyHostToDevice);
         off += sol[l].size();
     }
-    // terminal ket matrices: 2-centre kets (lc, ld <= 4) and single functions (l <= 6)
+    // terminal ket matrices: 2-centre kets (lc, ld <= MDX_LMAX_4C) and single functions (l <= MDX_LMAX_3C)
     std::vector<double> T;
     for (int cart = 0; cart < 2 && e == hipSuccess; ++cart) {
-        for (int lc = 0; lc <= 4; ++lc)
-            for (int ld = 0; ld <= 4; ++ld) {
+        for (int lc = 0; lc <= MDX_LMAX_4C; ++lc)
+            for (int ld = 0; ld <= MDX_LMAX_4C; ++ld) {
                 c->tket_off[cart][lc][ld] = T.size();
                 build_tket(c, lc, ld, cart != 0, T);
             }
-        for (int l = 0; l <= 6; ++l) {
+        for (int l = 0; l <= MDX_LMAX_3C; ++l) {
             c->tket1_off[cart][l] = T.size();
             build_tket(c, l, -1, cart != 0, T);
         }

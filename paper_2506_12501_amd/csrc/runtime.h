@@ -22,7 +22,7 @@ struct mdx_ctx {
     size_t solid_off[9] = {};
     std::vector<std::vector<double>> solid_host;
     double *tket = nullptr;      // terminal ket matrices
-    size_t tket_off[2][5][5] = {};
+    size_t tket_off[2][MDX_LMAX_4C + 1][MDX_LMAX_4C + 1] = {};
     size_t tket1_off[2][7] = {};
     std::map<std::tuple<int, int, int, int, int, int>, int> variant;        // autotuner overrides
     std::map<std::tuple<int, int, int, int, int, int>, int> grad_variant;   // same, backward kernel

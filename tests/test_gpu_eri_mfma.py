@@ -38,11 +38,25 @@ def test_dddd_cartesian():
     assert_close(got, ref, "(dd|dd) cart")
 
 
-@pytest.mark.parametrize("name", ["(ff|ff)", "(gg|gg)"])
+@pytest.mark.parametrize("name", ["(ff|ff)", "(gg|gg)", "(hh|hh)"])
 def test_config4_high_l(name):
     b = W.config4(name, nbra=4, nket=3, seed=24)
     got, ref = run(b)
     assert_close(got, ref, name)
+
+
+def test_hhhh_contracted():
+    """l = 5 per shell, K = 2: two primitive quartets per sweep chunk, L = 20"""
+    b = W.make_class_batch("(hh|hh)", 2, 2, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=27)
+    got, ref = run(b)
+    assert_close(got, ref, "(hh|hh) K=2")
+
+
+def test_hhhh_three_primitives():
+    """K = 3: nine bra primitive quartets pass through LDS two at a time"""
+    b = W.make_class_batch("(hh|hh)", 1, 2, 3, 4.0, 0.1, 20.0, 0.1, 1.0, seed=28)
+    got, ref = run(b)
+    assert_close(got, ref, "(hh|hh) K=3")
 
 
 @pytest.mark.parametrize("name", ["(d|dd)", "(f|dd)", "(g|dd)", "(h|dd)", "(i|dd)"])

@@ -49,7 +49,7 @@ def test_contracted_classes(name):
     check_sampled(W.config2(name, seed=0), seed=1)
 
 
-@pytest.mark.parametrize("name", W.C4_CLASSES_4C + W.C4_CLASSES_3C)
+@pytest.mark.parametrize("name", W.C4_CLASSES_4C + W.C4_CLASSES_3C + W.HIGH_L_CLASSES_4C)
 def test_high_l_classes(name):
     check_sampled(W.config4(name, seed=0), n=48, seed=2)
 

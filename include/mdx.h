@@ -49,7 +49,7 @@ typedef enum {
 } mdx_status;
 
 /* compiled limits */
-#define MDX_LMAX_4C 5      /* l per shell, 4-centre                      */
+#define MDX_LMAX_4C 6      /* l per shell, 4-centre                      */
 #define MDX_LMAX_3C 6      /* l of the single-function side, 3-/2-centre */
 #define MDX_BOYS_MAX_M 32  /* highest Boys order of mdx_boys             */
 
@@ -123,7 +123,8 @@ mdx_status mdx_boys(mdx_ctx *ctx, int32_t n, const double *x, int mmax, double *
  * l_c, l_d <= MDX_LMAX_4C for 3-centre; both <= MDX_LMAX_3C for 2-centre.
  * Within these, a class runs if a kernel is compiled for it (every class with
  * l <= 2 per shell, the d/f/g classes of the matrix-core instance list, and
- * (hh|hh), spherical); others return MDX_EUNSUPPORTED.
+ * (hh|hh), and (ii|ii) of single primitive pairs, spherical); others return
+ * MDX_EUNSUPPORTED.
  */
 size_t mdx_eri_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
                               const int32_t *bra, int32_t nket, const int32_t *ket, int flags);

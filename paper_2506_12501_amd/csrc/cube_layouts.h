@@ -1,15 +1,15 @@
 // cube_layouts.h -- written by gen_cube_layouts.py; do not edit.
 // Compact [r]^(0) table layouts: entry (t, u, v), t + u + v <= D - 1, at
 // t*ST + u*SU + v; tables of successive quartets SIZE doubles apart; valid
-// (every entry of up to 48 tables at its own address) for D = 1..21.
+// (every entry of up to 48 tables at its own address) for D = 1..25.
 #pragma once
 
 namespace mdx {
 
 constexpr int CUBE_COMPACT_QMAX = 48;
-constexpr int CUBE_COMPACT_DMAX = 21;
+constexpr int CUBE_COMPACT_DMAX = 25;
 // {D, SU, ST, SIZE}
-constexpr int CUBE_COMPACT[21][4] = {
+constexpr int CUBE_COMPACT[25][4] = {
     {1, 1, 1, 1},
     {2, 2, 3, 4},
     {3, 4, 6, 13},
@@ -31,6 +31,10 @@ constexpr int CUBE_COMPACT[21][4] = {
     {19, 22, 409, 3493},
     {20, 22, 377, 3980},
     {21, 22, 441, 4641},
+    {22, 24, 515, 5436},
+    {23, 48, 553, 6143},
+    {24, 26, 607, 7010},
+    {25, 52, 651, 7877},
 };
 
 }  // namespace mdx

@@ -23,6 +23,10 @@
 // operands (one wave's first pass takes the column of X and the output
 // column; every pass takes its part of the output row), which removes a fifth
 // to a quarter of the matrix-core work.
+// Row parts: the bra Hermite rows of a column tile in RS parts, each accumulating
+// its own tiles of X and adding its share of the bra transform to the
+// output tiles, so that only MT/RS tiles of X are live at once ((ii|ii) has
+// 455 bra Hermite rows, 29 tiles).
 #pragma once
 
 #include "mfma_common.h"
@@ -47,6 +51,9 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
     constexpr int NTCDM = TAIL ? NTCD - 1 : NTCD;   // column tiles on the matrix cores
     constexpr int ABT = 16 * (NTAB - 1), CDT = 16 * (NTCD - 1);   // the tail functions (TAIL)
     static_assert(!TAIL || NB == 1, "tail functions with one shellset per workgroup");
+    constexpr int RS = MT > 24 ? 2 : 1;         // row parts (only where a column tile of X would not fit)
+    static_assert(!TAIL || RS == 1, "row parts without the VALU tail");
+    constexpr int MTP = (MT + RS - 1) / RS;     // row tiles per part
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
     static_assert(NB <= 64 && NB <= CB::QMAX, "tables of one workgroup");
@@ -117,16 +124,36 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
         int zo = 0;
         asm volatile("" : "+v"(zo));
         const double *hb = Hb + zo;
+        d4 O[NTABM];
+#pragma unroll
+        for (int i = 0; i < NTABM; ++i) O[i] = d4{0.0, 0.0, 0.0, 0.0};
+        double trow = 0.0, ocol[NTAB];
+#pragma unroll
+        for (int i = 0; i < NTAB; ++i) ocol[i] = 0.0;
+#pragma unroll 1
+        for (int part = 0; part < RS; ++part) {
+        const int T0 = part * MTP;                                   // first row tile of this part
+        const int MTN = (part + 1) * MTP < MT ? MTP : MT - T0;       // row tiles of this part
+        int ab0[MTP];   // table offsets of this part's bra rows (row 16(T0 + T) + c)
+#pragma unroll
+        for (int T = 0; T < MTP; ++T) {
+            if constexpr (RS == 1) {
+                ab0[T] = abase[T];
+            } else {
+                const int row = 16 * (T0 + T) + c;
+                ab0[T] = row < NHB ? CB::off(row) : 0;
+            }
+        }
         // ket transform of column tile jt: M = bra rows, K = ket rows, N = 16 ket functions
         // (gathers of step s + 1 and ket rows of step s + 3 are issued while step s
         // multiplies)
         const double *hk = Hk + 16 * jt + c;
-        d4 X[MT];
+        d4 X[MTP];
 #pragma unroll
-        for (int T = 0; T < MT; ++T) X[T] = d4{0.0, 0.0, 0.0, 0.0};
-        double av[2][MT], bq[4], tq[4], xt[MT];
+        for (int T = 0; T < MTP; ++T) X[T] = d4{0.0, 0.0, 0.0, 0.0};
+        double av[2][MTP], bq[4], tq[4], xt[MTP];
 #pragma unroll
-        for (int T = 0; T < MT; ++T) xt[T] = 0.0;
+        for (int T = 0; T < MTP; ++T) xt[T] = 0.0;
         const double *hkt = Hk + CDT;   // TAIL: ket column CDT
 #pragma unroll
         for (int k = 0; k < 3 && k < KS; ++k) {
@@ -136,14 +163,16 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
         {
             const int qo = sel4(KO.o[0], KO.o[1], KO.o[2], KO.o[3], g) + zo + qb;
 #pragma unroll
-            for (int T = 0; T < MT; ++T) av[0][T] = cube[abase[T] + qo];
+            for (int T = 0; T < MTP; ++T)
+                if (T < MTN) av[0][T] = cube[ab0[T] + qo];
         }
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
             if (s + 1 < KS) {
                 const int qo = sel4(KO.o[4 * s + 4], KO.o[4 * s + 5], KO.o[4 * s + 6], KO.o[4 * s + 7], g) + zo + qb;
 #pragma unroll
-                for (int T = 0; T < MT; ++T) av[(s + 1) & 1][T] = cube[abase[T] + qo];
+                for (int T = 0; T < MTP; ++T)
+                    if (T < MTN) av[(s + 1) & 1][T] = cube[ab0[T] + qo];
             }
             if (s + 3 < KS) {
                 bq[(s + 3) & 3] = 4 * (s + 3) + g < RPB ? hk[(int64_t)(4 * (s + 3) + g) * NCDP] : 0.0;
@@ -151,18 +180,19 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
                     tq[(s + 3) & 3] = (tpass && 4 * (s + 3) + g < RPB) ? hkt[(int64_t)(4 * (s + 3) + g) * NCDP] : 0.0;
             }
 #pragma unroll
-            for (int T = 0; T < MT; ++T) X[T] = mfma(av[s & 1][T], bq[s & 3], X[T]);
+            for (int T = 0; T < MTP; ++T)
+                if (T < MTN) X[T] = mfma(av[s & 1][T], bq[s & 3], X[T]);
             if constexpr (TAIL)
                 if (tpass)
 #pragma unroll
-                    for (int T = 0; T < MT; ++T) xt[T] = fma(av[s & 1][T], tq[s & 3], xt[T]);
+                    for (int T = 0; T < MTP; ++T) xt[T] = fma(av[s & 1][T], tq[s & 3], xt[T]);
             __builtin_amdgcn_sched_barrier(0);
         }
         if constexpr (TAIL) {
             if (tpass) {
                 // column CDT of X: sum the four lane groups, rows past NHB are 0
 #pragma unroll
-                for (int T = 0; T < MT; ++T) {
+                for (int T = 0; T < MTP; ++T) {
                     double v = xt[T];
                     v += __shfl_xor(v, 16);
                     v += __shfl_xor(v, 32);
@@ -176,36 +206,35 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
         // multiplies (scheduling barriers keep the loads from all being hoisted)
         // (TAIL: output row ABT from the same accumulators on the VALU: each lane
         // multiplies its own rows, the four lane groups are summed after)
-        d4 O[NTABM];
-#pragma unroll
-        for (int i = 0; i < NTABM; ++i) O[i] = d4{0.0, 0.0, 0.0, 0.0};
-        double hq[3][NTAB], trow = 0.0, ocol[NTAB];
-#pragma unroll
-        for (int i = 0; i < NTAB; ++i) ocol[i] = 0.0;
+        const double *hbp = hb + (int64_t)(16 * T0) * NABP;   // H_bra rows of this part
+        double hq[3][NTAB];
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
             for (int i = 0; i < NTAB; ++i)
-                hq[k][i] = hb[(int64_t)(4 * k + g) * NABP + (i < NTABM ? 16 * i + c : ABT)];
+                hq[k][i] = hbp[(int64_t)(4 * k + g) * NABP + (i < NTABM ? 16 * i + c : ABT)];
 #pragma unroll
-        for (int k = 0; k < 4 * MT; ++k) {
-            if (k + 2 < 4 * MT) {
+        for (int k = 0; k < 4 * MTP; ++k) {
+            if (k < 4 * MTN) {
+                if (k + 2 < 4 * MTN) {
 #pragma unroll
-                for (int i = 0; i < NTAB; ++i)
-                    hq[(k + 2) % 3][i] = hb[(int64_t)(4 * (k + 2) + g) * NABP + (i < NTABM ? 16 * i + c : ABT)];
-            }
+                    for (int i = 0; i < NTAB; ++i)
+                        hq[(k + 2) % 3][i] = hbp[(int64_t)(4 * (k + 2) + g) * NABP + (i < NTABM ? 16 * i + c : ABT)];
+                }
 #pragma unroll
-            for (int i = 0; i < NTABM; ++i) O[i] = mfma(hq[k % 3][i], X[k >> 2][k & 3], O[i]);
-            if constexpr (TAIL) {
-                trow = fma(hq[k % 3][NTAB - 1], X[k >> 2][k & 3], trow);
-                if (tpass) {   // output column CDT: H_bra rows times the column of X
-                    const double xv = Xt[4 * k + g];
+                for (int i = 0; i < NTABM; ++i) O[i] = mfma(hq[k % 3][i], X[k >> 2][k & 3], O[i]);
+                if constexpr (TAIL) {
+                    trow = fma(hq[k % 3][NTAB - 1], X[k >> 2][k & 3], trow);
+                    if (tpass) {   // output column CDT: H_bra rows times the column of X
+                        const double xv = Xt[4 * k + g];
 #pragma unroll
-                    for (int i = 0; i < NTAB; ++i) ocol[i] = fma(hq[k % 3][i], xv, ocol[i]);
+                        for (int i = 0; i < NTAB; ++i) ocol[i] = fma(hq[k % 3][i], xv, ocol[i]);
+                    }
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
         }
+        }   // row parts
         const int cd = 16 * jt + c;
 #pragma unroll
         for (int i = 0; i < NTABM; ++i)
@@ -256,6 +285,8 @@ __host__ __device__ inline size_t prim_lds_bytes()
     X(8, 8, 81, 81, 6, 6, 6, 3, 1, false, CUBE_LAY_COMPACT)                                        \
     X(10, 10, 121, 121, 8, 8, 2, 1, 1, false, CUBE_LAY_COMPACT)   /* (hh|hh)                 */    \
     X(10, 10, 121, 121, 8, 8, 4, 1, 1, false, CUBE_LAY_COMPACT)                                    \
-    X(10, 10, 121, 121, 8, 8, 3, 1, 1, false, CUBE_LAY_COMPACT)
+    X(10, 10, 121, 121, 8, 8, 3, 1, 1, false, CUBE_LAY_COMPACT)                                    \
+    X(12, 12, 169, 169, 11, 11, 2, 1, 1, false, CUBE_LAY_COMPACT) /* (ii|ii)                 */    \
+    X(12, 12, 169, 169, 11, 11, 4, 1, 1, false, CUBE_LAY_COMPACT)
 
 }  // namespace mdx

@@ -19,7 +19,7 @@ import numpy as np
 
 QMAX = 48          # tables per interleaved block the layouts are valid for
 QREF = 18          # block size the footprint is minimised for
-LMAX = 20
+LMAX = 24
 
 
 def herm(L):

@@ -179,7 +179,7 @@ C2_CLASSES = ["(dd|dd)", "(pd|dd)"]
 C4_CLASSES_4C = ["(ff|ff)", "(gg|gg)"]
 C4_CLASSES_3C = ["(s|dd)", "(p|dd)", "(d|dd)", "(f|dd)", "(g|dd)", "(h|dd)", "(i|dd)"]
 # beyond l = 4 per 4-centre shell (same recipe as the high-L classes above)
-HIGH_L_CLASSES_4C = ["(hh|hh)"]
+HIGH_L_CLASSES_4C = ["(hh|hh)", "(ii|ii)"]
 
 
 def config1(name: str, npair: int = 16, seed: int = 0) -> ClassBatch:

@@ -45,6 +45,22 @@ def test_config4_high_l(name):
     assert_close(got, ref, name)
 
 
+def test_iiii_single_primitive():
+    """l = 6 per shell, L = 24: the single-primitive kernel with its bra rows in two parts"""
+    b = W.config4("(ii|ii)", nbra=3, nket=2, seed=29)
+    got, ref = run(b)
+    assert_close(got, ref, "(ii|ii)")
+
+
+def test_iiii_contracted_is_refused():
+    """contracted (ii|ii) has no kernel: the general kernel's tables do not fit LDS"""
+    from paper_2506_12501_amd import native
+    b = W.make_class_batch("(ii|ii)", 2, 2, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=30)
+    with pytest.raises(native.MdxError) as e:
+        native.eri(native.DeviceShells(b.basis), 4, b.bra, b.ket)
+    assert e.value.status == native.MDX_EUNSUPPORTED
+
+
 def test_hhhh_contracted():
     """l = 5 per shell, K = 2: two primitive quartets per sweep chunk, L = 20"""
     b = W.make_class_batch("(hh|hh)", 2, 2, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=27)

@@ -192,7 +192,7 @@ mdx_status mdx_eri_grad_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentr
  *         nb = functions of shell b; either may be NULL (not computed).
  *   ws    DEVICE, at least mdx_one_body_workspace_size bytes, 256-byte aligned.
  *   flags MDX_SPHERICAL or MDX_CARTESIAN.
- * Limits: l_a, l_b <= 2 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
+ * Limits: l_a, l_b <= 3 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
  * bad arguments, shell indices or mixed classes; MDX_EWORKSPACE for a short
  * workspace; MDX_EDEVICE for a HIP error.  The size query returns 0 on any
  * error (mdx_last_error says why).
@@ -215,7 +215,7 @@ mdx_status mdx_one_body_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t np
  *   V       DEVICE double, [ij, ab] column-major: V[ij + npair*ab].
  *   ws      DEVICE, at least mdx_nuclear_workspace_size bytes, 256-byte aligned.
  *   flags   MDX_SPHERICAL or MDX_CARTESIAN.
- * Limits: l_a, l_b <= 2 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
+ * Limits: l_a, l_b <= 3 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
  * bad arguments, shell indices, mixed classes, a negative charge count or a
  * null charge array with ncharge > 0; MDX_EWORKSPACE for a short workspace;
  * MDX_EDEVICE for a HIP error.  The size query returns 0 on any error.

@@ -26,6 +26,8 @@ namespace mdx {
 
 static inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
+constexpr int ONEBODY_LMAX = 3;   // per shell, overlap / kinetic / nuclear attraction
+
 struct OneBodyArgs {
     const PairRec *pairs;
     int npair;
@@ -368,8 +370,9 @@ static mdx_status check_pairs(mdx_ctx *c, const mdx_shells *sh, int32_t npair, c
             if (i == 0) l[k] = sh->l[s];
             else if (sh->l[s] != l[k]) return fail(MDX_EINVAL, "pair %d: class differs from pair 0", i);
         }
-    if (npair > 0 && (l[0] < 0 || l[1] < 0 || l[0] > 2 || l[1] > 2))
-        return fail(MDX_EUNSUPPORTED, "one-body integrals for l_a = %d, l_b = %d (compiled for l <= 2)", l[0], l[1]);
+    if (npair > 0 && (l[0] < 0 || l[1] < 0 || l[0] > ONEBODY_LMAX || l[1] > ONEBODY_LMAX))
+        return fail(MDX_EUNSUPPORTED, "one-body integrals for l_a = %d, l_b = %d (compiled for l <= %d)", l[0], l[1],
+                    ONEBODY_LMAX);
     return MDX_OK;
 }
 
@@ -411,18 +414,25 @@ static mdx_status stage_pairs(mdx_ctx *c, const mdx_shells *sh, int32_t npair, c
     return MDX_OK;
 }
 
-// one case per (l_a, l_b), l <= 2
+// one case per (l_a, l_b), l <= ONEBODY_LMAX = 3
 #define MDX_ONEBODY_SWITCH(LAUNCH, la, lb, ...)          \
-    switch ((la) * 3 + (lb)) {                           \
+    switch ((la) * 4 + (lb)) {                           \
     case 0: LAUNCH<0, 0>(__VA_ARGS__); break;            \
     case 1: LAUNCH<0, 1>(__VA_ARGS__); break;            \
     case 2: LAUNCH<0, 2>(__VA_ARGS__); break;            \
-    case 3: LAUNCH<1, 0>(__VA_ARGS__); break;            \
-    case 4: LAUNCH<1, 1>(__VA_ARGS__); break;            \
-    case 5: LAUNCH<1, 2>(__VA_ARGS__); break;            \
-    case 6: LAUNCH<2, 0>(__VA_ARGS__); break;            \
-    case 7: LAUNCH<2, 1>(__VA_ARGS__); break;            \
-    default: LAUNCH<2, 2>(__VA_ARGS__); break;           \
+    case 3: LAUNCH<0, 3>(__VA_ARGS__); break;            \
+    case 4: LAUNCH<1, 0>(__VA_ARGS__); break;            \
+    case 5: LAUNCH<1, 1>(__VA_ARGS__); break;            \
+    case 6: LAUNCH<1, 2>(__VA_ARGS__); break;            \
+    case 7: LAUNCH<1, 3>(__VA_ARGS__); break;            \
+    case 8: LAUNCH<2, 0>(__VA_ARGS__); break;            \
+    case 9: LAUNCH<2, 1>(__VA_ARGS__); break;            \
+    case 10: LAUNCH<2, 2>(__VA_ARGS__); break;           \
+    case 11: LAUNCH<2, 3>(__VA_ARGS__); break;           \
+    case 12: LAUNCH<3, 0>(__VA_ARGS__); break;           \
+    case 13: LAUNCH<3, 1>(__VA_ARGS__); break;           \
+    case 14: LAUNCH<3, 2>(__VA_ARGS__); break;           \
+    default: LAUNCH<3, 3>(__VA_ARGS__); break;           \
     }
 
 extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,

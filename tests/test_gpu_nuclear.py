@@ -13,7 +13,7 @@ from tests.gpu_util import assert_close
 
 pytestmark = pytest.mark.gpu
 
-LET = "spd"
+LET = "spdf"
 
 
 def run(basis, pairs, charges, cart, quad=False):
@@ -46,8 +46,8 @@ def charges_with_edges(basis, pairs, n, seed):
     return np.ascontiguousarray(np.r_[ch, extra])
 
 
-@pytest.mark.parametrize("la", [0, 1, 2])
-@pytest.mark.parametrize("lb", [0, 1, 2])
+@pytest.mark.parametrize("la", [0, 1, 2, 3])
+@pytest.mark.parametrize("lb", [0, 1, 2, 3])
 @pytest.mark.parametrize("cart", [False, True])
 def test_classes_contracted(la, lb, cart):
     basis, pairs = pair_batch(la, lb, 67, 3, seed=21 + 3 * la + lb)
@@ -96,7 +96,7 @@ def test_water_cluster_cut_with_nuclear_charges():
 def test_errors():
     import torch
     from paper_2506_12501_amd import native
-    b = W.make_class_batch("(fd|ss)", 3, 1, 1, 4.0, 0.1, 10.0, 0.1, 1.0, seed=1)
+    b = W.make_class_batch("(gd|ss)", 3, 1, 1, 4.0, 0.1, 10.0, 0.1, 1.0, seed=1)
     sh = native.DeviceShells(b.basis)
     ch = torch.as_tensor(W.point_charges(4, seed=1), device="cuda")
     with pytest.raises(native.MdxError) as e:

@@ -10,7 +10,7 @@ from tests.gpu_util import assert_close
 
 pytestmark = pytest.mark.gpu
 
-LET = "spd"
+LET = "spdf"
 
 
 def run(basis, pairs, cart, quad=False, **kw):
@@ -58,8 +58,8 @@ def pair_batch(la, lb, npair, K, seed):
     return b.basis, b.bra
 
 
-@pytest.mark.parametrize("la", [0, 1, 2])
-@pytest.mark.parametrize("lb", [0, 1, 2])
+@pytest.mark.parametrize("la", [0, 1, 2, 3])
+@pytest.mark.parametrize("lb", [0, 1, 2, 3])
 @pytest.mark.parametrize("cart", [False, True])
 def test_classes_contracted(la, lb, cart):
     basis, pairs = pair_batch(la, lb, 133, 3, seed=7 + 3 * la + lb)
@@ -119,7 +119,7 @@ def test_empty_batch():
 
 def test_errors():
     from paper_2506_12501_amd import native
-    b = W.make_class_batch("(fd|ss)", 3, 1, 1, 4.0, 0.1, 10.0, 0.1, 1.0, seed=1)
+    b = W.make_class_batch("(gd|ss)", 3, 1, 1, 4.0, 0.1, 10.0, 0.1, 1.0, seed=1)
     sh = native.DeviceShells(b.basis)
     with pytest.raises(native.MdxError) as e:
         native.one_body(sh, b.bra)

@@ -117,7 +117,9 @@ __device__ __forceinline__ void store_pair(const double (&X)[ncart(LA)][ncart(LB
     }
 }
 
-template <int LA, int LB, bool CART>
+// PART: 0 = S and T together; 1 = S only; 2 = T only (large classes run the
+// two as separate launches so that one lane holds one set of accumulators)
+template <int LA, int LB, bool CART, int PART>
 __global__ void __launch_bounds__(64) onebody_kernel(OneBodyArgs a)
 {
     const int ij = blockIdx.x * 64 + (int)threadIdx.x;
@@ -138,11 +140,23 @@ __global__ void __launch_bounds__(64) onebody_kernel(OneBodyArgs a)
         for (int kb = 0; kb < pr.kb; ++kb) {
             const double zb = a.expo[pr.offb + kb], cb = a.coef[pr.offb + kb];
             const double p = za + zb;
-            double E0[3][LA + 1][LB + 3];
+            // 1-D overlaps s1 and kinetic factors t1 per axis; each axis's E
+            // table is reduced to them at once, so only one table is live
+            double s1[3][LA + 1][LB + 1], t1[3][LA + 1][LB + 1];
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
                 const double P = (za * A[ax] + zb * B[ax]) / p;
-                e0_axis<LA, LB + 2>(p, P - A[ax], P - B[ax], E0[ax]);
+                double E0[LA + 1][LB + 3];
+                e0_axis<LA, LB + 2>(p, P - A[ax], P - B[ax], E0);
+#pragma unroll
+                for (int ia = 0; ia <= LA; ++ia)
+#pragma unroll
+                    for (int jb = 0; jb <= LB; ++jb) {
+                        s1[ax][ia][jb] = E0[ia][jb];
+                        double d2 = 4.0 * zb * zb * E0[ia][jb + 2] - 2.0 * zb * (2 * jb + 1) * E0[ia][jb];
+                        if (jb >= 2) d2 += (double)(jb * (jb - 1)) * E0[ia][jb - 2];
+                        t1[ax][ia][jb] = -0.5 * d2;
+                    }
             }
             // c_a c_b (pi/p)^{3/2} exp(-za zb/p |A-B|^2), Eqs. (8), (14)
             const double f = ca * cb * (M_PI / p) * sqrt(M_PI / p) * exp(-za * zb / p * AB2);
@@ -154,18 +168,19 @@ __global__ void __launch_bounds__(64) onebody_kernel(OneBodyArgs a)
 #pragma unroll
                     for (int ax = 0; ax < 3; ++ax) {
                         const int ia = cart_exp(LA, i, ax), jb = cart_exp(LB, j, ax);
-                        s[ax] = E0[ax][ia][jb];
-                        double d2 = 4.0 * zb * zb * E0[ax][ia][jb + 2] - 2.0 * zb * (2 * jb + 1) * s[ax];
-                        if (jb >= 2) d2 += (double)(jb * (jb - 1)) * E0[ax][ia][jb - 2];
-                        t[ax] = -0.5 * d2;
+                        s[ax] = s1[ax][ia][jb];
+                        t[ax] = t1[ax][ia][jb];
                     }
-                    S[i][j] = fma(f, s[0] * s[1] * s[2], S[i][j]);
-                    T[i][j] = fma(f, t[0] * s[1] * s[2] + s[0] * t[1] * s[2] + s[0] * s[1] * t[2], T[i][j]);
+                    if constexpr (PART != 2) S[i][j] = fma(f, s[0] * s[1] * s[2], S[i][j]);
+                    if constexpr (PART != 1)
+                        T[i][j] = fma(f, t[0] * s[1] * s[2] + s[0] * t[1] * s[2] + s[0] * s[1] * t[2], T[i][j]);
                 }
         }
     }
-    if (a.S) store_pair<LA, LB, CART>(S, a.Ca, a.Cb, a.S, ij, a.npair);
-    if (a.T) store_pair<LA, LB, CART>(T, a.Ca, a.Cb, a.T, ij, a.npair);
+    if constexpr (PART != 2)
+        if (a.S) store_pair<LA, LB, CART>(S, a.Ca, a.Cb, a.S, ij, a.npair);
+    if constexpr (PART != 1)
+        if (a.T) store_pair<LA, LB, CART>(T, a.Ca, a.Cb, a.T, ij, a.npair);
 }
 
 struct NuclearArgs {
@@ -341,12 +356,23 @@ static void launch_nuclear(const NuclearArgs &a, bool cart, hipStream_t s)
     else hipLaunchKernelGGL((nuclear_kernel<LA, LB, false, G, LT>), dim3(nblk), dim3(64 * G), 0, s, a);
 }
 
+template <int LA, int LB, int PART>
+static void launch_onebody_part(const OneBodyArgs &a, bool cart, hipStream_t s)
+{
+    const int nblk = (a.npair + 63) / 64;
+    if (cart) hipLaunchKernelGGL((onebody_kernel<LA, LB, true, PART>), dim3(nblk), dim3(64), 0, s, a);
+    else hipLaunchKernelGGL((onebody_kernel<LA, LB, false, PART>), dim3(nblk), dim3(64), 0, s, a);
+}
+
 template <int LA, int LB>
 static void launch_onebody(const OneBodyArgs &a, bool cart, hipStream_t s)
 {
-    const int nblk = (a.npair + 63) / 64;
-    if (cart) hipLaunchKernelGGL((onebody_kernel<LA, LB, true>), dim3(nblk), dim3(64), 0, s, a);
-    else hipLaunchKernelGGL((onebody_kernel<LA, LB, false>), dim3(nblk), dim3(64), 0, s, a);
+    if constexpr (LA + LB >= 5) {   // S and T apart: one set of accumulators per lane
+        if (a.S) launch_onebody_part<LA, LB, 1>(a, cart, s);
+        if (a.T) launch_onebody_part<LA, LB, 2>(a, cart, s);
+    } else {
+        launch_onebody_part<LA, LB, 0>(a, cart, s);
+    }
 }
 
 // validation shared by the size query and the call; l = (l_a, l_b)

@@ -151,7 +151,8 @@ mdx_status mdx_eri_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, in
  * Same other arguments, limits and workspace (mdx_eri_workspace_size) as
  * mdx_eri_batch.  Classes whose default kernel is a single-primitive or
  * 3-centre matrix-core variant run on the general matrix-core kernel.
- * Errors as mdx_eri_batch; MDX_EINVAL also for a J without its density.
+ * Errors as mdx_eri_batch; MDX_EINVAL also for a J without its density.  An
+ * empty batch (nbra or nket 0) reads and writes nothing and returns MDX_OK.
  */
 mdx_status mdx_eri_digest_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
                                 const int32_t *bra, int32_t nket, const int32_t *ket, int flags,

@@ -435,9 +435,9 @@ extern "C" mdx_status mdx_eri_digest_batch(mdx_ctx *c, const mdx_shells *sh, int
     ClassPlan cp;
     mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp);
     if (st != MDX_OK) return st;
+    if (nbra == 0 || nket == 0 || (!Jbra && !Jket)) return MDX_OK;   // nothing is read or written
     if (Jbra && !Dket) return fail(MDX_EINVAL, "mdx_eri_digest_batch: Jbra needs Dket");
     if (Jket && !Dbra) return fail(MDX_EINVAL, "mdx_eri_digest_batch: Jket needs Dbra");
-    if (nbra == 0 || nket == 0 || (!Jbra && !Jket)) return MDX_OK;
     if (!ws) return fail(MDX_EINVAL, "mdx_eri_digest_batch: null workspace");
     if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_eri_digest_batch: workspace not 256-byte aligned");
     // digestion is compiled for the first shape of the general matrix-core

@@ -230,7 +230,11 @@ def eri_digest(shells: DeviceShells, ncentre: int, bra, ket, Dbra=None, Dket=Non
     bra = _pairs(bra)
     ket = _pairs(ket)
     nbra, nket = bra.shape[0], ket.shape[0]
-    nab, ncd = _class_sizes(shells, ncentre, bra, ket, cartesian)
+    if nbra and nket:
+        nab, ncd = _class_sizes(shells, ncentre, bra, ket, cartesian)
+    else:   # an empty side: the densities carry the function counts
+        nab = Dbra.shape[1] if Dbra is not None else 0
+        ncd = Dket.shape[1] if Dket is not None else 0
     flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
     L = lib()
     sp = ctypes.byref(shells.struct)

@@ -71,6 +71,25 @@ def test_single_primitive_classes_on_the_general_kernel(name):
     run(W.make_class_batch(name, 11, 7, 1, 4.0, 0.1, 20.0, 0.1, 1.0, seed=7))
 
 
+@pytest.mark.parametrize("name", ["(p|p)", "(d|d)", "(f|d)", "(d|ds)"])
+def test_two_and_three_centre(name):
+    run(W.make_class_batch(name, 66, 5, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=10))
+
+
+def test_matrix_core_cartesian():
+    run(W.make_class_batch("(dd|dd)", 9, 7, 1, 4.0, 0.1, 20.0, 0.1, 1.0, seed=11), cart=True)
+
+
+def test_empty_batch_is_a_no_op():
+    import torch
+    from paper_2506_12501_amd import native
+    b = W.make_class_batch("(pp|pp)", 3, 2, 1, 4.0, 0.1, 20.0, 0.1, 1.0, seed=12)
+    Jb, Jk = native.eri_digest(native.DeviceShells(b.basis), 4, b.bra[:0], b.ket,
+                               torch.zeros((0, 9), dtype=torch.float64, device="cuda"),
+                               torch.ones((2, 9), dtype=torch.float64, device="cuda"))
+    assert Jb.numel() == 0 and np.all(Jk.cpu().numpy() == 0.0)
+
+
 def test_cartesian_and_one_side_only():
     b = W.make_class_batch("(dp|ps)", 40, 13, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=8)
     run(b, cart=True)

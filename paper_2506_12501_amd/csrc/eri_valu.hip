@@ -51,8 +51,8 @@ __global__ void __launch_bounds__(64) eri_valu_digest_kernel(EriArgs a)
     for (int ab = 0; ab < NAB; ++ab) jb[ab] = 0.0;
     const int J1 = min(a.nket, (jc + 1) * NJ);
     for (int J = jc * NJ; J < J1; ++J) {
-        int zo = 0;   // opaque zero: keeps the Db loads inside the loop (no NAB live registers)
-        asm volatile("" : "+v"(zo));
+        int zo = 0;   // large bra sides: an opaque zero keeps the Db loads inside the loop
+        if constexpr (NAB > 9) asm volatile("" : "+v"(zo));   // (no NAB registers live across it)
         double out[NAB][NCD];
         eri_valu_compute<LB, LK, NAB, NCD, GB, GK>(a, I, J, out);
         if (d.Jb) {

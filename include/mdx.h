@@ -87,6 +87,7 @@ typedef struct {
 mdx_status mdx_create(int device, mdx_ctx **out);
 void mdx_destroy(mdx_ctx *ctx);
 
+/* name of a status code ("MDX_OK", "MDX_EINVAL", ...; static storage) */
 const char *mdx_status_string(mdx_status s);
 /* text of the last error raised on this thread (static storage) */
 const char *mdx_last_error(void);

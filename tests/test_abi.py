@@ -18,7 +18,8 @@ def header_functions():
 def test_header_declares_the_entry_points():
     names = header_functions()
     for required in ["mdx_eri_batch", "mdx_eri_grad_batch", "mdx_boys", "mdx_create", "mdx_destroy",
-                     "mdx_plan_create", "mdx_plan_execute"]:
+                     "mdx_plan_create", "mdx_plan_execute", "mdx_eri_digest_batch", "mdx_one_body_batch",
+                     "mdx_nuclear_batch"]:
         assert required in names
 
 
@@ -55,3 +56,19 @@ def test_no_gpu_means_clean_error():
     h = ctypes.c_void_p()
     st = native.lib().mdx_create(0, ctypes.byref(h))
     assert st in (native.MDX_EINVAL, native.MDX_EDEVICE)
+
+
+def test_every_entry_point_is_documented():
+    """each declaration follows its contract comment: between the nearest
+    comment block and the declaration stands at most one other declaration
+    (a size query and its call share one contract)"""
+    src = open(os.path.join(ROOT, "include", "mdx.h")).read()
+    for name in header_functions():
+        # the declaration: the first occurrence outside a comment line
+        for m in re.finditer(r"\b" + name + r"\s*\(", src):
+            line = src[src.rfind("\n", 0, m.start()) + 1:m.start()].strip()
+            if not line.startswith(("*", "/*")):
+                break
+        i = m.start()
+        gap = src[src.rfind("*/", 0, i):i]
+        assert src.rfind("*/", 0, i) >= 0 and gap.count(";") <= 1, name

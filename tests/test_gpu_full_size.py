@@ -44,6 +44,15 @@ def test_sp_classes_all_elements(name):
     assert_close(got, O.eri(b.basis, 4, b.bra, b.ket), f"{name} 16x16")
 
 
+@pytest.mark.parametrize("name", ["(pp|pp)", "(pp|ps)", "(dd|ss)"])
+def test_large_register_kernel_batches(name):
+    """dense batches large enough for the register kernel's multi-ket mapping
+    (64 bra pairs x 16 ket pairs per workgroup): 520 bra pairs (a ragged last
+    tile) x 7,300 ket pairs (a last chunk of 4), sampled shellsets"""
+    b = W.make_class_batch(name, 520, 7300, 1, 4.0, 0.1, 100.0, None, None, seed=31)
+    check_sampled(b, n=96, seed=4)
+
+
 @pytest.mark.parametrize("name", W.C2_CLASSES)
 def test_contracted_classes(name):
     check_sampled(W.config2(name, seed=0), seed=1)

@@ -1,6 +1,9 @@
 /*
- * mdx.h -- C ABI of libmdx: batched McMurchie-Davidson (MD) electron-repulsion
- * integrals (ERIs) over contracted Gaussian shells, on one AMD MI355X (gfx950).
+ * mdx.h -- C ABI of libmdx: batched McMurchie-Davidson (MD) Gaussian integrals
+ * over contracted shells, on one AMD MI355X (gfx950): electron-repulsion
+ * integrals (ERIs), their centre derivatives, their contraction with
+ * densities, and the 1-particle overlap, kinetic-energy and nuclear-attraction
+ * integrals.
  *
  * The integrals are those of Asadchev & Valeev, "Implementation of
  * McMurchie-Davidson algorithm for Gaussian AO integrals suited for SIMD
@@ -9,7 +12,8 @@
  *   3-centre (a|cd)    Sec. 2.1, Eq. (4)
  *   2-centre (a|c)     Eq. (4) with a single ket function (Sec. 2.2.3)
  * evaluated in batches of shellsets of one class (Sec. 2.1, paragraph after
- * Eq. (19); Sec. 3.1), in the [ij,ab,cd,kl] column-major layout of Sec. 3.1.
+ * Eq. (19); Sec. 3.1), in the [ij,ab,cd,kl] column-major layout of Sec. 3.1;
+ * 1-particle integrals of shell pairs (Sec. 2.1, Eq. (8); Eqs. (24)-(37)).
  *
  * Conventions (all entry points):
  *  - Atomic units.  A primitive Cartesian Gaussian is
@@ -20,8 +24,10 @@
  *  - Real solid harmonics (default; Eqs. (18)-(19)): order m = -l..l, each
  *    normalised to the norm of the x^l Cartesian of the same exponent.
  *  - Everything runs asynchronously on the caller's stream.  The caller owns
- *    every buffer; outputs are overwritten, never accumulated.  No call
- *    allocates device memory: scratch lives in the caller's workspace.
+ *    every buffer; outputs are overwritten (the J blocks of
+ *    mdx_eri_digest_batch are the one exception: accumulated).  Apart from
+ *    mdx_create and mdx_plan_create no call allocates device memory: scratch
+ *    lives in the caller's workspace.
  *  - On any error no kernel is launched and no output is written.
  *  - One mdx_ctx per device and per host thread (a context is not
  *    thread-safe).  No C++ exception crosses this interface.

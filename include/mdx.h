@@ -64,6 +64,7 @@ typedef enum {
 #define MDX_CARTESIAN 1    /* Cartesian components                       */
 #define MDX_FUSED 2        /* plans: one graph launch, persistent kernels */
 #define MDX_GRADIENT 4     /* mdx_set_variant: choose the backward kernel */
+#define MDX_PAIRED 8       /* mdx_eri_batch: quartet q = (bra q, ket q)   */
 
 typedef struct mdx_ctx mdx_ctx;
 
@@ -123,7 +124,10 @@ mdx_status mdx_boys(mdx_ctx *ctx, int32_t n, const double *x, int mmax, double *
  *       out[ij + nbra*(ab + nab*(cd + ncd*kl))],  ab = a*nb + b, cd = c*nd + d,
  *       nab = n(l_a)*n(l_b) (n(l) = 2l+1 spherical, (l+1)(l+2)/2 Cartesian;
  *       a single-function side has nab = n(l_a)).
- *   flags: MDX_SPHERICAL or MDX_CARTESIAN.
+ *   flags: MDX_SPHERICAL or MDX_CARTESIAN, optionally | MDX_PAIRED: then
+ *       nbra == nket and only the quartets q = (bra q, ket q) are computed,
+ *       out[q + nbra*(ab + nab*cd)] (the paired form; pass the same flags to
+ *       mdx_eri_workspace_size).
  *   ws, ws_bytes: DEVICE workspace of at least mdx_eri_workspace_size(...)
  *   bytes, 256-byte aligned; its contents on entry do not matter.
  * Limits: l <= MDX_LMAX_4C per shell for 4-centre; l_a <= MDX_LMAX_3C and

@@ -62,7 +62,7 @@ mdx_status check_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nb
     if (ncentre < 2 || ncentre > 4) return fail(MDX_EINVAL, "ncentre = %d (must be 2, 3 or 4)", ncentre);
     if (nbra < 0 || nket < 0) return fail(MDX_EINVAL, "negative pair count");
     if ((nbra > 0 && !bra) || (nket > 0 && !ket)) return fail(MDX_EINVAL, "null pair list");
-    if (flags & ~(MDX_CARTESIAN | MDX_FUSED)) return fail(MDX_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(MDX_CARTESIAN | MDX_FUSED | MDX_PAIRED)) return fail(MDX_EINVAL, "unknown flags 0x%x", flags);
     if (sh->nshell < 0 || (sh->nshell > 0 && (!sh->l || !sh->nprim || !sh->prim_offset || !sh->center ||
                                                !sh->exponent || !sh->coef)))
         return fail(MDX_EINVAL, "incomplete shell table");
@@ -237,6 +237,22 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
         for (int j = 0; j < ncdk; ++j) om.ocd[j] = j * nab_c;
         cp.out_doubles = off;
     }
+    if (flags & MDX_PAIRED) {   // quartet q = (bra q, ket q): the shellsets I = J of the outer product
+        if (bra_count) return fail(MDX_EINVAL, "MDX_PAIRED with bra prefixes");
+        if (nbra != nket) return fail(MDX_EINVAL, "MDX_PAIRED needs nbra == nket (%d, %d)", nbra, nket);
+        cp.diag = cp.paired = true;
+        if (cp.kind == K_MFMA) {   // the first shape: one shellset per workgroup
+            cp.variant = 1;
+            cp.bra_per_tile = eri_mfma_bra_per_tile(cp.key, 1);
+            if (cp.bra_per_tile != 1)
+                return fail(MDX_EUNSUPPORTED, "MDX_PAIRED for class (%d %d|%d %d)", cp.la, cp.lb, cp.lc, cp.ld);
+        }
+        // out[q + n*(ab + nab*cd)] in the caller's orientation; I = J = q
+        om.sI = 0;
+        om.sJ = 1;
+        om.mult = nbra;
+        cp.out_doubles = (int64_t)nbra * nab_c * ncd_c;
+    }
     return MDX_OK;
 }
 
@@ -338,8 +354,10 @@ mdx_status class_args(mdx_ctx *c, const ClassPlan &cp, const ClassDev &d, double
     a.om = cp.om;
     a.om.out = out;
     if (cp.diag) {
-        a.diag = 1;
-        nblocks = (int)nk;
+        // register kernel on a paired batch: one quartet per lane (diag = 2);
+        // otherwise one shellset per workgroup
+        a.diag = (cp.paired && cp.kind == K_VALU) ? 2 : 1;
+        nblocks = a.diag == 2 ? (int)((nk + 63) / 64) : (int)nk;
     } else if (cp.count.empty()) {
         int64_t nbl;
         if (cp.kind == K_VALU) {   // 64 bra pairs (one per lane) per ket pair
@@ -432,6 +450,7 @@ extern "C" mdx_status mdx_eri_digest_batch(mdx_ctx *c, const mdx_shells *sh, int
                                            void *ws, size_t ws_bytes, mdx_stream_t stream)
 {
     if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_digest_batch: MDX_FUSED applies to plans only");
+    if (flags & MDX_PAIRED) return fail(MDX_EINVAL, "mdx_eri_digest_batch: MDX_PAIRED applies to mdx_eri_batch only");
     ClassPlan cp;
     mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp);
     if (st != MDX_OK) return st;

@@ -8,6 +8,12 @@ template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
 __global__ void __launch_bounds__(64) eri_valu_kernel(EriArgs a)
 {
     int J, I;
+    if (a.diag == 2) {   // paired batch: quartet q = (bra q, ket q), one per lane
+        I = J = blockIdx.x * 64 + (int)threadIdx.x;
+        if (J >= a.nket) return;
+        eri_valu_shellset<LB, LK, NAB, NCD, GB, GK>(a, I, J, a.nbra);
+        return;
+    }
     if (a.diag) {   // diagonal shellsets (I = J) only: lane 0 of block J
         J = blockIdx.x;
         I = J + (int)threadIdx.x;

@@ -144,6 +144,7 @@ mdx_status plan_grad(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra
 {
     int l[4];
     if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_grad_batch: MDX_FUSED applies to plans only");
+    if (flags & MDX_PAIRED) return fail(MDX_EINVAL, "mdx_eri_grad_batch: MDX_PAIRED applies to mdx_eri_batch only");
     mdx_status st = check_class(c, sh, ncentre, nbra, bra, nket, ket, flags, l);
     if (st != MDX_OK) return st;
     empty = nbra == 0 || nket == 0;

@@ -54,7 +54,8 @@ struct EriArgs {
     int tiles_per_J;          // dense tiling: bra tiles (VALU) / 8-pair bra blocks (MFMA)
     const int32_t *tile_off;  // ragged: [nket+1] tiles before each ket pair (VALU tile: 64 bra
                               // pairs, MFMA tile: one), or null
-    int diag;                 // 1: only the diagonal shellsets I = J (one per block)
+    int diag;                 // 1: only the diagonal shellsets I = J (one per block);
+                              // 2 (register kernel): I = J, one per lane
     const double *boys;       // Boys table
     const double *Tket;       // terminal ket matrix [ncart(LK) pad 4][ncolp] (MFMA kernel)
     int ntile_total;          // number of tiles (persistent kernels)

@@ -57,7 +57,8 @@ struct ClassPlan {
     int cart = 0;
     int la = 0, lb = 0, lc = 0, ld = 0;   // caller's
     bool swapped = false;                 // kernel bra = caller ket
-    bool diag = false;                    // only the shellsets I = J (Schwarz factors)
+    bool diag = false;                    // only the shellsets I = J (Schwarz factors, paired batches)
+    bool paired = false;                  // MDX_PAIRED: quartet q = (bra q, ket q), out[q + n*(ab + nab*cd)]
     SidePlan bra, ket;
     EriKey key{};
     KernelKind kind = K_VALU;

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmdx.so")
 
 MDX_OK, MDX_EINVAL, MDX_EUNSUPPORTED, MDX_EWORKSPACE, MDX_ENOMEM, MDX_EDEVICE = range(6)
-MDX_SPHERICAL, MDX_CARTESIAN, MDX_FUSED, MDX_GRADIENT = 0, 1, 2, 4
+MDX_SPHERICAL, MDX_CARTESIAN, MDX_FUSED, MDX_GRADIENT, MDX_PAIRED = 0, 1, 2, 4, 8
 
 _p = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -190,9 +190,10 @@ def boys(x, mmax: int, ctx: Context | None = None):
 
 
 def eri(shells: DeviceShells, ncentre: int, bra, ket, cartesian: bool = False, ctx: Context | None = None,
-        out=None):
+        out=None, paired: bool = False):
     """Dense batch; returns a view of shape [nbra, nab, ncd, nket] over the
-    library's [ij,ab,cd,kl] column-major buffer."""
+    library's [ij,ab,cd,kl] column-major buffer.  paired=True: only the
+    quartets q = (bra q, ket q), a view of shape [n, nab, ncd]."""
     import torch
     dev = shells.center.device
     ctx = ctx or Context.get(dev.index or 0)
@@ -200,7 +201,7 @@ def eri(shells: DeviceShells, ncentre: int, bra, ket, cartesian: bool = False, c
     ket = _pairs(ket)
     nbra, nket = bra.shape[0], ket.shape[0]
     nab, ncd = _class_sizes(shells, ncentre, bra, ket, cartesian)
-    flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
+    flags = (MDX_CARTESIAN if cartesian else MDX_SPHERICAL) | (MDX_PAIRED if paired else 0)
     L = lib()
     wsz = L.mdx_eri_workspace_size(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket,
                                    _i32p(ket), flags)
@@ -212,9 +213,11 @@ def eri(shells: DeviceShells, ncentre: int, bra, ket, cartesian: bool = False, c
     base = _ptr(ws)
     aligned = (base + 255) // 256 * 256
     if out is None:
-        out = torch.empty(nbra * nab * ncd * nket, dtype=torch.float64, device=dev)
+        out = torch.empty((nbra if paired else nbra * nket) * nab * ncd, dtype=torch.float64, device=dev)
     check(L.mdx_eri_batch(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket, _i32p(ket),
                           flags, _ptr(out), ctypes.c_void_p(aligned), wsz, _stream(torch)), "mdx_eri_batch")
+    if paired:
+        return out.view(ncd, nab, nbra).permute(2, 1, 0)
     return out.view(nket, ncd, nab, nbra).permute(3, 2, 1, 0)
 
 

@@ -109,29 +109,32 @@ static int cart_index(int ax, int ay, int az)
 /* Real solid harmonics: closed-form coefficients                      */
 /* C[m+l][cart] = coefficient of x^ax y^ay z^az in S_lm (Racah norm.)  */
 /* ------------------------------------------------------------------ */
-static double fact(int n) { double r = 1; for (int i = 2; i <= n; ++i) r *= i; return r; }
-static double binom(int n, int k)
+/* Built in REAL: the __float128 build then checks the fp64 build's
+ * Cartesian -> solid step too (its coefficients carry no double rounding). */
+static REAL fact(int n) { REAL r = 1; for (int i = 2; i <= n; ++i) r *= i; return r; }
+static REAL binom(int n, int k)
 {
-    if (k < 0 || k > n) return 0.0;
+    if (k < 0 || k > n) return 0;
     return fact(n) / (fact(k) * fact(n - k));
 }
+static REAL ipow(REAL x, int n) { REAL r = 1; for (int i = 0; i < n; ++i) r *= x; return r; }
 
-static void solid_coefs(int l, double C[][OR_MAXCART])
+static void solid_coefs(int l, REAL C[][OR_MAXCART])
 {
     int nc = ncart(l);
     for (int i = 0; i < 2 * l + 1; ++i)
-        for (int j = 0; j < nc; ++j) C[i][j] = 0.0;
+        for (int j = 0; j < nc; ++j) C[i][j] = 0;
     for (int m = -l; m <= l; ++m) {
         int am = m < 0 ? -m : m;
         int wm = m < 0 ? 1 : 0;                     /* 2 v_m */
-        double N = 1.0 / (pow(2.0, am) * fact(l)) *
-                   sqrt(2.0 * fact(l + am) * fact(l - am) / (m == 0 ? 2.0 : 1.0));
+        REAL N = 1 / (ipow(2, am) * fact(l)) *
+                 R_SQRT(2 * fact(l + am) * fact(l - am) / (REAL)(m == 0 ? 2 : 1));
         for (int t = 0; t <= (l - am) / 2; ++t)
             for (int u = 0; u <= t; ++u)
                 for (int w = wm; w <= am; w += 2) {  /* w = 2v */
                     int sgn_exp = t + (w - wm) / 2;
-                    double c = ((sgn_exp & 1) ? -1.0 : 1.0) * pow(0.25, t) *
-                               binom(l, t) * binom(l - t, am + t) * binom(t, u) * binom(am, w);
+                    REAL c = ((sgn_exp & 1) ? -1 : 1) * ipow((REAL)0.25, t) *
+                             binom(l, t) * binom(l - t, am + t) * binom(t, u) * binom(am, w);
                     int ax = 2 * t + am - 2 * u - w;
                     int ay = 2 * u + w;
                     int az = l - 2 * t - am;
@@ -490,7 +493,7 @@ static void cart_quartet(const shell_t *sa, const shell_t *sb, const shell_t *sc
 static void to_solid(int la, int lb, int lc, int ld, const REAL *cart, REAL *sph)
 {
     /* built per call: no shared mutable state between OpenMP threads */
-    double Cs[4][2 * OR_LMAX + 1][OR_MAXCART];
+    REAL Cs[4][2 * OR_LMAX + 1][OR_MAXCART];
     int l4[4] = {la, lb, lc, ld};
     for (int i = 0; i < 4; ++i) solid_coefs(l4[i], Cs[i]);
     int nc4[4], ns4[4];
@@ -512,7 +515,7 @@ static void to_solid(int la, int lb, int lc, int ld, const REAL *cart, REAL *sph
                 for (size_t r = 0; r < inner; ++r) {
                     REAL s = 0;
                     for (int k = 0; k < nin; ++k)
-                        s += (REAL)Cs[ax][m][k] * cur[(o * nin + k) * inner + r];
+                        s += Cs[ax][m][k] * cur[(o * nin + k) * inner + r];
                     nxt[(o * nout + m) * inner + r] = s;
                 }
         dims[ax] = nout;
@@ -562,10 +565,10 @@ void EXPORT(boys)(int n, const double *x, int mmax, double *F)
 /* solid-harmonic coefficients C[(m+l)*ncart(l) + cart] (closed form) */
 void EXPORT(solid_coefs)(int l, double *C)
 {
-    double Cs[2 * OR_LMAX + 1][OR_MAXCART];
+    REAL Cs[2 * OR_LMAX + 1][OR_MAXCART];
     solid_coefs(l, Cs);
     for (int m = 0; m < 2 * l + 1; ++m)
-        for (int k = 0; k < ncart(l); ++k) C[m * ncart(l) + k] = Cs[m][k];
+        for (int k = 0; k < ncart(l); ++k) C[m * ncart(l) + k] = (double)Cs[m][k];
 }
 
 /* 1-D Hermite coefficients E[(i*(lb+1)+j)*(la+lb+1)+t] for one axis */
@@ -607,13 +610,13 @@ void EXPORT(overlap)(int la, int lb, const double *A, const double *B, int Ka, i
         for (int i = 0; i < na * nb; ++i) out[i] = (double)S[i];
         return;
     }
-    double Ca[2 * OR_LMAX + 1][OR_MAXCART], Cb[2 * OR_LMAX + 1][OR_MAXCART];
+    REAL Ca[2 * OR_LMAX + 1][OR_MAXCART], Cb[2 * OR_LMAX + 1][OR_MAXCART];
     solid_coefs(la, Ca); solid_coefs(lb, Cb);
     for (int m = 0; m < nsph(la); ++m)
         for (int n = 0; n < nsph(lb); ++n) {
             REAL s = 0;
             for (int i = 0; i < na; ++i)
-                for (int j = 0; j < nb; ++j) s += (REAL)Ca[m][i] * (REAL)Cb[n][j] * S[i * nb + j];
+                for (int j = 0; j < nb; ++j) s += Ca[m][i] * Cb[n][j] * S[i * nb + j];
             out[m * nsph(lb) + n] = (double)s;
         }
 }
@@ -656,13 +659,13 @@ void EXPORT(kinetic)(int la, int lb, const double *A, const double *B, int Ka, i
         for (int i = 0; i < na * nb; ++i) out[i] = (double)T[i];
         return;
     }
-    double Ca[2 * OR_LMAX + 1][OR_MAXCART], Cb[2 * OR_LMAX + 1][OR_MAXCART];
+    REAL Ca[2 * OR_LMAX + 1][OR_MAXCART], Cb[2 * OR_LMAX + 1][OR_MAXCART];
     solid_coefs(la, Ca); solid_coefs(lb, Cb);
     for (int m = 0; m < nsph(la); ++m)
         for (int n = 0; n < nsph(lb); ++n) {
             REAL s = 0;
             for (int i = 0; i < na; ++i)
-                for (int j = 0; j < nb; ++j) s += (REAL)Ca[m][i] * (REAL)Cb[n][j] * T[i * nb + j];
+                for (int j = 0; j < nb; ++j) s += Ca[m][i] * Cb[n][j] * T[i * nb + j];
             out[m * nsph(lb) + n] = (double)s;
         }
 }
@@ -712,13 +715,13 @@ void EXPORT(nuclear)(int la, int lb, const double *A, const double *B, int Ka, i
         for (int i = 0; i < na * nb; ++i) out[i] = (double)V[i];
         return;
     }
-    double Ca[2 * OR_LMAX + 1][OR_MAXCART], Cb[2 * OR_LMAX + 1][OR_MAXCART];
+    REAL Ca[2 * OR_LMAX + 1][OR_MAXCART], Cb[2 * OR_LMAX + 1][OR_MAXCART];
     solid_coefs(la, Ca); solid_coefs(lb, Cb);
     for (int m = 0; m < nsph(la); ++m)
         for (int n = 0; n < nsph(lb); ++n) {
             REAL s = 0;
             for (int i = 0; i < na; ++i)
-                for (int j = 0; j < nb; ++j) s += (REAL)Ca[m][i] * (REAL)Cb[n][j] * V[i * nb + j];
+                for (int j = 0; j < nb; ++j) s += Ca[m][i] * Cb[n][j] * V[i * nb + j];
             out[m * nsph(lb) + n] = (double)s;
         }
 }

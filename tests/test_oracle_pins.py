@@ -423,3 +423,41 @@ def test_cluster_fp64_within_schwarz_scaled_bar():
         ref, scale = T.oracle_batch(b, bt, quad=True)
         f64, _ = T.oracle_batch(b, bt, quad=False)
         T.assert_close_cs(f64, ref, scale, bt["name"])
+
+
+def _abs_row_sums(l):
+    """sum_k |C[m, k]| of each real solid harmonic's Cartesian expansion"""
+    return np.abs(O.solid_coefs(l, quad=True)).sum(axis=1)
+
+
+@pytest.mark.parametrize("name,nbra,nket", [("(gg|gg)", 3, 2), ("(hh|hh)", 2, 1), ("(ii|ii)", 1, 1),
+                                            ("(g|dd)", 6, 5), ("(h|dd)", 6, 5), ("(i|dd)", 6, 5)])
+def test_fp64_vs_quad_oracle_high_l(name, nbra, nket):
+    """The fp64 oracle against its __float128 build (whose Cartesian-to-solid
+    coefficients are formed in __float128 as well, Eqs. (18)-(19)) on high-L
+    classes, primitive shells of the high-L workload (exponents 0.1..20, 4 A box).
+
+    Cartesian: within 1e-13 of each shellset's largest element.  Solid: the
+    transform sums Cartesian values of up to ~1e3 times the size of the solid
+    result (the spherical part of an l = 6 shell far from the ket is a high
+    multipole), so its fp64 rounding is bounded by the transform of the
+    Cartesian magnitudes: per element |err| <= 4e-15 * prod_s (sum_k |C_s[m,k]|)
+    * max|cart|.  The shellset-relative error is also held below 1e-10."""
+    b = W.config4(name, nbra=nbra, nket=nket, seed=24)
+    la, lb, lc, ld = W.parse_class(name)
+    lb = max(lb, 0)
+    cq = O.eri(b.basis, b.ncentre, b.bra, b.ket, cartesian=True, quad=True)
+    c64 = O.eri(b.basis, b.ncentre, b.bra, b.ket, cartesian=True)
+    cmax = np.abs(cq).max(axis=(1, 2))                               # [nbra, nket]
+    assert np.all(np.abs(c64 - cq).max(axis=(1, 2)) <= 1e-13 * cmax), name
+    sq = O.eri(b.basis, b.ncentre, b.bra, b.ket, quad=True)
+    s64 = O.eri(b.basis, b.ncentre, b.bra, b.ket)
+    rab = np.multiply.outer(_abs_row_sums(la), _abs_row_sums(lb)).reshape(-1)
+    rcd = np.multiply.outer(_abs_row_sums(lc), _abs_row_sums(ld)).reshape(-1)
+    bound = 4e-15 * rab[None, :, None, None] * rcd[None, None, :, None] * cmax[:, None, None, :]
+    err = np.abs(s64 - sq)
+    assert np.all(err <= bound), (name, float(np.max(err / bound)))
+    smax = np.abs(sq).max(axis=(1, 2))
+    rel = err.max(axis=(1, 2)) / smax
+    assert rel.max() <= 1e-10, (name, float(rel.max()))
+    print(name, "fp64 vs quad, solid: max err / shellset max %.2e" % rel.max())

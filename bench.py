@@ -8,7 +8,9 @@ K = 3 per shell, exponents log-uniform in [0.05, 50], coefficients uniform in
 [0.1, 1], centres uniform in a 10 A cube (seed 0).  Inputs are resident in HBM
 before the timed region; outputs are written to HBM every step.
 
-Prints one JSON line (see the keys at the end of main()).
+Prints one compact JSON line on stdout (compact_record: headline, roofline,
+CPU baseline, parity and one-number summaries of the other legs) and writes
+the full record of every leg to --detail-out.
 """
 from __future__ import annotations
 
@@ -389,6 +391,9 @@ def cluster_leg(native, ctx, torch, reps, sample, tune=True):
     tuned = autotune.tune_batches(ctx, sh, batches) if tune else {}
     log(f"cluster tuning: { {k: v[0] for k, v in tuned.items()} }")
     fused = native.Plan(sh, nb, fused=True)
+    # the same per-batch launches as `plain`, with the tuned kernels: fusion
+    # alone is plain_tuned / fused
+    plain_tuned = native.Plan(sh, nb, fused=False) if tuned else None
     for name, (best, _) in tuned.items():   # back to the defaults for everything after this leg
         la, lb = (int(x) for x in b.l[next(bt for bt in batches if bt["name"] == name)["bra"][0]])
         lc, ld = (int(x) for x in b.l[next(bt for bt in batches if bt["name"] == name)["ket"][0]])
@@ -414,6 +419,7 @@ def cluster_leg(native, ctx, torch, reps, sample, tune=True):
 
     t_plain = timed(plain, o_plain)
     t_fused = timed(fused, o_fused)
+    t_plain_tuned = timed(plain_tuned, o_plain) if plain_tuned is not None else None
     identical = bool(torch.equal(o_plain, o_fused))        # expected only where tuning kept the default kernels
     max_diff = float((o_plain - o_fused).abs().max())
     log(f"cluster: plain {min(t_plain):.2f} ms, fused {min(t_fused):.2f} ms")
@@ -433,7 +439,7 @@ def cluster_leg(native, ctx, torch, reps, sample, tune=True):
     # stratified parity sample against the __float128 oracle
     rng = np.random.default_rng(11)
     out_h = None
-    nchk = nbad = 0
+    nchk = nbad = nqq_only = 0
     worst_cs = 0.0
     for bt in batches:
         cnt = bt["bra_count"]
@@ -451,9 +457,11 @@ def cluster_leg(native, ctx, torch, reps, sample, tune=True):
                + cnt[ks][:, None, None] * (ab[None] + nab * cd[None]))
         got = o_fused[torch.as_tensor(idx.reshape(-1), device="cuda")].cpu().numpy().reshape(ref.shape)
         err = np.abs(got - ref)
-        ok = (err <= ATOL) | (err <= RTOL * np.abs(ref)) | (err <= 1e-12 * qq[:, None, None])
+        g13 = (err <= ATOL) | (err <= RTOL * np.abs(ref))
+        ok = g13 | (err <= 1e-12 * qq[:, None, None])
         nchk += ok.size
         nbad += int(np.count_nonzero(~ok))
+        nqq_only += int(np.count_nonzero(ok & ~g13))
         worst_cs = max(worst_cs, float(np.max(err / qq[:, None, None])))
     best_f, best_p = min(t_fused), min(t_plain)
     return {
@@ -464,13 +472,17 @@ def cluster_leg(native, ctx, torch, reps, sample, tune=True):
         "output_gb": total * 8 / 1e9,
         "schwarz_ms": schwarz_ms,
         "plain_ms": best_p, "fused_ms": best_f, "plain_ms_all": t_plain, "fused_ms_all": t_fused,
-        "fused_speedup": best_p / best_f, "outputs_identical": identical, "max_abs_diff_plain_fused": max_diff,
+        "plain_tuned_ms": min(t_plain_tuned) if t_plain_tuned else None, "plain_tuned_ms_all": t_plain_tuned,
+        "fused_speedup": best_p / best_f,
+        "fusion_only_speedup": min(t_plain_tuned) / best_f if t_plain_tuned else None,
+        "outputs_identical": identical, "max_abs_diff_plain_fused": max_diff,
         "fused_tuning": {k: {"variant": v[0], "ms": {str(a): t for a, t in v[1].items()}} for k, v in tuned.items()},
         "plain_uses": "default kernel choice per class",
         "shellsets_per_s_fused": nquart / (best_f * 1e-3),
         "algorithmic_gflop": flops / 1e9, "fused_tflops": flops / (best_f * 1e-3) / 1e12,
         "pct_fp64_peak_fused": 100 * flops / (best_f * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,
-        "parity_sample": {"checked": nchk, "failed": nbad, "max_err_over_QQ": worst_cs, "reference": "__float128 oracle",
+        "parity_sample": {"checked": nchk, "failed": nbad, "passed_only_by_QQ_clause": nqq_only,
+                          "max_err_over_QQ": worst_cs, "reference": "__float128 oracle",
                           "tolerance": "|err| <= 1e-12 or <= 1e-10 |ref| or <= 1e-12 Q_ab Q_cd",
                           "sample": f"up to {sample} quartets per class, uniform"},
         "per_class_quartets": {n: sum(bt["quartets"] for bt in batches if bt["name"] == n)
@@ -483,6 +495,49 @@ def class_flops(batch):
     la, lb, lc, ld = W.parse_class(batch.name)
     K = int(batch.basis.nprim[0])
     return F.shellset_flops(la, lb, lc, ld, K, K if lb >= 0 else 1, K, K if ld >= 0 else 1)
+
+
+def cpu_model():
+    """CPU model name of this host (from /proc/cpuinfo)"""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+_SINGLE_THREAD = """
+import json, sys, time
+sys.path.insert(0, {root!r})
+from oracle import oracle as O
+from paper_2506_12501_amd import workloads as W
+n, t = 0, 0.0
+for name in {names!r}:
+    b = W.config2(name, npair={npair}, seed=0)
+    bra, ket = b.bra[:{m}], b.ket[:{m}]
+    t0 = time.perf_counter()
+    O.eri(b.basis, b.ncentre, bra, ket)
+    t += time.perf_counter() - t0
+    n += bra.shape[0] * ket.shape[0]
+print(json.dumps({{"shellsets": n, "seconds": t}}))
+"""
+
+
+def cpu_single_thread(names, npair, m):
+    """The oracle on one thread (a child process with OMP_NUM_THREADS=1 that
+    touches no GPU) over the first m x m shellsets of each class."""
+    import subprocess
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _SINGLE_THREAD.format(root=ROOT, names=list(names), npair=npair, m=m)],
+                       capture_output=True, text=True, env=env, timeout=600)
+    if r.returncode != 0:
+        log("single-thread oracle run failed: " + r.stderr[-500:])
+        return None
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": d["shellsets"] / d["seconds"], "cores": 1,
+            "sample": f"{m}x{m} shellsets of each class, {d['shellsets']} shellsets, {d['seconds']:.1f} s"}
 
 
 def cpu_baseline(runs, sample_pairs):
@@ -510,6 +565,7 @@ def cpu_baseline(runs, sample_pairs):
         worst_abs = max(worst_abs, float(err.max()))
         worst_rel = max(worst_rel, float(np.max(err / np.maximum(np.abs(ref), 1e-300) * (err > ATOL))))
     return {"value": total_n / total_t, "unit": "shellsets/s", "cores": nthreads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{sample_pairs}x{sample_pairs} shellsets of each class (first pairs of the workload), "
                       f"{total_n} shellsets, {total_t:.1f} s"}, \
            {"checked": nchk, "failed": nbad, "max_abs_err": worst_abs, "max_rel_err_above_atol": worst_rel,
@@ -541,6 +597,68 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def _r(x, sig=5):
+    """round floats (recursively) to `sig` significant digits for the compact line"""
+    if isinstance(x, float):
+        return float(f"{x:.{sig}g}")
+    if isinstance(x, dict):
+        return {k: _r(v, sig) for k, v in x.items()}
+    if isinstance(x, (list, tuple)):
+        return [_r(v, sig) for v in x]
+    return x
+
+
+COMPACT_MAX_BYTES = 4096
+
+
+def compact_record(full, detail_path=None):
+    """The one JSON line printed on stdout: the headline keys, the roofline of
+    the dominant kernel, the CPU baseline, parity and one-number summaries of
+    the other legs (their full records go to the detail file)."""
+    keys = ("metric", "value", "unit", "n_gpus", "steps", "warmup", "ms_per_step", "higher_is_better", "scaling",
+            "vs_baseline", "dtype", "data", "config", "step_tflops_algorithmic", "step_pct_fp64_peak", "roofline",
+            "cpu_baseline")
+    rec = {k: full.get(k) for k in keys}
+    rec["per_class"] = {n: {k: c[k] for k in ("kernel_ms", "pct_fp64_peak", "shellsets_per_s_kernel")}
+                        for n, c in (full.get("per_class") or {}).items()}
+    if full.get("parity_sample"):
+        p = full["parity_sample"]
+        rec["parity_sample"] = {k: p[k] for k in ("checked", "failed", "max_abs_err")}
+    cl = full.get("mixed_cluster")
+    if cl:
+        rec["mixed_cluster"] = {k: cl.get(k) for k in ("quartets", "plain_ms", "plain_tuned_ms", "fused_ms",
+                                                        "fused_speedup", "fusion_only_speedup",
+                                                        "pct_fp64_peak_fused")}
+        ps = cl["parity_sample"]
+        rec["mixed_cluster"]["parity"] = {k: ps.get(k) for k in ("checked", "failed", "passed_only_by_QQ_clause",
+                                                                 "max_err_over_QQ")}
+    ex = full.get("extras") or {}
+    summ = {}
+    if "gradient" in ex:
+        summ["gradient_pct_fp64_peak"] = ex["gradient"]["pct_fp64_peak"]
+        summ["gradient_ms_per_call"] = ex["gradient"]["ms_per_call"]
+    if "high_l" in ex:
+        summ["high_l_pct_fp64_peak"] = {n: v["pct_fp64_peak"] for n, v in ex["high_l"].items()}
+    if "sp_hbm" in ex:
+        summ["sp_hbm_frac"] = {n: v["hbm_frac"] for n, v in ex["sp_hbm"].items()}
+    if "digest" in ex:
+        summ["digest_kernel_ms"] = {n: v["kernel_ms"] for n, v in ex["digest"].items()}
+    if "one_body" in ex:
+        summ["one_body_pct_fp64_peak"] = {n: v["pct_fp64_peak"] for n, v in ex["one_body"].items()}
+    if "nuclear" in ex:
+        summ["nuclear_kernel_ms"] = {n: v["kernel_ms"] for n, v in ex["nuclear"].items()}
+    if summ:
+        rec["extras_summary"] = summ
+    rec["detail"] = detail_path
+    rec = _r(rec)
+    # keep the line short: drop the largest summaries first if it ever grows
+    for k in ("nuclear_kernel_ms", "digest_kernel_ms", "one_body_pct_fp64_peak", "sp_hbm_frac"):
+        if len(json.dumps(rec, separators=(",", ":"))) <= COMPACT_MAX_BYTES:
+            break
+        rec.get("extras_summary", {}).pop(k, None)
+    return rec
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -559,6 +677,10 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many MiB device-to-device (HBM counter calibration)")
     ap.add_argument("--classes", default=None, help="comma-separated subset of the workload's classes")
+    ap.add_argument("--detail-out", default=os.path.join("gpurun_out", "bench_detail.json"),
+                    help="file for the full record of every leg (the stdout line is a compact summary)")
+    ap.add_argument("--cpu-single-sample", type=int, default=24,
+                    help="m: the single-thread oracle times m x m shellsets of each class")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -656,6 +778,7 @@ def main():
     cpu, parity = (None, None)
     if not args.no_cpu:
         cpu, parity = cpu_baseline(runs, args.cpu_sample)
+        cpu["single_thread"] = cpu_single_thread(names, args.npair, args.cpu_single_sample)
         log("cpu baseline done")
 
     total_flops = sum(class_flops(r.batch) * r.n for r in runs)
@@ -686,7 +809,21 @@ def main():
         "mixed_cluster": cluster,
         "wall_s_timed": wall,
     }
-    print(json.dumps(rec), flush=True)
+    detail = None
+    if args.detail_out:
+        try:
+            os.makedirs(os.path.dirname(os.path.abspath(args.detail_out)), exist_ok=True)
+            with open(args.detail_out, "w") as f:
+                json.dump(rec, f, indent=1)
+            detail = args.detail_out
+        except OSError as e:
+            log(f"could not write {args.detail_out}: {e}")
+    if extras:
+        for leg, v in extras.items():
+            log(f"{leg}: " + json.dumps(_r(v, 4))[:2000])
+    if cluster:
+        log("mixed_cluster: " + json.dumps(_r({k: v for k, v in cluster.items() if k != "fused_tuning"}, 4))[:2000])
+    print(json.dumps(compact_record(rec, detail), separators=(",", ":")), flush=True)
 
 
 if __name__ == "__main__":

@@ -145,9 +145,9 @@ __global__ void __launch_bounds__(64) onebody_kernel(OneBodyArgs a)
             double s1[3][LA + 1][LB + 1], t1[3][LA + 1][LB + 1];
 #pragma unroll
             for (int ax = 0; ax < 3; ++ax) {
-                const double P = (za * A[ax] + zb * B[ax]) / p;
+                // X_PA, X_PB from centre differences: exactly 0 on one centre
                 double E0[LA + 1][LB + 3];
-                e0_axis<LA, LB + 2>(p, P - A[ax], P - B[ax], E0);
+                e0_axis<LA, LB + 2>(p, zb / p * (B[ax] - A[ax]), za / p * (A[ax] - B[ax]), E0);
 #pragma unroll
                 for (int ia = 0; ia <= LA; ++ia)
 #pragma unroll
@@ -271,8 +271,9 @@ __global__ void __launch_bounds__(64 * G) nuclear_kernel(NuclearArgs a)
             for (int kb = 0; kb < pr.kb; ++kb) {
                 const double zb = a.expo[pr.offb + kb], cb = a.coef[pr.offb + kb];
                 const double p = za + zb, rp = 1.0 / p;
-                const double P[3] = {(za * A[0] + zb * B[0]) * rp, (za * A[1] + zb * B[1]) * rp,
-                                     (za * A[2] + zb * B[2]) * rp};
+                // P = A + (zeta_b/p)(B - A): exactly A on one centre
+                const double P[3] = {A[0] + zb * rp * (B[0] - A[0]), A[1] + zb * rp * (B[1] - A[1]),
+                                     A[2] + zb * rp * (B[2] - A[2])};
                 // sum_I q_I [r]_I^(0) over this wave's charges, Eqs. (26), (30),
                 // before any transform (Eq. (37))
                 double Rs[NH];
@@ -300,7 +301,7 @@ __global__ void __launch_bounds__(64 * G) nuclear_kernel(NuclearArgs a)
                 // E coefficients of the pair and the bra transform, Eq. (34)
                 double E[3][LA + 1][LB + 1][L + 1];
 #pragma unroll
-                for (int ax = 0; ax < 3; ++ax) e_axis<LA, LB>(0.5 * rp, P[ax] - A[ax], P[ax] - B[ax], E[ax]);
+                for (int ax = 0; ax < 3; ++ax) e_axis<LA, LB>(0.5 * rp, zb * rp * (B[ax] - A[ax]), za * rp * (A[ax] - B[ax]), E[ax]);
                 const double f = -ca * cb * exp(-za * zb * rp * AB2);
 #pragma unroll
                 for (int i = 0; i < NA; ++i)

@@ -139,8 +139,9 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
     const double i2p = 0.5 / p;
     if (threadIdx.x < 3) {
         const int ax = threadIdx.x;
-        const double P = (za * Av[ax] + zb * B[ax]) / p;
-        const double XPA = P - Av[ax], XPB = P - B[ax];
+        // X_PA = (zeta_b/p)(B - A) and X_PB = (zeta_a/p)(A - B): both exactly 0
+        // when the two centres coincide (P - A formed from a rounded P is not)
+        const double XPA = zb / p * (B[ax] - Av[ax]), XPB = za / p * (Av[ax] - B[ax]);
         // Eqs. (10), (11) with E^0_00 = 1 (the exponential is applied below)
         E(ax, 0, 0, 0) = 1.0;
         // the derivative-bra role also needs a+1 and b+1 (d/dA of Eq. (1))
@@ -169,9 +170,11 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         sh_pref = g.role != 1 ? 2.0 * 17.493418327624862 * pref : pref;
         PrimRec r{};
         r.p = valid ? p : 1.0;
-        r.Px = (za * Av[0] + zb * B[0]) / p;
-        r.Py = (za * Av[1] + zb * B[1]) / p;
-        r.Pz = (za * Av[2] + zb * B[2]) / p;
+        // P = A + (zeta_b/p)(B - A): exactly A on one centre, so P - Q of two
+        // one-centre pairs on the same atom is exactly 0
+        r.Px = Av[0] + zb / p * (B[0] - Av[0]);
+        r.Py = Av[1] + zb / p * (B[1] - Av[1]);
+        r.Pz = Av[2] + zb / p * (B[2] - Av[2]);
         r.ws = valid ? 1.0 : 0.0;
         // terminal weight (-1)^L K c c / (zeta_q (2 zeta_q)^L), Eqs. (17), (40)
         r.wt = valid ? ((g.L & 1) ? -1.0 : 1.0) * pref * pow(2.0 * p, -(double)g.L) : 0.0;

@@ -1,20 +1,30 @@
-"""Integral parity, GPU vs CPU oracle: classes on the matrix-core kernel."""
+"""Integral parity, GPU vs CPU oracle: classes on the matrix-core kernel.
+
+Classes with a shell of l >= 4 are held to the __float128 oracle: the fp64
+oracle's own solid-harmonic transform loses up to ~3e-11 of the shellset
+maximum there (pinned in test_oracle_pins.py).  Contracted (hh|hh) stays on
+the fp64 oracle (the quad build needs minutes per contracted shellset); its
+primitive (hh|hh) is pinned to 1.4e-13 of the shellset maximum."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_2506_12501_amd import workloads as W
-from tests.gpu_util import assert_close
+from tests.gpu_util import assert_close, assert_close_shellsets
 
 pytestmark = pytest.mark.gpu
 
 
-def run(batch, cartesian=False):
+def run(batch, cartesian=False, quad=False):
     from paper_2506_12501_amd import native
     sh = native.DeviceShells(batch.basis)
     got = native.eri(sh, batch.ncentre, batch.bra, batch.ket, cartesian=cartesian).cpu().numpy()
-    ref = O.eri(batch.basis, batch.ncentre, batch.bra, batch.ket, cartesian=cartesian)
+    ref = O.eri(batch.basis, batch.ncentre, batch.bra, batch.ket, cartesian=cartesian, quad=quad)
     return got, ref
+
+
+def high_l(name):
+    return max(W.parse_class(name)) >= 4
 
 
 @pytest.mark.parametrize("name", ["(dd|dd)", "(pd|dd)", "(dp|dd)", "(dd|pd)"])
@@ -41,15 +51,15 @@ def test_dddd_cartesian():
 @pytest.mark.parametrize("name", ["(ff|ff)", "(gg|gg)", "(hh|hh)"])
 def test_config4_high_l(name):
     b = W.config4(name, nbra=4, nket=3, seed=24)
-    got, ref = run(b)
-    assert_close(got, ref, name)
+    got, ref = run(b, quad=high_l(name))
+    assert_close_shellsets(got, ref, name)
 
 
 def test_iiii_single_primitive():
     """l = 6 per shell, L = 24: the single-primitive kernel with its bra rows in two parts"""
     b = W.config4("(ii|ii)", nbra=3, nket=2, seed=29)
-    got, ref = run(b)
-    assert_close(got, ref, "(ii|ii)")
+    got, ref = run(b, quad=True)
+    assert_close_shellsets(got, ref, "(ii|ii)")
 
 
 def test_iiii_contracted_is_refused():
@@ -65,27 +75,27 @@ def test_hhhh_contracted():
     """l = 5 per shell, K = 2: two primitive quartets per sweep chunk, L = 20"""
     b = W.make_class_batch("(hh|hh)", 2, 2, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=27)
     got, ref = run(b)
-    assert_close(got, ref, "(hh|hh) K=2")
+    assert_close_shellsets(got, ref, "(hh|hh) K=2")
 
 
 def test_hhhh_three_primitives():
     """K = 3: nine bra primitive quartets pass through LDS two at a time"""
     b = W.make_class_batch("(hh|hh)", 1, 2, 3, 4.0, 0.1, 20.0, 0.1, 1.0, seed=28)
     got, ref = run(b)
-    assert_close(got, ref, "(hh|hh) K=3")
+    assert_close_shellsets(got, ref, "(hh|hh) K=3")
 
 
 @pytest.mark.parametrize("name", ["(d|dd)", "(f|dd)", "(g|dd)", "(h|dd)", "(i|dd)"])
 def test_config4_three_centre(name):
     b = W.config4(name, nbra=6, nket=5, seed=25)
-    got, ref = run(b)
-    assert_close(got, ref, name)
+    got, ref = run(b, quad=True)
+    assert_close_shellsets(got, ref, name)
 
 
 def test_contracted_three_centre_aux():
     # contracted aux shell: primitives summed into [0]^(m) before the recursion
     b = W.make_class_batch("(f|dd)", 5, 3, 4, 5.0, 0.1, 20.0, 0.1, 1.0, seed=26)
-    got, ref = run(b)
+    got, ref = run(b, quad=True)
     assert_close(got, ref, "(f|dd) K=4")
 
 

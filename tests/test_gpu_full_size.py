@@ -9,7 +9,7 @@ import pytest
 from oracle import oracle as O
 from paper_2506_12501_amd import screening as S, workloads as W
 from tests.cluster_util import oracle_Q
-from tests.gpu_util import ATOL, RTOL, assert_close
+from tests.gpu_util import ATOL, RTOL, assert_close, assert_close_shellsets
 
 pytestmark = pytest.mark.gpu
 
@@ -23,7 +23,7 @@ def sample_quartets(nbra, nket, n, seed):
     return q
 
 
-def check_sampled(batch, n=96, seed=0):
+def check_sampled(batch, n=96, seed=0, quad=False):
     from paper_2506_12501_amd import native
     sh = native.DeviceShells(batch.basis)
     out = native.eri(sh, batch.ncentre, batch.bra, batch.ket)      # [nbra, nab, ncd, nket] view
@@ -31,8 +31,8 @@ def check_sampled(batch, n=96, seed=0):
     idx = (np.asarray(q[:, 0]), np.asarray(q[:, 1]))
     import torch
     got = out[torch.as_tensor(idx[0], device=out.device), :, :, torch.as_tensor(idx[1], device=out.device)]
-    ref = O.eri(batch.basis, batch.ncentre, batch.bra, batch.ket, quartets=q)    # [q, nab, ncd]
-    assert_close(got.cpu().numpy(), ref, f"{batch.name} full size, {n} sampled shellsets")
+    ref = O.eri(batch.basis, batch.ncentre, batch.bra, batch.ket, quartets=q, quad=quad)    # [q, nab, ncd]
+    assert_close_shellsets(got.cpu().numpy(), ref, f"{batch.name} full size, {n} sampled shellsets")
 
 
 @pytest.mark.parametrize("name", W.C1_CLASSES)
@@ -60,12 +60,17 @@ def test_contracted_classes(name):
 
 @pytest.mark.parametrize("name", W.C4_CLASSES_4C + W.C4_CLASSES_3C + W.HIGH_L_CLASSES_4C)
 def test_high_l_classes(name):
-    check_sampled(W.config4(name, seed=0), n=48, seed=2)
+    # l >= 4 against the __float128 oracle (the fp64 oracle's solid transform
+    # loses up to ~3e-11 of the shellset maximum there); (ii|ii) costs ~25 s of
+    # quad work per shellset, so it is sampled more thinly
+    quad = max(W.parse_class(name)) >= 4
+    check_sampled(W.config4(name, seed=0), n=16 if name == "(ii|ii)" else 48, seed=2, quad=quad)
 
 
 def test_water_cluster_plan_sampled():
     """the whole screened 384-shell cluster in one fused plan (contraction-degree
-    batches) against the __float128 oracle on sampled quartets of every batch"""
+    batches) against the __float128 oracle on sampled quartets of every batch,
+    per element within 1e-12 abs or 1e-10 rel (no Cauchy-Schwarz clause)"""
     import torch
     from paper_2506_12501_amd import native
     b, _ = W.water_cluster(seed=0)
@@ -94,7 +99,8 @@ def test_water_cluster_plan_sampled():
                + cnt[ks][:, None, None] * (ab[None] + nab * cd[None]))
         got = out[torch.as_tensor(idx.reshape(-1), device=out.device)].cpu().numpy().reshape(ref.shape)
         err = np.abs(got - ref)
-        ok = (err <= ATOL) | (err <= RTOL * np.abs(ref)) | (err <= 1e-12 * qq[:, None, None])
+        # plain per-element bar: one-centre symmetry zeros come out exactly 0
+        ok = (err <= ATOL) | (err <= RTOL * np.abs(ref))
         assert ok.all(), (bt["name"], bt["Kbra"], bt["Kket"], float(np.max(err / qq[:, None, None])))
         nchk += ok.size
     print("cluster: batches", len(batches), "elements checked", nchk)

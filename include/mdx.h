@@ -27,7 +27,8 @@
  *    every buffer; outputs are overwritten (the J blocks of
  *    mdx_eri_digest_batch are the one exception: accumulated).  Apart from
  *    mdx_create and mdx_plan_create no call allocates device memory: scratch
- *    lives in the caller's workspace.
+ *    lives in the caller's workspace (mdx_eri_batch_noalloc: in a static
+ *    device buffer of the library).
  *  - On any error no kernel is launched and no output is written.
  *  - One mdx_ctx per device and per host thread (a context is not
  *    thread-safe).  No C++ exception crosses this interface.
@@ -142,6 +143,25 @@ size_t mdx_eri_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int ncentr
 mdx_status mdx_eri_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
                          const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
                          double *out, void *ws, size_t ws_bytes, mdx_stream_t stream);
+
+/*
+ * mdx_eri_batch for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same batch, layouts, flags, limits and errors as mdx_eri_batch, with
+ * the workspace taken from a library-owned static device buffer of
+ * MDX_NOALLOC_SCRATCH_BYTES bytes per device instead of a caller argument.
+ * The call allocates nothing (no hipMalloc, hipFree or allocating library
+ * routine).  A batch whose workspace (mdx_eri_workspace_size) exceeds the
+ * buffer returns MDX_EWORKSPACE before any launch; split it, or use
+ * mdx_eri_batch.  Every call on a device shares that device's buffer: calls
+ * that overlap in time on one device (different streams, or host threads)
+ * race on it; calls in one stream are ordered and safe.  The buffer is set up
+ * by mdx_create and lives until the process ends.
+ */
+#define MDX_NOALLOC_SCRATCH_BYTES (64u << 20)
+mdx_status mdx_eri_batch_noalloc(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
+                                 const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
+                                 double *out, mdx_stream_t stream);
 
 /*
  * The "consume" use of a dense batch (Sec. 3.1: integrals feed a contraction

@@ -444,6 +444,29 @@ extern "C" mdx_status mdx_eri_batch(mdx_ctx *c, const mdx_shells *sh, int ncentr
     return enqueue_class(c, sh, cp, L, (char *)ws, out, (hipStream_t)stream, true);
 }
 
+extern "C" mdx_status mdx_eri_batch_noalloc(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra,
+                                            const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
+                                            double *out, mdx_stream_t stream)
+{
+    if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_batch_noalloc: MDX_FUSED applies to plans only");
+    ClassPlan cp;
+    mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp);
+    if (st != MDX_OK) return st;
+    if (nbra == 0 || nket == 0) return MDX_OK;
+    if (!out) return fail(MDX_EINVAL, "mdx_eri_batch_noalloc: null output");
+    if (!c->scratch) return fail(MDX_EDEVICE, "mdx_eri_batch_noalloc: the context has no static scratch");
+    const WsLayout L = ws_layout(cp, 0);
+    if (L.total > (size_t)MDX_NOALLOC_SCRATCH_BYTES)
+        return fail(MDX_EWORKSPACE,
+                    "mdx_eri_batch_noalloc: the batch needs %zu bytes of scratch, the static buffer holds %zu "
+                    "(split the batch, or use mdx_eri_batch with a workspace)",
+                    L.total, (size_t)MDX_NOALLOC_SCRATCH_BYTES);
+    HIP_TRY2(hipSetDevice(c->device));
+    // the same planning, tables and kernels as mdx_eri_batch; nothing in the
+    // scratch needs to start at zero (the workspace contract of mdx_eri_batch)
+    return enqueue_class(c, sh, cp, L, c->scratch, out, (hipStream_t)stream, true);
+}
+
 extern "C" mdx_status mdx_eri_digest_batch(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra,
                                            const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
                                            const double *Dbra, const double *Dket, double *Jbra, double *Jket,

@@ -1,6 +1,7 @@
 // mdx.cpp -- host runtime behind include/mdx.h: validation, planning, pair-data
 // and integral launches.  No device allocation happens inside a call; all
-// scratch lives in the caller's workspace.
+// scratch lives in the caller's workspace, or, for mdx_eri_batch_noalloc, in a
+// static device buffer defined here.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -129,6 +130,31 @@ void solid_tables(std::vector<std::vector<double>> &out)   // out[l] = [nsph][nc
 // ---------------------------------------------------------------------------
 // context
 // ---------------------------------------------------------------------------
+// Scratch of mdx_eri_batch_noalloc: one copy per device, alive until the
+// process ends.  Host code must never use this name as a device address (on
+// the host it is only a stand-in); its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static __device__ __align__(256) unsigned char scratch[MDX_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex scratch_mu;
+static std::map<int, char *> scratch_addr;   // device -> device address of `scratch`
+
+static hipError_t scratch_of_device(int device, char **ptr)
+{
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    auto it = scratch_addr.find(device);
+    if (it != scratch_addr.end()) {
+        *ptr = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));   // the current device's copy
+    if (e != hipSuccess) return e;
+    scratch_addr[device] = (char *)p;
+    *ptr = (char *)p;
+    return hipSuccess;
+}
+
 extern "C" mdx_status mdx_create(int device, mdx_ctx **out)
 {
     if (!out) return fail(MDX_EINVAL, "mdx_create: null output pointer");
@@ -145,6 +171,13 @@ extern "C" mdx_status mdx_create(int device, mdx_ctx **out)
     if (!c) return fail(MDX_ENOMEM, "mdx_create: out of host memory");
     c->device = device;
     c->ncu = prop.multiProcessorCount;
+    {
+        const hipError_t es = scratch_of_device(device, &c->scratch);   // device is current (hipSetDevice above)
+        if (es != hipSuccess) {
+            delete c;
+            return fail(MDX_EDEVICE, "mdx_create: static scratch of device %d: %s", device, hipGetErrorString(es));
+        }
+    }
     // Boys table
     const size_t nb = sizeof(mdx_boys_table_host);
     hipError_t e = hipMalloc((void **)&c->boys, nb);

@@ -26,6 +26,7 @@ struct mdx_ctx {
     size_t tket1_off[2][7] = {};
     std::map<std::tuple<int, int, int, int, int, int>, int> variant;        // autotuner overrides
     std::map<std::tuple<int, int, int, int, int, int>, int> grad_variant;   // same, backward kernel
+    char *scratch = nullptr;     // device address of the static scratch buffer (mdx_eri_batch_noalloc)
     std::vector<hipEvent_t> prof_events;   // profiling hook (pairs)
     size_t prof_count = 0;
 };

@@ -18,6 +18,7 @@ LIBPATH = os.path.join(HERE, "libmdx.so")
 
 MDX_OK, MDX_EINVAL, MDX_EUNSUPPORTED, MDX_EWORKSPACE, MDX_ENOMEM, MDX_EDEVICE = range(6)
 MDX_SPHERICAL, MDX_CARTESIAN, MDX_FUSED, MDX_GRADIENT, MDX_PAIRED = 0, 1, 2, 4, 8
+MDX_NOALLOC_SCRATCH_BYTES = 64 << 20     # static scratch of mdx_eri_batch_noalloc, per device
 
 _p = ctypes.c_void_p
 _i32 = ctypes.c_int32
@@ -53,6 +54,8 @@ EXPORTS = {
                                                  _i32, _pi32, ctypes.c_int]),
     "mdx_eri_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32, _pi32,
                                      ctypes.c_int, _p, _p, ctypes.c_size_t, _p]),
+    "mdx_eri_batch_noalloc": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32,
+                                             _pi32, ctypes.c_int, _p, _p]),
     "mdx_eri_digest_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32, _pi32,
                                             ctypes.c_int, _p, _p, _p, _p, _p, ctypes.c_size_t, _p]),
     "mdx_eri_grad_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32,
@@ -219,6 +222,30 @@ def eri(shells: DeviceShells, ncentre: int, bra, ket, cartesian: bool = False, c
     if paired:
         return out.view(ncd, nab, nbra).permute(2, 1, 0)
     return out.view(nket, ncd, nab, nbra).permute(3, 2, 1, 0)
+
+
+def eri_noalloc(shells: DeviceShells, ncentre: int, bra, ket, out, cartesian: bool = False,
+                ctx: Context | None = None, paired: bool = False):
+    """mdx_eri_batch_noalloc into the caller's `out` (a device tensor of at
+    least nbra*nket*nab*ncd doubles, or nbra*nab*ncd with paired=True); the
+    library's static scratch replaces the workspace.  Returns the same view
+    as eri()."""
+    import torch
+    dev = shells.center.device
+    ctx = ctx or Context.get(dev.index or 0)
+    bra = _pairs(bra)
+    ket = _pairs(ket)
+    nbra, nket = bra.shape[0], ket.shape[0]
+    nab, ncd = _class_sizes(shells, ncentre, bra, ket, cartesian)
+    n = (nbra if paired else nbra * nket) * nab * ncd
+    if out.dtype != torch.float64 or out.device != dev or not out.is_contiguous() or out.numel() < n:
+        raise ValueError(f"out must be a contiguous float64 tensor of >= {n} elements on {dev}")
+    flags = (MDX_CARTESIAN if cartesian else MDX_SPHERICAL) | (MDX_PAIRED if paired else 0)
+    check(lib().mdx_eri_batch_noalloc(ctx.handle, ctypes.byref(shells.struct), ncentre, nbra, _i32p(bra), nket,
+                                      _i32p(ket), flags, _ptr(out), _stream(torch)), "mdx_eri_batch_noalloc")
+    if paired:
+        return out[:n].view(ncd, nab, nbra).permute(2, 1, 0)
+    return out[:n].view(nket, ncd, nab, nbra).permute(3, 2, 1, 0)
 
 
 def eri_digest(shells: DeviceShells, ncentre: int, bra, ket, Dbra=None, Dket=None, cartesian: bool = False,

@@ -76,6 +76,7 @@ struct PairDataArgs {
     PrimRec *prim;
     double *H;
     int32_t *nprim;
+    int per_block;       // items per workgroup (set by launch_pairdata)
 };
 void launch_pairdata(const PairDataArgs &a, hipStream_t s);
 

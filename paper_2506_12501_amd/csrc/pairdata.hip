@@ -27,7 +27,7 @@ __device__ __forceinline__ void cart_of(int l, int idx, int &ax, int &ay, int &a
     ax = l - s;
 }
 
-// LDS of one block, sized for the side's angular momenta (see pairdata_lds_bytes)
+// LDS of one item (one primitive pair, or one pair of a grouped side)
 struct PdLayout {
     int EA, EB, ET;   // E[3][EA][EB][ET]
     int na, nb;       // output functions per centre
@@ -46,27 +46,62 @@ __host__ __device__ inline PdLayout pd_layout(const SideGeom &g)
     return L;
 }
 
-constexpr int PD_NTM = 10;   // nonzero Cartesian terms per real solid harmonic, l <= 7
+constexpr int PD_NTM = 10;      // nonzero Cartesian terms per real solid harmonic, l <= 7
+constexpr int PD_THREADS = 256;
 
-__host__ __device__ inline size_t pairdata_lds_bytes(const SideGeom &g)
+// doubles of one item's E table plus its prefactor slot (kept even for 16-byte alignment)
+__host__ __device__ inline int pd_item_doubles(const SideGeom &g)
+{
+    const PdLayout L = pd_layout(g);
+    return (3 * L.EA * L.EB * L.ET + 2) & ~1;
+}
+
+__host__ __device__ inline size_t pairdata_lds_bytes(const SideGeom &g, int per_block)
 {
     const PdLayout L = pd_layout(g);
     const size_t nf = L.na + L.nb;
-    return (3 * (size_t)L.EA * L.EB * L.ET + nf * PD_NTM + 2) * 8 + (nf + nf * PD_NTM * 3) * 4;
+    return ((size_t)per_block * pd_item_doubles(g) + nf * PD_NTM) * 8 + (nf + nf * PD_NTM * 3) * 4;
 }
 
-__global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
+// H elements one item writes (rows x padded columns; the derivative role six blocks)
+static int pd_item_elements(const SideGeom &g)
+{
+    if (g.grouped) return (g.role == 0 ? g.rows_per_block : g.nterm) * g.ncolp;
+    if (g.role == 1) return g.rows_per_block * g.ncolp;
+    return (g.role == 2 ? 6 : 1) * (g.nh + 15) * g.ncolp;
+}
+
+// Items per 256-thread workgroup: each item gets a power-of-two group of
+// threads, about one thread per two H elements (at least 16, so that the
+// three E recursions and the term tables have lanes; at most the whole
+// workgroup).  Small s/p items share a workgroup instead of idling 128 lanes.
+static int pd_per_block(const SideGeom &g)
+{
+    const int e = pd_item_elements(g);
+    int t = 16;
+    while (t < PD_THREADS && 2 * t < e) t *= 2;
+    return PD_THREADS / t;
+}
+
+__global__ void __launch_bounds__(PD_THREADS) pairdata_kernel(PairDataArgs a)
 {
     const SideGeom &g = a.g;
-    // one block per primitive pair of a pair (items), or per pair (grouped side)
-    int pair, k;
-    if (g.grouped) {
-        pair = blockIdx.x;
-        k = 0;
-    } else {
-        const int2 it = a.items[blockIdx.x];
-        pair = it.x;
-        k = it.y;
+    const int G = a.per_block;                      // items of this workgroup
+    const int T = PD_THREADS / G;                   // threads of one item
+    const int slot = (int)threadIdx.x / T, lt = (int)threadIdx.x % T;
+    const int item = blockIdx.x * G + slot;
+    const int nitem = g.grouped ? g.npair : a.nitems;
+    const bool live = item < nitem;                 // dead slots still reach every barrier
+    // one item = one primitive pair of a pair (items), or one pair (grouped side)
+    int pair = 0, k = 0;
+    if (live) {
+        if (g.grouped) {
+            pair = item;
+        } else {
+            const int2 it = a.items[item];
+            pair = it.x;
+            k = it.y;
+        }
     }
     const PairRec pr = a.pairs[pair];
     const int np = pr.ka * pr.kb;
@@ -75,17 +110,17 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
     const PdLayout PL = pd_layout(g);
     const int EA = PL.EA, EB = PL.EB, ET = PL.ET;
     extern __shared__ double pd_smem[];
-    double *Eb = pd_smem;                                   // [3][EA][EB][ET]
+    double *Eb = pd_smem + slot * pd_item_doubles(g);         // [3][EA][EB][ET] of this item
 #define E(ax, i, j, t) Eb[(((ax) * EA + (i)) * EB + (j)) * ET + (t)]
     double &sh_pref = Eb[3 * EA * EB * ET];
-    double *ta_w = Eb + 3 * EA * EB * ET + 2;               // [na][NTM]
+    double *ta_w = pd_smem + G * pd_item_doubles(g);       // [na][NTM], shared by the items
     double *tb_w = ta_w + PL.na * PD_NTM;                   // [nb][NTM]
     int *ta_n = (int *)(tb_w + PL.nb * PD_NTM);             // [na]
     int *tb_n = ta_n + PL.na;                               // [nb]
     int *ta_c = tb_n + PL.nb;                               // [na][NTM][3]
     int *tb_c = ta_c + PL.na * PD_NTM * 3;                  // [nb][NTM][3]
 
-    if (threadIdx.x == 0 && k == 0) a.nprim[pair] = np;
+    if (live && lt == 0 && k == 0) a.nprim[pair] = np;
 
     const double A0 = a.center[3 * pr.sa], A1 = a.center[3 * pr.sa + 1], A2 = a.center[3 * pr.sa + 2];
     double B[3] = {A0, A1, A2};
@@ -96,7 +131,8 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
 
     if (g.grouped) {
         // single-function solid side: primitive records carry the weights
-        for (int kk = threadIdx.x; kk < g.kmax; kk += blockDim.x) {
+        if (!live) return;                          // no barrier on this path
+        for (int kk = lt; kk < g.kmax; kk += T) {
             PrimRec r{};
             if (kk < np) {
                 const double z = a.expo[pr.offa + kk], c = a.coef[pr.offa + kk];
@@ -112,7 +148,7 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         const double sgn = (g.role == 1 && (la & 1)) ? -1.0 : 1.0;
         double *Hp = a.H + (int64_t)pair * g.pair_stride;
         const int nrows = g.rows_per_block;
-        for (int e = threadIdx.x; e < nrows * g.ncolp; e += blockDim.x) {
+        for (int e = lt; e < nrows * g.ncolp; e += T) {
             const int row = e / g.ncolp, col = e % g.ncolp;
             double v = 0.0;
             if (row < g.nterm && col < g.ncol) v = sgn * (g.cart ? (row == col ? 1.0 : 0.0) : a.Ca[col * ncart(la) + row]);
@@ -120,11 +156,38 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         }
         // bra role pads rows to 16
         if (g.role == 0)
-            for (int e = nrows * g.ncolp + threadIdx.x; e < g.pair_stride; e += blockDim.x) Hp[e] = 0.0;
+            for (int e = nrows * g.ncolp + lt; e < g.pair_stride; e += T) Hp[e] = 0.0;
         return;
     }
 
-    const bool valid = k < np;
+    // nonzero Cartesian->solid terms of every output function, both centres
+    // (at most PD_NTM nonzero terms per real solid harmonic; one per Cartesian);
+    // class constants, built once per workgroup
+    constexpr int NTM = PD_NTM;
+    const int nb_out = g.lb >= 0 ? nfunc(lb, g.cart) : 1;
+    const int na_out = nfunc(la, g.cart);
+    for (int side = 0; side < 2; ++side) {
+        const int l = side == 0 ? la : lb, nout = side == 0 ? na_out : nb_out;
+        const double *C = side == 0 ? a.Ca : a.Cb;
+        const bool unit = side == 1 && g.lb < 0;
+        for (int mo = (int)threadIdx.x; mo < nout; mo += PD_THREADS) {
+            int n = 0;
+            for (int ic = 0; ic < ncart(l); ++ic) {
+                const double w = unit ? 1.0 : (g.cart ? (ic == mo ? 1.0 : 0.0) : C[mo * ncart(l) + ic]);
+                if (w == 0.0 || n == NTM) continue;
+                int x, y, z;
+                cart_of(l, ic, x, y, z);
+                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 0] = x;
+                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 1] = y;
+                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 2] = z;
+                (side == 0 ? ta_w : tb_w)[mo * NTM + n] = w;
+                ++n;
+            }
+            (side == 0 ? ta_n : tb_n)[mo] = n;
+        }
+    }
+
+    const bool valid = live && k < np;
     double za = 1.0, zb = 0.0, ca = 0.0, cb = 1.0;
     if (valid) {
         const int ka = k / pr.kb, kb = k % pr.kb;
@@ -137,8 +200,8 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
     }
     const double p = za + zb;
     const double i2p = 0.5 / p;
-    if (threadIdx.x < 3) {
-        const int ax = threadIdx.x;
+    if (lt < 3) {
+        const int ax = lt;
         // X_PA = (zeta_b/p)(B - A) and X_PB = (zeta_a/p)(A - B): both exactly 0
         // when the two centres coincide (P - A formed from a rounded P is not)
         const double XPA = zb / p * (B[ax] - Av[ax]), XPB = za / p * (Av[ax] - B[ax]);
@@ -163,24 +226,27 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
                 }
         }
     }
-    if (threadIdx.x == 0) {
+    if (lt == 0) {
         const double dx = Av[0] - B[0], dy = Av[1] - B[1], dz = Av[2] - B[2];
         const double K = valid ? exp(-za * zb / p * (dx * dx + dy * dy + dz * dz)) * ca * cb : 0.0;
         const double pref = K / p;   // + 2 pi^{5/2} on the bra
         sh_pref = g.role != 1 ? 2.0 * 17.493418327624862 * pref : pref;
-        PrimRec r{};
-        r.p = valid ? p : 1.0;
-        // P = A + (zeta_b/p)(B - A): exactly A on one centre, so P - Q of two
-        // one-centre pairs on the same atom is exactly 0
-        r.Px = Av[0] + zb / p * (B[0] - Av[0]);
-        r.Py = Av[1] + zb / p * (B[1] - Av[1]);
-        r.Pz = Av[2] + zb / p * (B[2] - Av[2]);
-        r.ws = valid ? 1.0 : 0.0;
-        // terminal weight (-1)^L K c c / (zeta_q (2 zeta_q)^L), Eqs. (17), (40)
-        r.wt = valid ? ((g.L & 1) ? -1.0 : 1.0) * pref * pow(2.0 * p, -(double)g.L) : 0.0;
-        a.prim[pair * g.kmax + k] = r;
+        if (live) {
+            PrimRec r{};
+            r.p = valid ? p : 1.0;
+            // P = A + (zeta_b/p)(B - A): exactly A on one centre, so P - Q of two
+            // one-centre pairs on the same atom is exactly 0
+            r.Px = Av[0] + zb / p * (B[0] - Av[0]);
+            r.Py = Av[1] + zb / p * (B[1] - Av[1]);
+            r.Pz = Av[2] + zb / p * (B[2] - Av[2]);
+            r.ws = valid ? 1.0 : 0.0;
+            // terminal weight (-1)^L K c c / (zeta_q (2 zeta_q)^L), Eqs. (17), (40)
+            r.wt = valid ? ((g.L & 1) ? -1.0 : 1.0) * pref * pow(2.0 * p, -(double)g.L) : 0.0;
+            a.prim[pair * g.kmax + k] = r;
+        }
     }
     __syncthreads();
+    if (!live) return;
     const double pref = sh_pref;
 
     // rows of this primitive block
@@ -197,32 +263,6 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         nrows = g.rows_per_block;
         Hp = a.H + (int64_t)pair * g.pair_stride + (int64_t)k * g.rows_per_block * g.ncolp;
     }
-    const int nb_out = g.lb >= 0 ? nfunc(lb, g.cart) : 1;
-    const int na_out = nfunc(la, g.cart);
-    // nonzero Cartesian->solid terms of every output function, both centres
-    // (at most PD_NTM nonzero terms per real solid harmonic; one per Cartesian)
-    constexpr int NTM = PD_NTM;
-    for (int side = 0; side < 2; ++side) {
-        const int l = side == 0 ? la : lb, nout = side == 0 ? na_out : nb_out;
-        const double *C = side == 0 ? a.Ca : a.Cb;
-        const bool unit = side == 1 && g.lb < 0;
-        for (int mo = threadIdx.x; mo < nout; mo += blockDim.x) {
-            int n = 0;
-            for (int ic = 0; ic < ncart(l); ++ic) {
-                const double w = unit ? 1.0 : (g.cart ? (ic == mo ? 1.0 : 0.0) : C[mo * ncart(l) + ic]);
-                if (w == 0.0 || n == NTM) continue;
-                int x, y, z;
-                cart_of(l, ic, x, y, z);
-                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 0] = x;
-                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 1] = y;
-                (side == 0 ? ta_c : tb_c)[(mo * NTM + n) * 3 + 2] = z;
-                (side == 0 ? ta_w : tb_w)[mo * NTM + n] = w;
-                ++n;
-            }
-            (side == 0 ? ta_n : tb_n)[mo] = n;
-        }
-    }
-    __syncthreads();
     if (g.role == 2) {
         // derivative bra: d/dA_i of x_A^a exp(-zeta_a r_A^2) is 2 zeta_a (a+1_i) - a_i (a-1_i)
         // (likewise for B), so along axis i the Hermite coefficient of the derivative is
@@ -231,7 +271,7 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
             return (i >= 0 && j >= 0 && t <= i + j) ? E(ax, i, j, t) : 0.0;
         };
         const int64_t dstride = (int64_t)g.rows_per_block * g.ncolp;
-        for (int e = threadIdx.x; e < 6 * nrows * g.ncolp; e += blockDim.x) {
+        for (int e = lt; e < 6 * nrows * g.ncolp; e += T) {
             const int d = e / (nrows * g.ncolp), rem = e - d * nrows * g.ncolp;
             const int row = row0 + rem / g.ncolp, col = rem % g.ncolp;
             const int rk = row - k * g.nh;
@@ -262,7 +302,7 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
         }
         return;
     }
-    for (int e = threadIdx.x; e < nrows * g.ncolp; e += blockDim.x) {
+    for (int e = lt; e < nrows * g.ncolp; e += T) {
         const int row = row0 + e / g.ncolp, col = e % g.ncolp;
         // Hermite triple of this row
         int h = -1;
@@ -298,10 +338,14 @@ __global__ void __launch_bounds__(128) pairdata_kernel(PairDataArgs a)
 
 #undef E
 
-void launch_pairdata(const PairDataArgs &a, hipStream_t s)
+void launch_pairdata(const PairDataArgs &a0, hipStream_t s)
 {
-    const int nblk = a.g.grouped ? a.g.npair : a.nitems;
-    if (nblk > 0) hipLaunchKernelGGL(pairdata_kernel, dim3(nblk), dim3(128), pairdata_lds_bytes(a.g), s, a);
+    PairDataArgs a = a0;
+    a.per_block = pd_per_block(a.g);
+    const int nitem = a.g.grouped ? a.g.npair : a.nitems;
+    const int nblk = (nitem + a.per_block - 1) / a.per_block;
+    if (nblk > 0)
+        hipLaunchKernelGGL(pairdata_kernel, dim3(nblk), dim3(PD_THREADS), pairdata_lds_bytes(a.g, a.per_block), s, a);
 }
 
 }  // namespace mdx

@@ -52,7 +52,7 @@ def test_plain_and_fused_plans_match_oracle():
     for bt in batches:
         off, n = bt["out_offset"], bt["quartets"] * bt["nab"] * bt["ncd"]
         ref, scale = oracle_batch(b, bt)
-        assert_close_cs(o2[off:off + n], ref, scale, bt["name"])
+        assert_close_cs(o2[off:off + n], ref, scale, bt["name"], g13_only=True)
     print("quartets", sum(bt["quartets"] for bt in batches), "doubles", total)
 
 
@@ -70,7 +70,7 @@ def test_bucketed_plans_share_pair_data():
     for bt in batches:
         off, n = bt["out_offset"], bt["quartets"] * bt["nab"] * bt["ncd"]
         ref, scale = oracle_batch(b, bt)
-        assert_close_cs(o2[off:off + n], ref, scale, f"{bt['name']} K{bt['Kbra']}x{bt['Kket']}")
+        assert_close_cs(o2[off:off + n], ref, scale, f"{bt['name']} K{bt['Kbra']}x{bt['Kket']}", g13_only=True)
     print("batches", len(batches), "quartets", sum(bt["quartets"] for bt in batches))
 
 

@@ -154,6 +154,13 @@ class NuclearRun(OneBodyRun):
         self.charges = torch.as_tensor(charges, device="cuda")
         self.nch = int(self.charges.shape[0])
         del self.T
+        L = native.lib()
+        self.wsz = L.mdx_nuclear_workspace_size(ctx.handle, ctypes.byref(self.sh.struct), self.n,
+                                                native._i32p(self.pairs), self.nch, 0)
+        if self.wsz == 0:
+            native.check(native.MDX_EINVAL, "nuclear workspace size")
+        self.ws = torch.empty(self.wsz // 8 + 64, dtype=torch.float64, device="cuda")
+        self.wsp = (self.ws.data_ptr() + 255) // 256 * 256
 
     def __call__(self):
         n = self.native

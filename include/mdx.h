@@ -218,13 +218,15 @@ mdx_status mdx_eri_grad_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentr
  * coefficients of Eqs. (10)-(11) and (14), and
  *   T_ab = -1/2 <a| nabla^2 |b>
  * from the same 1-D overlaps with the ket's exponent raised and lowered by 2.
- * One shell pair per lane (the paper assigns one pair to one SIMD lane).
+ * The paper assigns one pair to one SIMD lane.
  *   pairs HOST int32[2*npair].
  *   S, T  DEVICE double, [ij, ab] column-major: S[ij + npair*ab], ab = a*nb + b,
  *         nb = functions of shell b; either may be NULL (not computed).
  *   ws    DEVICE, at least mdx_one_body_workspace_size bytes, 256-byte aligned.
  *   flags MDX_SPHERICAL or MDX_CARTESIAN.
- * Limits: l_a, l_b <= 3 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
+ * Shells with l <= 3 run one shell pair per lane; larger ones one pair per
+ * wave (lanes over the Cartesian function pairs).
+ * Limits: l_a, l_b <= 6 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
  * bad arguments, shell indices or mixed classes; MDX_EWORKSPACE for a short
  * workspace; MDX_EDEVICE for a HIP error.  The size query returns 0 on any
  * error (mdx_last_error says why).
@@ -245,15 +247,23 @@ mdx_status mdx_one_body_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t np
  *   charges DEVICE double[4*ncharge]: x, y, z (bohr), q of charge I at
  *           charges[4I .. 4I+3].  ncharge = 0 gives V = 0.
  *   V       DEVICE double, [ij, ab] column-major: V[ij + npair*ab].
- *   ws      DEVICE, at least mdx_nuclear_workspace_size bytes, 256-byte aligned.
+ *   ws      DEVICE, at least mdx_nuclear_workspace_size bytes (which depends
+ *           on the charge count), 256-byte aligned.
  *   flags   MDX_SPHERICAL or MDX_CARTESIAN.
- * Limits: l_a, l_b <= 3 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
+ * Classes with l_a, l_b <= 3 run one shell pair per lane.  Classes with a
+ * shell of l = 4..6 run on the matrix-core integral kernel: a point charge is
+ * the infinite-exponent limit of an s Gaussian, so the batch is the 4-centre
+ * chain (ab|s s) with one ket pair whose primitives are the charges, and the
+ * kernel's contraction over the terminal ket Hermite of each primitive is the
+ * charge sum of Eq. (37).
+ * Limits: l_a, l_b <= 6; Cartesian classes up to 225 functions per pair
+ * (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
  * bad arguments, shell indices, mixed classes, a negative charge count or a
  * null charge array with ncharge > 0; MDX_EWORKSPACE for a short workspace;
  * MDX_EDEVICE for a HIP error.  The size query returns 0 on any error.
  */
 size_t mdx_nuclear_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
-                                  int flags);
+                                  int32_t ncharge, int flags);
 mdx_status mdx_nuclear_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
                              int32_t ncharge, const double *charges, int flags, double *V, void *ws,
                              size_t ws_bytes, mdx_stream_t stream);

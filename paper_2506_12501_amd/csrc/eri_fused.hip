@@ -34,7 +34,7 @@ eri_mfma_queue(QueueArgs q)
         const int w = __builtin_amdgcn_readfirstlane(item);
         if (w >= q.total) break;
         const int b = __builtin_amdgcn_readfirstlane(queue_batch(q, w));
-        const EriArgs &a = q.desc[b];
+        const EriArgs a = load_const(q.desc + b);   // batch arguments: scalar loads
         int J, I;
         ragged_tile(a.tile_off, a.nket, w - q.base[b], J, I);
         const int nI = a.om.count[J];
@@ -42,8 +42,14 @@ eri_mfma_queue(QueueArgs q)
     }
 }
 
+// The smallest shellsets (up to 3 integrals) keep 5 or more waves per SIMD: their
+// lanes wait on Boys-table reads, which only more resident waves hide.
+template <int NAB, int NCD>
+constexpr int valu_queue_waves() { return NAB * NCD <= 1 ? 8 : (NAB * NCD <= 3 ? 5 : 1); }
+
 template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
-__global__ void __launch_bounds__(64) eri_valu_queue(QueueArgs q)
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(valu_queue_waves<NAB, NCD>())))
+eri_valu_queue(QueueArgs q)
 {
     __shared__ int item;
     for (;;) {
@@ -53,11 +59,13 @@ __global__ void __launch_bounds__(64) eri_valu_queue(QueueArgs q)
         const int w = __builtin_amdgcn_readfirstlane(item);
         if (w >= q.total) break;
         const int b = __builtin_amdgcn_readfirstlane(queue_batch(q, w));
-        const EriArgs &a = q.desc[b];
+        const EriArgs a = load_const(q.desc + b);   // batch arguments: scalar loads
         int J, t0;
         ragged_tile(a.tile_off, a.nket, w - q.base[b], J, t0);
+        J = __builtin_amdgcn_readfirstlane(J);   // uniform (derived from w); its ket data become scalar loads
+        t0 = __builtin_amdgcn_readfirstlane(t0);
         const int I = t0 * 64 + (int)threadIdx.x;
-        const int nI = a.om.count[J];
+        const int nI = load_const(a.om.count + J);
         if (I < nI) eri_valu_shellset<LB, LK, NAB, NCD, GB, GK>(a, I, J, nI);
     }
 }

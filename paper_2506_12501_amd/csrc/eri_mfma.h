@@ -175,13 +175,14 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                     for (int ib = b0; ib < b1; ++ib) {
                         const PrimRec B = bp[ib];
                         const double pq = B.p + K.p;
-                        const double rho = B.p * K.p / pq;
+                        const double ypq = rsqrt_d(pq);   // 1/sqrt(p+q)
+                        const double rho = B.p * K.p * (ypq * ypq);
                         X = B.Px - K.Px;
                         Yv = B.Py - K.Py;
                         Z = B.Pz - K.Pz;
                         double F[D];
-                        boys_eval<L>(rho * (X * X + Yv * Yv + Z * Z), F, a.boys);
-                        double f = B.ws * K.ws * rsqrt_d(pq);
+                        boys_eval<L, false>(rho * (X * X + Yv * Yv + Z * Z), F, a.boys);
+                        double f = B.ws * K.ws * ypq;
                         const double m2r = -2.0 * rho;
 #pragma unroll
                         for (int m = 0; m <= L; ++m) {
@@ -469,6 +470,11 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     X(5, 4, 11, 25, true, 1, 2, 2, 2, 1, 2, 0, 1)               /* (h|dd)                    */    \
     X(6, 4, 13, 25, true, 1, 2, 2, 2, 1, 2, 0, 1)               /* (i|dd)                    */    \
     X(0, 4, 1, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (s|dd)                    */    \
-    X(1, 4, 3, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (p|dd)                    */
+    X(1, 4, 3, 25, true, 1, 2, 2, 1, 1, 2, 0, 1)                /* (p|dd)                    */    \
+    /* one wave per shellset for small, lightly contracted shellsets (screened molecules) */      \
+    X(4, 4, 25, 25, false, 2, 2, 2, 3, 1, 4, CUBE_LAY_COMPACT, 2)  /* (dd|dd)                 */   \
+    X(4, 3, 25, 15, false, 2, 1, 1, 3, 1, 4, CUBE_LAY_COMPACT, 3)  /* (dd|dp)                 */   \
+    X(4, 2, 25, 9, false, 2, 1, 1, 3, 1, 4, CUBE_LAY_COMPACT, 3)   /* (dd|pp)                 */   \
+    X(3, 3, 15, 15, false, 1, 1, 1, 4, 1, 4, CUBE_LAY_COMPACT, 2)  /* (dp|dp)                 */
 
 }  // namespace mdx

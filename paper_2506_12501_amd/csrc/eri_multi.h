@@ -59,13 +59,14 @@ __device__ __forceinline__ void eri_multi_unit(const EriArgs &a, const int I0, c
         for (int ib = 0; ib < npb; ++ib) {
             const PrimRec B = bp[ib];
             const double pq = B.p + K.p;
-            const double rho = B.p * K.p / pq;
+            const double ypq = rsqrt_d(pq);   // 1/sqrt(p+q)
+            const double rho = B.p * K.p * (ypq * ypq);
             X = B.Px - K.Px;
             Y = B.Py - K.Py;
             Z = B.Pz - K.Pz;
             double F[D];
             boys_eval<L>(rho * (X * X + Y * Y + Z * Z), F, a.boys);
-            double f = B.ws * K.ws * rsqrt_d(pq);
+            double f = B.ws * K.ws * ypq;
             const double m2r = -2.0 * rho;
 #pragma unroll
             for (int m = 0; m <= L; ++m) {

@@ -74,11 +74,12 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
         const PrimRec B = a.bra.prim[(int64_t)(I0 + q) * a.bra.kmax];
         const PrimRec K = a.ket.prim[(int64_t)J * a.ket.kmax];
         const double pq = B.p + K.p;
-        const double rho = B.p * K.p / pq;
+        const double ypq = rsqrt_d(pq);   // 1/sqrt(p+q)
+        const double rho = B.p * K.p * (ypq * ypq);
         const double X = B.Px - K.Px, Y = B.Py - K.Py, Z = B.Pz - K.Pz;
         double F[D];
         boys_eval<L>(rho * (X * X + Y * Y + Z * Z), F, a.boys);
-        double f = B.ws * K.ws * rsqrt_d(pq);
+        double f = B.ws * K.ws * ypq;
         const double m2r = -2.0 * rho;
 #pragma unroll
         for (int m = 0; m <= L; ++m) {

@@ -17,9 +17,10 @@
 
 namespace mdx {
 
-// Shellset (bra pair I, ket pair J) of the calling lane into out[ab][cd];
-// J is the same for the whole wave (its ket data are scalar loads).
-template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
+// Shellset (bra pair I, ket pair J) of the calling lane into out[ab][cd].
+// UJ: J is the same for the whole wave, so its ket data are scalar loads
+// (false only for paired batches, one quartet per lane).
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK, bool UJ = true>
 __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, const int J, double (&out)[NAB][NCD])
 {
     constexpr int L = LB + LK;
@@ -36,7 +37,7 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
 
 
     const int npb = a.bra.nprim[I];
-    const int npk = a.ket.nprim[J];
+    const int npk = UJ ? load_const(a.ket.nprim + J) : a.ket.nprim[J];
     const PrimRec *bp = a.bra.prim + (int64_t)I * a.bra.kmax;
     const PrimRec *kp = a.ket.prim + (int64_t)J * a.ket.kmax;
     const double *Hb = a.bra.H + (int64_t)I * a.bra.pair_stride;
@@ -47,14 +48,21 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
 #pragma unroll
         for (int j = 0; j < NCD; ++j) out[i][j] = 0.0;
 
-    const int nkb = GB ? 1 : npb;
+    // The bra primitive loop runs to the side's largest count (the same for
+    // every lane), each lane contributing while kb < its own count: the ket
+    // loops inside stay wave-uniform, so the ket records and H rows (the same
+    // ket pair in every lane of a wave) are scalar loads.
+    const int nkbw = GB ? 1 : a.bra.kmax;
     const int nkk = GK ? 1 : npk;
-    for (int kb = 0; kb < nkb; ++kb) {
+    for (int kb = 0; kb < nkbw; ++kb) {
+        if (!GB && kb >= npb) continue;
         double X[NHB][NCD];
 #pragma unroll
         for (int i = 0; i < NHB; ++i)
 #pragma unroll
             for (int j = 0; j < NCD; ++j) X[i][j] = 0.0;
+        PrimRec B1{};
+        if constexpr (!GB) B1 = bp[kb];
 
         for (int kk = 0; kk < nkk; ++kk) {
             double S[L + 1];
@@ -64,18 +72,19 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
             const int b0 = GB ? 0 : kb, b1 = GB ? npb : kb + 1;
             const int k0 = GK ? 0 : kk, k1 = GK ? npk : kk + 1;
             for (int ib = b0; ib < b1; ++ib) {
-                const PrimRec B = bp[ib];
+                const PrimRec B = GB ? bp[ib] : B1;
                 for (int ik = k0; ik < k1; ++ik) {
-                    const PrimRec K = kp[ik];
+                    const PrimRec K = UJ ? load_const(kp + ik) : kp[ik];   // the wave's ket pair: scalar
                     const double pq = B.p + K.p;
-                    const double rho = B.p * K.p / pq;
+                    const double y = rsqrt_d(pq);            // 1/sqrt(p+q)
+                    const double rho = B.p * K.p * (y * y);
                     PQ0 = B.Px - K.Px;
                     PQ1 = B.Py - K.Py;
                     PQ2 = B.Pz - K.Pz;
                     const double T = rho * (PQ0 * PQ0 + PQ1 * PQ1 + PQ2 * PQ2);
                     double F[L + 1];
                     boys_eval<L>(T, F, a.boys);
-                    double f = B.ws * K.ws * rsqrt_d(pq);
+                    double f = B.ws * K.ws * y;
                     const double m2r = -2.0 * rho;
 #pragma unroll
                     for (int m = 0; m <= L; ++m) {
@@ -95,7 +104,7 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
                 const int qh = r < NKN ? r : nherm(LK - 1) + (r - NKN);
                 double hk[NCD];
 #pragma unroll
-                for (int j = 0; j < NCD; ++j) hk[j] = Hk[hrow * NCDP + j];
+                for (int j = 0; j < NCD; ++j) hk[j] = UJ ? load_const(Hk + hrow * NCDP + j) : Hk[hrow * NCDP + j];
 #pragma unroll
                 for (int i = 0; i < NHB; ++i) {
                     const double v = R[sum.idx[HB0 + i][qh]];
@@ -120,11 +129,11 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
 }
 
 // Shellset (I, J) of the calling lane, stored in the caller's layout; I < nI.
-template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK, bool UJ = true>
 __device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I, const int J, const int nI)
 {
     double out[NAB][NCD];
-    eri_valu_compute<LB, LK, NAB, NCD, GB, GK>(a, I, J, out);
+    eri_valu_compute<LB, LK, NAB, NCD, GB, GK, UJ>(a, I, J, out);
     // store, [ij,ab,cd,kl] addressing of the caller
     const int64_t base = (a.om.count ? a.om.obase[J] : (int64_t)J * a.om.sJ) + (int64_t)I * a.om.sI;
     const int64_t mult = a.om.count ? (int64_t)nI : a.om.mult;

@@ -11,7 +11,7 @@ __global__ void __launch_bounds__(64) eri_valu_kernel(EriArgs a)
     if (a.diag == 2) {   // paired batch: quartet q = (bra q, ket q), one per lane
         I = J = blockIdx.x * 64 + (int)threadIdx.x;
         if (J >= a.nket) return;
-        eri_valu_shellset<LB, LK, NAB, NCD, GB, GK>(a, I, J, a.nbra);
+        eri_valu_shellset<LB, LK, NAB, NCD, GB, GK, false>(a, I, J, a.nbra);
         return;
     }
     if (a.diag) {   // diagonal shellsets (I = J) only: lane 0 of block J
@@ -26,7 +26,8 @@ __global__ void __launch_bounds__(64) eri_valu_kernel(EriArgs a)
         J = t / a.tiles_per_J;
         I = (t % a.tiles_per_J) * 64 + (int)threadIdx.x;
     }
-    const int nI = a.diag ? J + 1 : (a.om.count ? a.om.count[J] : a.nbra);
+    J = __builtin_amdgcn_readfirstlane(J);   // one ket pair per wave: its data become scalar loads
+    const int nI = a.diag ? J + 1 : (a.om.count ? load_const(a.om.count + J) : a.nbra);
     if (I >= nI) return;
     eri_valu_shellset<LB, LK, NAB, NCD, GB, GK>(a, I, J, nI);
 }

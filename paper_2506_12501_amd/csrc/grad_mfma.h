@@ -143,11 +143,12 @@ eri_grad_kernel(GradArgs a)
             const PrimRec B = bp[kb_lo + q];
             const PrimRec K = kp[kk];
             const double pq = B.p + K.p;
-            const double rho = B.p * K.p / pq;
+            const double ypq = rsqrt_d(pq);   // 1/sqrt(p+q)
+            const double rho = B.p * K.p * (ypq * ypq);
             const double X = B.Px - K.Px, Yv = B.Py - K.Py, Z = B.Pz - K.Pz;
             double F[D];
             boys_eval<L>(rho * (X * X + Yv * Yv + Z * Z), F, a.boys);
-            double f = B.ws * K.ws * rsqrt_d(pq);
+            double f = B.ws * K.ws * ypq;
             const double m2r = -2.0 * rho;
             double *Sq = S + (kk * nqmax + q) * D;
 #pragma unroll

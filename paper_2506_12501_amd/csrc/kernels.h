@@ -5,7 +5,40 @@
 
 namespace mdx {
 
-__device__ __forceinline__ double rsqrt_d(double x) { return 1.0 / sqrt(x); }
+// 1/sqrt(x) and 1/x for positive, normal, finite x: the hardware estimates
+// refined by two Newton steps each (to about an ulp; no IEEE rounding
+// fix-ups, which cost two to three times as many instructions)
+__device__ __forceinline__ double rsqrt_d(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
+// Read of data that no kernel writes while the reading kernel runs (pair data,
+// tables), through the constant address space: with a wave-uniform address the
+// compiler issues a scalar load instead of one vector load per lane.
+template <typename T>
+__device__ __forceinline__ T load_const(const T *p)
+{
+    static_assert(sizeof(T) % 4 == 0, "whole words");
+    typedef const __attribute__((address_space(4))) int cint;
+    cint *q = (cint *)(const void *)p;
+    T r;
+    int *d = (int *)&r;
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) d[i] = q[i];
+    return r;
+}
+
+__device__ __forceinline__ double rcp_d(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return r;
+}
 
 // Blocks are dealt to the 8 XCDs round-robin.  Renumber them so that each XCD
 // receives a contiguous range of work items (consecutive bra pairs of a ket

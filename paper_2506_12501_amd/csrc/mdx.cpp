@@ -179,9 +179,12 @@ extern "C" mdx_status mdx_create(int device, mdx_ctx **out)
         }
     }
     // Boys table
-    const size_t nb = sizeof(mdx_boys_table_host);
-    hipError_t e = hipMalloc((void **)&c->boys, nb);
-    if (e == hipSuccess) e = hipMemcpy(c->boys, mdx_boys_table_host, nb, hipMemcpyHostToDevice);
+    static_assert(sizeof(mdx_boys_table_host) == sizeof(double) * BOYS_EXP_OFF, "Boys table shape");
+    std::vector<double> btab(BOYS_EXP_OFF + BOYS_NROW);
+    std::memcpy(btab.data(), mdx_boys_table_host, sizeof(mdx_boys_table_host));
+    for (int k = 0; k < BOYS_NROW; ++k) btab[BOYS_EXP_OFF + k] = std::exp(-(double)k / BOYS_STEP_INV);
+    hipError_t e = hipMalloc((void **)&c->boys, btab.size() * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpy(c->boys, btab.data(), btab.size() * sizeof(double), hipMemcpyHostToDevice);
     // solid harmonics, l <= 8
     std::vector<std::vector<double>> sol;
     solid_tables(sol);

@@ -26,7 +26,17 @@ namespace mdx {
 
 static inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr int ONEBODY_LMAX = 3;   // per shell, overlap / kinetic / nuclear attraction
+constexpr int ONEBODY_LMAX = 6;        // per shell, overlap / kinetic / nuclear attraction
+constexpr int ONEBODY_LANE_LMAX = 3;   // one pair per lane up to here; beyond, one pair per wave
+                                       // (overlap, kinetic) or the matrix-core kernel (nuclear)
+
+// 1-particle Coulomb integrals of shells with l >= 4 (nuclear_mfma.hip)
+bool nuclear_on_mfma(int la, int lb);
+mdx_status nuclear_mfma_workspace(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la,
+                                  int lb, int32_t ncharge, bool cart, size_t &bytes);
+mdx_status nuclear_mfma_enqueue(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la, int lb,
+                                int32_t ncharge, const double *charges, bool cart, double *V, void *ws,
+                                size_t ws_bytes, hipStream_t s);
 
 struct OneBodyArgs {
     const PairRec *pairs;
@@ -181,6 +191,117 @@ __global__ void __launch_bounds__(64) onebody_kernel(OneBodyArgs a)
         if (a.S) store_pair<LA, LB, CART>(S, a.Ca, a.Cb, a.S, ij, a.npair);
     if constexpr (PART != 1)
         if (a.T) store_pair<LA, LB, CART>(T, a.Ca, a.Cb, a.T, ij, a.npair);
+}
+
+// Overlap and kinetic energy of shells beyond the lane kernels (l <= 6): one
+// shell pair per wave.  Per primitive pair the lanes build the E tables of
+// Eqs. (10)-(11) in LDS (lanes over (axis, t), one recursion step at a time),
+// reduce them to the 1-D overlap and kinetic factors, and then every lane
+// accumulates its share of the Cartesian function pairs.  The solid transform
+// of Eq. (18) runs through LDS, ket index first.
+template <int LA, int LB, bool CART>
+__global__ void __launch_bounds__(64) onebody_wave_kernel(OneBodyArgs a)
+{
+    constexpr int NA = ncart(LA), NB = ncart(LB), NF = NA * NB, R = (NF + 63) / 64;
+    constexpr int JB = LB + 3, TT = LA + LB + 3;   // kinetic needs j + 2
+    constexpr int MA = CART ? NA : 2 * LA + 1, MB = CART ? NB : 2 * LB + 1;
+    __shared__ double E[3][LA + 1][JB][TT];
+    __shared__ double s1[3][LA + 1][LB + 1], t1[3][LA + 1][LB + 1];
+    __shared__ double X[NF];
+    __shared__ double U[NA * MB];
+    const int ij = blockIdx.x, lane = (int)threadIdx.x;
+    const PairRec pr = a.pairs[ij];
+    const double A[3] = {a.center[3 * pr.sa], a.center[3 * pr.sa + 1], a.center[3 * pr.sa + 2]};
+    const double B[3] = {a.center[3 * pr.sb], a.center[3 * pr.sb + 1], a.center[3 * pr.sb + 2]};
+    const double AB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+    int ex[R][3], ey[R][3];   // Cartesian exponents of this lane's function pairs (a in ex, b in ey)
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int e = min(lane + 64 * r, NF - 1), i = e / NB, j = e % NB;
+#pragma unroll
+        for (int ax = 0; ax < 3; ++ax) {
+            ex[r][ax] = cart_exp(LA, i, ax);
+            ey[r][ax] = cart_exp(LB, j, ax);
+        }
+    }
+    double S[R], T[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) S[r] = T[r] = 0.0;
+    const int ax = lane / 16, t = lane % 16;   // recursion lane: axis ax, Hermite index t
+    for (int ka = 0; ka < pr.ka; ++ka) {
+        const double za = a.expo[pr.offa + ka], ca = a.coef[pr.offa + ka];
+        for (int kb = 0; kb < pr.kb; ++kb) {
+            const double zb = a.expo[pr.offb + kb], cb = a.coef[pr.offb + kb];
+            const double p = za + zb, i2p = 0.5 / p;
+            // X_PA, X_PB from centre differences: exactly 0 on one centre
+            const double XPA = ax < 3 ? zb / p * (B[ax] - A[ax]) : 0.0, XPB = ax < 3 ? za / p * (A[ax] - B[ax]) : 0.0;
+            __syncthreads();   // the previous primitive pair's readers are done
+            auto get = [&](int i, int j, int tt) -> double { return (tt < 0 || tt > i + j) ? 0.0 : E[ax][i][j][tt]; };
+            for (int i = 0; i <= LA; ++i) {
+                if (ax < 3 && t <= i) {
+                    E[ax][i][0][t] = i == 0 ? 1.0
+                                            : i2p * get(i - 1, 0, t - 1) + XPA * get(i - 1, 0, t) + (t + 1) * get(i - 1, 0, t + 1);
+                }
+                __syncthreads();
+                for (int j = 1; j < JB; ++j) {
+                    if (ax < 3 && t <= i + j)
+                        E[ax][i][j][t] = i2p * get(i, j - 1, t - 1) + XPB * get(i, j - 1, t) + (t + 1) * get(i, j - 1, t + 1);
+                    __syncthreads();
+                }
+            }
+            // 1-D overlap and kinetic factors (the Laplacian on the ket Gaussian)
+            for (int e = lane; e < 3 * (LA + 1) * (LB + 1); e += 64) {
+                const int x = e / ((LA + 1) * (LB + 1)), ia = (e / (LB + 1)) % (LA + 1), jb = e % (LB + 1);
+                s1[x][ia][jb] = E[x][ia][jb][0];
+                double d2 = 4.0 * zb * zb * E[x][ia][jb + 2][0] - 2.0 * zb * (2 * jb + 1) * E[x][ia][jb][0];
+                if (jb >= 2) d2 += (double)(jb * (jb - 1)) * E[x][ia][jb - 2][0];
+                t1[x][ia][jb] = -0.5 * d2;
+            }
+            __syncthreads();
+            // c_a c_b (pi/p)^{3/2} exp(-za zb/p |A-B|^2), Eqs. (8), (14)
+            const double f = ca * cb * (M_PI / p) * sqrt(M_PI / p) * exp(-za * zb / p * AB2);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const double sx = s1[0][ex[r][0]][ey[r][0]], sy = s1[1][ex[r][1]][ey[r][1]], sz = s1[2][ex[r][2]][ey[r][2]];
+                const double tx = t1[0][ex[r][0]][ey[r][0]], ty = t1[1][ex[r][1]][ey[r][1]], tz = t1[2][ex[r][2]][ey[r][2]];
+                S[r] = fma(f, sx * sy * sz, S[r]);
+                T[r] = fma(f, tx * sy * sz + sx * ty * sz + sx * sy * tz, T[r]);
+            }
+        }
+    }
+    for (int part = 0; part < 2; ++part) {
+        double *out = part == 0 ? a.S : a.T;
+        if (!out) continue;   // uniform
+        const double *acc = part == 0 ? S : T;
+        if constexpr (CART) {
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = lane + 64 * r;
+                if (e < NF) out[ij + (int64_t)a.npair * e] = acc[r];
+            }
+        } else {
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = lane + 64 * r;
+                if (e < NF) X[e] = acc[r];
+            }
+            __syncthreads();
+            for (int e = lane; e < NA * MB; e += 64) {   // U[i][n] = sum_j Cb[n][j] X[i][j]
+                const int i = e / MB, n = e % MB;
+                double u = 0.0;
+                for (int j = 0; j < NB; ++j) u = fma(a.Cb[n * NB + j], X[i * NB + j], u);
+                U[e] = u;
+            }
+            __syncthreads();
+            for (int e = lane; e < MA * MB; e += 64) {   // out[m][n] = sum_i Ca[m][i] U[i][n]
+                const int m = e / MB, n = e % MB;
+                double v = 0.0;
+                for (int i = 0; i < NA; ++i) v = fma(a.Ca[m * NA + i], U[i * MB + n], v);
+                out[ij + (int64_t)a.npair * e] = v;
+            }
+        }
+    }
 }
 
 struct NuclearArgs {
@@ -368,7 +489,10 @@ static void launch_onebody_part(const OneBodyArgs &a, bool cart, hipStream_t s)
 template <int LA, int LB>
 static void launch_onebody(const OneBodyArgs &a, bool cart, hipStream_t s)
 {
-    if constexpr (LA + LB >= 5) {   // S and T apart: one set of accumulators per lane
+    if constexpr (LA > ONEBODY_LANE_LMAX || LB > ONEBODY_LANE_LMAX) {   // one pair per wave
+        if (cart) hipLaunchKernelGGL((onebody_wave_kernel<LA, LB, true>), dim3(a.npair), dim3(64), 0, s, a);
+        else hipLaunchKernelGGL((onebody_wave_kernel<LA, LB, false>), dim3(a.npair), dim3(64), 0, s, a);
+    } else if constexpr (LA + LB >= 5) {   // S and T apart: one set of accumulators per lane
         if (a.S) launch_onebody_part<LA, LB, 1>(a, cart, s);
         if (a.T) launch_onebody_part<LA, LB, 2>(a, cart, s);
     } else {
@@ -441,7 +565,8 @@ static mdx_status stage_pairs(mdx_ctx *c, const mdx_shells *sh, int32_t npair, c
     return MDX_OK;
 }
 
-// one case per (l_a, l_b), l <= ONEBODY_LMAX = 3
+// one case per (l_a, l_b): l <= ONEBODY_LANE_LMAX (MDX_ONEBODY_SWITCH) or
+// l <= ONEBODY_LMAX (MDX_ONEBODY_SWITCH7)
 #define MDX_ONEBODY_SWITCH(LAUNCH, la, lb, ...)          \
     switch ((la) * 4 + (lb)) {                           \
     case 0: LAUNCH<0, 0>(__VA_ARGS__); break;            \
@@ -460,6 +585,59 @@ static mdx_status stage_pairs(mdx_ctx *c, const mdx_shells *sh, int32_t npair, c
     case 13: LAUNCH<3, 1>(__VA_ARGS__); break;           \
     case 14: LAUNCH<3, 2>(__VA_ARGS__); break;           \
     default: LAUNCH<3, 3>(__VA_ARGS__); break;           \
+    }
+
+#define MDX_ONEBODY_SWITCH7(LAUNCH, la, lb, ...)         \
+    switch ((la) * 7 + (lb)) {                           \
+    case 0: LAUNCH<0, 0>(__VA_ARGS__); break; \
+    case 1: LAUNCH<0, 1>(__VA_ARGS__); break; \
+    case 2: LAUNCH<0, 2>(__VA_ARGS__); break; \
+    case 3: LAUNCH<0, 3>(__VA_ARGS__); break; \
+    case 4: LAUNCH<0, 4>(__VA_ARGS__); break; \
+    case 5: LAUNCH<0, 5>(__VA_ARGS__); break; \
+    case 6: LAUNCH<0, 6>(__VA_ARGS__); break; \
+    case 7: LAUNCH<1, 0>(__VA_ARGS__); break; \
+    case 8: LAUNCH<1, 1>(__VA_ARGS__); break; \
+    case 9: LAUNCH<1, 2>(__VA_ARGS__); break; \
+    case 10: LAUNCH<1, 3>(__VA_ARGS__); break; \
+    case 11: LAUNCH<1, 4>(__VA_ARGS__); break; \
+    case 12: LAUNCH<1, 5>(__VA_ARGS__); break; \
+    case 13: LAUNCH<1, 6>(__VA_ARGS__); break; \
+    case 14: LAUNCH<2, 0>(__VA_ARGS__); break; \
+    case 15: LAUNCH<2, 1>(__VA_ARGS__); break; \
+    case 16: LAUNCH<2, 2>(__VA_ARGS__); break; \
+    case 17: LAUNCH<2, 3>(__VA_ARGS__); break; \
+    case 18: LAUNCH<2, 4>(__VA_ARGS__); break; \
+    case 19: LAUNCH<2, 5>(__VA_ARGS__); break; \
+    case 20: LAUNCH<2, 6>(__VA_ARGS__); break; \
+    case 21: LAUNCH<3, 0>(__VA_ARGS__); break; \
+    case 22: LAUNCH<3, 1>(__VA_ARGS__); break; \
+    case 23: LAUNCH<3, 2>(__VA_ARGS__); break; \
+    case 24: LAUNCH<3, 3>(__VA_ARGS__); break; \
+    case 25: LAUNCH<3, 4>(__VA_ARGS__); break; \
+    case 26: LAUNCH<3, 5>(__VA_ARGS__); break; \
+    case 27: LAUNCH<3, 6>(__VA_ARGS__); break; \
+    case 28: LAUNCH<4, 0>(__VA_ARGS__); break; \
+    case 29: LAUNCH<4, 1>(__VA_ARGS__); break; \
+    case 30: LAUNCH<4, 2>(__VA_ARGS__); break; \
+    case 31: LAUNCH<4, 3>(__VA_ARGS__); break; \
+    case 32: LAUNCH<4, 4>(__VA_ARGS__); break; \
+    case 33: LAUNCH<4, 5>(__VA_ARGS__); break; \
+    case 34: LAUNCH<4, 6>(__VA_ARGS__); break; \
+    case 35: LAUNCH<5, 0>(__VA_ARGS__); break; \
+    case 36: LAUNCH<5, 1>(__VA_ARGS__); break; \
+    case 37: LAUNCH<5, 2>(__VA_ARGS__); break; \
+    case 38: LAUNCH<5, 3>(__VA_ARGS__); break; \
+    case 39: LAUNCH<5, 4>(__VA_ARGS__); break; \
+    case 40: LAUNCH<5, 5>(__VA_ARGS__); break; \
+    case 41: LAUNCH<5, 6>(__VA_ARGS__); break; \
+    case 42: LAUNCH<6, 0>(__VA_ARGS__); break; \
+    case 43: LAUNCH<6, 1>(__VA_ARGS__); break; \
+    case 44: LAUNCH<6, 2>(__VA_ARGS__); break; \
+    case 45: LAUNCH<6, 3>(__VA_ARGS__); break; \
+    case 46: LAUNCH<6, 4>(__VA_ARGS__); break; \
+    case 47: LAUNCH<6, 5>(__VA_ARGS__); break; \
+    default: LAUNCH<6, 6>(__VA_ARGS__); break; \
     }
 
 extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
@@ -484,16 +662,29 @@ extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32
     a.Cb = c->solid + c->solid_off[l[1]];
     a.S = S;
     a.T = T;
-    MDX_ONEBODY_SWITCH(launch_onebody, l[0], l[1], a, (flags & MDX_CARTESIAN) != 0, s)
+    MDX_ONEBODY_SWITCH7(launch_onebody, l[0], l[1], a, (flags & MDX_CARTESIAN) != 0, s)
     HIP_TRY2(hipGetLastError());
     if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
     return MDX_OK;
 }
 
 extern "C" size_t mdx_nuclear_workspace_size(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
-                                             int flags)
+                                             int32_t ncharge, int flags)
 {
-    return mdx_one_body_workspace_size(c, sh, npair, pairs, flags);
+    int l[2];
+    if (check_pairs(c, sh, npair, pairs, flags, l) != MDX_OK) return 0;
+    if (ncharge < 0) {
+        fail(MDX_EINVAL, "negative charge count");
+        return 0;
+    }
+    if (npair > 0 && nuclear_on_mfma(l[0], l[1])) {
+        size_t bytes = 0;
+        if (nuclear_mfma_workspace(c, sh, npair, pairs, l[0], l[1], ncharge, (flags & MDX_CARTESIAN) != 0, bytes) !=
+            MDX_OK)
+            return 0;
+        return bytes + 256;
+    }
+    return al256((size_t)npair * sizeof(PairRec)) + 256;
 }
 
 extern "C" mdx_status mdx_nuclear_batch(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
@@ -506,8 +697,11 @@ extern "C" mdx_status mdx_nuclear_batch(mdx_ctx *c, const mdx_shells *sh, int32_
     if (ncharge < 0) return fail(MDX_EINVAL, "negative charge count");
     if (ncharge > 0 && !charges) return fail(MDX_EINVAL, "null charge array");
     if (npair == 0) return MDX_OK;
-    if (!V) return fail(MDX_EINVAL, "mdx_nuclear_batch: null output");
     hipStream_t s = (hipStream_t)stream;
+    if (nuclear_on_mfma(l[0], l[1]))   // plans first (unsupported classes), then checks the buffers
+        return nuclear_mfma_enqueue(c, sh, npair, pairs, l[0], l[1], ncharge, charges, (flags & MDX_CARTESIAN) != 0, V,
+                                    ws, ws_bytes, s);
+    if (!V) return fail(MDX_EINVAL, "mdx_nuclear_batch: null output");
     hipEvent_t ev1;
     st = stage_pairs(c, sh, npair, pairs, ws, ws_bytes, s, "mdx_nuclear_batch", &ev1);
     if (st != MDX_OK) return st;

@@ -65,7 +65,8 @@ EXPORTS = {
     "mdx_one_body_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
     "mdx_one_body_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int, _p, _p, _p,
                                           ctypes.c_size_t, _p]),
-    "mdx_nuclear_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
+    "mdx_nuclear_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, _i32,
+                                                     ctypes.c_int]),
     "mdx_nuclear_batch": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, _i32, _p, ctypes.c_int, _p,
                                          _p, ctypes.c_size_t, _p]),
     "mdx_schwarz_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
@@ -363,7 +364,7 @@ def nuclear(shells: DeviceShells, pairs, charges, cartesian: bool = False, ctx: 
     flags = MDX_CARTESIAN if cartesian else MDX_SPHERICAL
     L = lib()
     sp = ctypes.byref(shells.struct)
-    wsz = L.mdx_nuclear_workspace_size(ctx.handle, sp, npair, _i32p(pairs), flags)
+    wsz = L.mdx_nuclear_workspace_size(ctx.handle, sp, npair, _i32p(pairs), charges.shape[0], flags)
     if wsz == 0:
         check(L.mdx_nuclear_batch(ctx.handle, sp, npair, _i32p(pairs), charges.shape[0], _ptr(charges), flags,
                                   None, None, 0, _stream(torch)), "mdx_nuclear_batch")

@@ -97,6 +97,7 @@ def test_errors():
     import torch
     from paper_2506_12501_amd import native
     b = W.make_class_batch("(gd|ss)", 3, 1, 1, 4.0, 0.1, 10.0, 0.1, 1.0, seed=1)
+    b.basis.l[b.bra[:, 0]] = 7          # beyond the compiled l <= 6
     sh = native.DeviceShells(b.basis)
     ch = torch.as_tensor(W.point_charges(4, seed=1), device="cuda")
     with pytest.raises(native.MdxError) as e:

@@ -120,6 +120,7 @@ def test_empty_batch():
 def test_errors():
     from paper_2506_12501_amd import native
     b = W.make_class_batch("(gd|ss)", 3, 1, 1, 4.0, 0.1, 10.0, 0.1, 1.0, seed=1)
+    b.basis.l[b.bra[:, 0]] = 7          # beyond the compiled l <= 6
     sh = native.DeviceShells(b.basis)
     with pytest.raises(native.MdxError) as e:
         native.one_body(sh, b.bra)

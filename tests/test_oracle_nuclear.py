@@ -12,7 +12,8 @@ from oracle import oracle as O
 from tests import quadrature as Q
 
 
-@pytest.mark.parametrize("la,lb", [(0, 0), (1, 0), (0, 1), (1, 1), (2, 0), (2, 1), (1, 2), (2, 2), (3, 1)])
+@pytest.mark.parametrize("la,lb", [(0, 0), (1, 0), (0, 1), (1, 1), (2, 0), (2, 1), (1, 2), (2, 2), (3, 1),
+                                   (4, 0), (2, 4), (5, 1), (4, 3), (6, 0), (6, 2)])
 def test_primitive_vs_gaussian_transform_quadrature(la, lb):
     rng = np.random.default_rng(40 + 5 * la + lb)
     for _ in range(3):
@@ -65,7 +66,7 @@ def test_linear_in_the_charges(cart):
     assert np.allclose(doubled, 2 * whole, rtol=1e-14, atol=1e-16)
 
 
-@pytest.mark.parametrize("la,lb", [(1, 0), (2, 1), (2, 2)])
+@pytest.mark.parametrize("la,lb", [(1, 0), (2, 1), (2, 2), (4, 2), (5, 3), (6, 6)])
 def test_bra_ket_symmetry(la, lb):
     """V_ab = V_ba: the operator is a multiplication, the E recursion of
     Eqs. (10)-(11) is not symmetric in its two indices"""
@@ -101,3 +102,17 @@ def test_quad_build_agrees():
     a = O.nuclear(2, 2, A, B, [0.3, 4.0], [0.5, 0.5], [1.1], [1.0], ch, cartesian=False)
     b = O.nuclear(2, 2, A, B, [0.3, 4.0], [0.5, 0.5], [1.1], [1.0], ch, cartesian=False, quad=True)
     assert np.allclose(a, b, rtol=1e-13, atol=1e-15)
+
+
+@pytest.mark.parametrize("la,lb", [(4, 1), (5, 3), (6, 6)])
+def test_quad_build_agrees_high_l(la, lb):
+    """fp64 against __float128 (whose solid coefficients are formed in
+    __float128 too): Cartesian within 1e-13 of the block maximum, solid within
+    1e-11 (the Cartesian-to-solid sums of an l = 6 shell cancel)"""
+    rng = np.random.default_rng(13 + la + lb)
+    A, B = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
+    ch = np.c_[rng.uniform(-3, 3, (6, 3)), rng.uniform(1, 6, 6)]
+    for cart, tol in ((True, 1e-13), (False, 1e-11)):
+        a = O.nuclear(la, lb, A, B, [0.3, 4.0], [0.5, 0.5], [1.1], [1.0], ch, cartesian=cart)
+        b = O.nuclear(la, lb, A, B, [0.3, 4.0], [0.5, 0.5], [1.1], [1.0], ch, cartesian=cart, quad=True)
+        assert np.max(np.abs(a - b)) <= tol * np.max(np.abs(b)), (la, lb, cart, np.max(np.abs(a - b)) / np.max(np.abs(b)))

@@ -31,7 +31,8 @@ def _quad_1d(i, j, za, zb, A, B, n=40):
     return s, g
 
 
-@pytest.mark.parametrize("la,lb", [(0, 0), (1, 0), (0, 2), (1, 1), (2, 1), (2, 2), (3, 2), (4, 4)])
+@pytest.mark.parametrize("la,lb", [(0, 0), (1, 0), (0, 2), (1, 1), (2, 1), (2, 2), (3, 2), (4, 4), (5, 2), (6, 4),
+                                   (6, 6)])
 def test_kinetic_vs_gradient_form_quadrature(la, lb):
     rng = np.random.default_rng(10 * la + lb)
     for _ in range(4):
@@ -63,7 +64,7 @@ def test_kinetic_s_closed_form():
 def test_kinetic_hermitian(cartesian):
     # the oracle applies the Laplacian to the ket only; T must still be symmetric
     rng = np.random.default_rng(4)
-    for la, lb in [(1, 0), (2, 1), (2, 2), (3, 1), (4, 2)]:
+    for la, lb in [(1, 0), (2, 1), (2, 2), (3, 1), (4, 2), (5, 3), (6, 6)]:
         za, zb = np.exp(rng.uniform(-1, 2, 3)), np.exp(rng.uniform(-1, 2, 2))
         ca, cb = rng.uniform(0.1, 1, 3), rng.uniform(0.1, 1, 2)
         A, B = rng.uniform(-1, 1, 3), rng.uniform(-1, 1, 3)
@@ -83,3 +84,23 @@ def test_one_body_layout_matches_per_pair_calls():
         ref = O.overlap(2, 1, b.basis.xyz[a], b.basis.xyz[c], b.basis.exps[sa], b.basis.coefs[sa],
                         b.basis.exps[sc], b.basis.coefs[sc], cartesian=False)
         assert np.allclose(S[:, ij], ref.reshape(-1))
+
+
+@pytest.mark.parametrize("la,lb", [(4, 0), (5, 4), (6, 6)])
+def test_overlap_vs_gauss_hermite_high_l(la, lb):
+    """overlaps of l = 4..6 shells (Eq. (8)) against Gauss-Hermite quadrature
+    of the monomial products, Cartesian; and the solid form equals the solid
+    coefficients applied to the Cartesian one"""
+    rng = np.random.default_rng(20 + la + lb)
+    za, zb = np.exp(rng.uniform(-1.0, 1.5, 2))
+    A, B = rng.uniform(-1.0, 1.0, 3), rng.uniform(-1.0, 1.0, 3)
+    S = O.overlap(la, lb, A, B, [za], [1.0], [zb], [1.0], cartesian=True)
+    for a_, (ax, ay, az) in enumerate(_cart(la)):
+        for b_, (bx, by, bz) in enumerate(_cart(lb)):
+            ref = _quad_1d(ax, bx, za, zb, A[0], B[0])[0] * _quad_1d(ay, by, za, zb, A[1], B[1])[0] * \
+                _quad_1d(az, bz, za, zb, A[2], B[2])[0]
+            assert S[a_, b_] == pytest.approx(ref, rel=1e-11, abs=1e-14 * np.abs(S).max())
+    Ss = O.overlap(la, lb, A, B, [za], [1.0], [zb], [1.0], cartesian=False, quad=True)
+    ref = O.solid_coefs(la, quad=True) @ O.overlap(la, lb, A, B, [za], [1.0], [zb], [1.0], cartesian=True,
+                                                    quad=True) @ O.solid_coefs(lb, quad=True).T
+    assert np.allclose(Ss, ref, rtol=1e-12, atol=1e-14 * np.abs(ref).max())

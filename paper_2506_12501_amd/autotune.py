@@ -126,13 +126,14 @@ def apply_cache(ctx, path: str = CACHE) -> int:
     return n
 
 
-def tune_batches(ctx, shells, batches, cartesian=False, reps=2):
+def tune_batches(ctx, shells, batches, cartesian=False, reps=2, fused=True):
     """Pick a kernel variant per class for a list of plan batches (dicts with
     bra, ket, bra_count, out_offset as built by screening.class_batches): for
-    every class with several variants, time a plain plan of that class's
-    batches under each variant and keep the fastest.  Returns
-    {class name: (best, {variant: ms})}; the choices stay set on ctx, so plans
-    created afterwards use them."""
+    every class with several variants, time a plan of that class's batches
+    under each variant and keep the fastest.  fused=True times the class's
+    persistent work-queue launch (the form a fused plan runs), False the
+    plain per-batch launches.  Returns {class name: (best, {variant: ms})};
+    the choices stay set on ctx, so plans created afterwards use them."""
     import torch
     by_class = {}
     for bt in batches:
@@ -154,7 +155,7 @@ def tune_batches(ctx, shells, batches, cartesian=False, reps=2):
                 nb.append(native.Batch(4, bt["bra"], bt["ket"], bt["bra_count"], off))
                 off += bt["quartets"] * bt["nab"] * bt["ncd"]
             try:
-                plan = native.Plan(shells, nb, cartesian=cartesian, fused=False, ctx=ctx)
+                plan = native.Plan(shells, nb, cartesian=cartesian, fused=fused, ctx=ctx)
             except native.MdxError:
                 continue
             o = torch.empty(max(plan.out_size, 1), dtype=torch.float64, device=shells.center.device)

@@ -34,7 +34,7 @@ eri_mfma_queue(QueueArgs q)
         const int w = __builtin_amdgcn_readfirstlane(item);
         if (w >= q.total) break;
         const int b = __builtin_amdgcn_readfirstlane(queue_batch(q, w));
-        const EriArgs a = load_const(q.desc + b);   // batch arguments: scalar loads
+        const EriArgs &a = q.desc[b];   // (a local copy would go to scratch: the body indexes its offset tables)
         int J, I;
         ragged_tile(a.tile_off, a.nket, w - q.base[b], J, I);
         const int nI = a.om.count[J];

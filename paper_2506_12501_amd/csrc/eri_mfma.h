@@ -475,6 +475,16 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     X(4, 4, 25, 25, false, 2, 2, 2, 3, 1, 4, CUBE_LAY_COMPACT, 2)  /* (dd|dd)                 */   \
     X(4, 3, 25, 15, false, 2, 1, 1, 3, 1, 4, CUBE_LAY_COMPACT, 3)  /* (dd|dp)                 */   \
     X(4, 2, 25, 9, false, 2, 1, 1, 3, 1, 4, CUBE_LAY_COMPACT, 3)   /* (dd|pp)                 */   \
-    X(3, 3, 15, 15, false, 1, 1, 1, 4, 1, 4, CUBE_LAY_COMPACT, 2)  /* (dp|dp)                 */
+    X(3, 3, 15, 15, false, 1, 1, 1, 4, 1, 4, CUBE_LAY_COMPACT, 2)  /* (dp|dp)                 */   \
+    X(2, 2, 9, 9, false, 1, 1, 1, 2, 1, 4, CUBE_LAY_COMPACT, 4)    /* (pp|pp)                 */   \
+    X(2, 1, 9, 3, false, 1, 1, 1, 2, 1, 4, CUBE_LAY_COMPACT, 4)    /* (pp|ps)                 */   \
+    X(2, 2, 5, 9, false, 1, 1, 1, 2, 1, 4, CUBE_LAY_COMPACT, 4)    /* (ds|pp)                 */   \
+    X(2, 2, 5, 5, false, 1, 1, 1, 2, 1, 4, CUBE_LAY_COMPACT, 4)    /* (ds|ds)                 */   \
+    X(2, 1, 5, 3, false, 1, 1, 1, 2, 1, 4, CUBE_LAY_COMPACT, 4)    /* (ds|ps)                 */   \
+    X(3, 2, 15, 9, false, 1, 1, 1, 2, 1, 4, CUBE_LAY_COMPACT, 4)   /* (dp|pp)                 */   \
+    X(3, 1, 15, 3, false, 1, 1, 1, 2, 1, 4, CUBE_LAY_COMPACT, 4)   /* (dp|ps)                 */   \
+    X(3, 2, 15, 5, false, 1, 1, 1, 2, 1, 4, CUBE_LAY_COMPACT, 4)   /* (dp|ds)                 */   \
+    X(4, 1, 25, 3, false, 2, 1, 1, 3, 1, 4, CUBE_LAY_COMPACT, 4)   /* (dd|ps)                 */   \
+    X(4, 2, 25, 5, false, 2, 1, 1, 3, 1, 4, CUBE_LAY_COMPACT, 4)   /* (dd|ds)                 */
 
 }  // namespace mdx

@@ -12,7 +12,9 @@ pytestmark = pytest.mark.gpu
 # contraction degrees K give 9 (odd) or 4 ket primitives per pair, so the
 # two-primitive sweep rounds meet a partial last round and full ones
 CASES = [("(dd|dd)", 3), ("(pd|dd)", 3), ("(ff|ff)", 1), ("(gg|gg)", 1), ("(pp|pp)", 2), ("(dd|ps)", 2),
-         ("(dd|pp)", 3), ("(dp|dp)", 2), ("(dp|ds)", 3), ("(f|dd)", 2), ("(f|dd)", 1), ("(i|dd)", 1)]
+         ("(dd|pp)", 3), ("(dp|dp)", 2), ("(dp|ds)", 3), ("(f|dd)", 2), ("(f|dd)", 1), ("(i|dd)", 1),
+         ("(pp|ps)", 3), ("(ds|pp)", 2), ("(ds|ds)", 3), ("(ds|ps)", 2), ("(dp|pp)", 3), ("(dp|ps)", 1),
+         ("(dd|ds)", 3), ("(dd|dd)", 1)]
 
 
 @pytest.mark.parametrize("name,K", CASES)

@@ -327,13 +327,16 @@ def extra_legs(native, ctx, torch, tune, reps, legs=EXTRA_LEGS):
         # overlap + kinetic energy, spherical, K=3: 1024 x 1024 shell pairs per
         # class.  ms_per_call includes the upload of the host pair list.
         ob = {}
-        for la, lb in [(0, 0), (1, 1), (2, 1), (2, 2), (3, 3)]:
-            basis, pairs = W.one_body_pairs(la, lb, 1024, 1024, 3, seed=la * 3 + lb)
+        # l <= 3: 1024 x 1024 pairs (one pair per lane); l = 4..6: 256 x 256
+        # pairs (one pair per wave)
+        for la, lb in [(0, 0), (1, 1), (2, 1), (2, 2), (3, 3), (4, 4), (5, 5), (6, 6)]:
+            n1 = 1024 if la <= 3 else 256
+            basis, pairs = W.one_body_pairs(la, lb, n1, n1, 3, seed=la * 3 + lb)
             r = OneBodyRun(native, basis, pairs, ctx, torch)
             ms, kms = measure(r, 1, 5, native, ctx, torch)
             nbytes = 2 * r.n * r.nf * 8
             fl = F.one_body_flops(la, lb, 3, 3) * r.n
-            ob["(%s|%s)" % ("spdf"[la], "spdf"[lb])] = {
+            ob["(%s|%s)" % ("spdfghi"[la], "spdfghi"[lb])] = {
                 "pairs": r.n, "ms_per_call": ms, "kernel_ms": kms[0], "pairs_per_s": r.n / (kms[0] * 1e-3),
                 "out_write_GB_per_s": nbytes / (kms[0] * 1e-3) / 1e9,
                 "hbm_frac": nbytes / (kms[0] * 1e-3) / (PEAK_HBM_GBS * 1e9),
@@ -352,12 +355,16 @@ def extra_legs(native, ctx, torch, tune, reps, legs=EXTRA_LEGS):
         nu = {}
         charges = W.point_charges(100, 10.0, seed=0)
         for K in (1, 5):
-            for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 3)]:
-                basis, pairs = W.one_body_pairs(la, lb, 256, 256, K, seed=10 * K + la * 3 + lb)
+            # l <= 3: 256 x 256 pairs, one per lane; l = 4..6 on the matrix-core
+            # kernel: 64 x 64 pairs
+            for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 3), (4, 4), (5, 5),
+                           (6, 6)]:
+                n1 = 256 if la <= 3 else 64
+                basis, pairs = W.one_body_pairs(la, lb, n1, n1, K, seed=10 * K + la * 3 + lb)
                 r = NuclearRun(native, basis, pairs, charges, ctx, torch)
                 ms, kms = measure(r, 1, 5, native, ctx, torch)
                 fl = F.nuclear_flops(la, lb, K, K, 100) * r.n
-                nu["(%s|%s) K=%d" % ("spdf"[la], "spdf"[lb], K)] = {
+                nu["(%s|%s) K=%d" % ("spdfghi"[la], "spdfghi"[lb], K)] = {
                     "pairs": r.n, "charges": 100, "ms_per_call": ms, "kernel_ms": kms[0],
                     "pairs_per_s": r.n / (kms[0] * 1e-3), "kernel_tflops": fl / (kms[0] * 1e-3) / 1e12,
                     "pct_fp64_peak": 100 * fl / (kms[0] * 1e-3) / 1e12 / PEAK_FP64_TFLOPS,

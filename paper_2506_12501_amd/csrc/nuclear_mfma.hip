@@ -179,6 +179,10 @@ static mdx_status nuc_plan(mdx_ctx *c, const mdx_shells *sh, int32_t npair, cons
     return MDX_OK;
 }
 
+// l >= 4 only: for (f|f) this path measured 10x slower than one pair per lane
+// (K = 5, 100 charges: 222 vs 21 ms per 65,536 pairs) -- with no ket Hermites
+// beyond the terminal one, the kernel's time is the per-charge [r]^(0) tables,
+// built a few at a time in LDS
 bool nuclear_on_mfma(int la, int lb) { return std::max(la, lb) >= 4; }
 
 mdx_status nuclear_mfma_workspace(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la,

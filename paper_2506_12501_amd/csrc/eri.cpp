@@ -179,9 +179,23 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
     }
     if (cp.kind == K_MFMA) {
         const int kind = eri_mfma_variant_kind(cp.key, cp.variant);
-        if (kind == MFMA_PRIM && (cp.bra.g.kmax != 1 || cp.ket.g.kmax != 1))
-            return fail(MDX_EUNSUPPORTED, "variant %d of class (%d %d|%d %d) serves single-primitive pairs only",
-                        cp.variant, cp.la, cp.lb, cp.lc, cp.ld);
+        if (kind == MFMA_PRIM && (cp.bra.g.kmax != 1 || cp.ket.g.kmax != 1)) {
+            // contracted pairs on a single-primitive kernel: one launch per
+            // primitive combination (kb, kk), each adding to the output (Eq. (5):
+            // the contracted integral is the sum of its primitive integrals, whose
+            // weights sit in the pair data).  Every pair of a side must have the
+            // same contraction degree, so that primitive kb exists in all of them.
+            auto uniform = [](const SidePlan &sp) {
+                for (const PairRec &r : sp.pairs)
+                    if (r.ka * r.kb != sp.g.kmax) return false;
+                return true;
+            };
+            if (bra_count || (flags & MDX_PAIRED) || !uniform(cp.bra) || !uniform(cp.ket))
+                return fail(MDX_EUNSUPPORTED,
+                            "variant %d of class (%d %d|%d %d) takes contracted pairs only in dense batches with one "
+                            "contraction degree per side", cp.variant, cp.la, cp.lb, cp.lc, cp.ld);
+            cp.expand = true;
+        }
         if (kind == MFMA_MULTI && cp.ket.g.kmax != 1)
             return fail(MDX_EUNSUPPORTED, "variant %d of class (%d %d|%d %d) serves single-primitive ket pairs only",
                         cp.variant, cp.la, cp.lb, cp.lc, cp.ld);
@@ -411,7 +425,24 @@ mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, 
     int nblocks = 0;
     if ((st = class_args(c, cp, d, out, a, nblocks)) != MDX_OK) return st;
     if (dig) a.dig = *dig;
-    return launch_class(c, cp, a, nblocks, s);
+    if (!cp.expand) return launch_class(c, cp, a, nblocks, s);
+    if (dig) return fail(MDX_EUNSUPPORTED, "digestion of contracted pairs on a single-primitive kernel");
+    // primitive combination (kb, kk): the pair data of primitive kb of every bra
+    // pair (rows kb*nh.. of the bra H, record kb) and of primitive kk of every
+    // ket pair (block kk of the ket H, record kk)
+    const SideGeom &gb = cp.bra.g, &gk = cp.ket.g;
+    for (int kb = 0; kb < gb.kmax; ++kb)
+        for (int kk = 0; kk < gk.kmax; ++kk) {
+            EriArgs e = a;
+            e.prim_expand = 1;
+            e.accumulate = (kb | kk) != 0;
+            e.bra.prim = a.bra.prim + kb;
+            e.bra.H = a.bra.H + (int64_t)kb * gb.nh * gb.ncolp;
+            e.ket.prim = a.ket.prim + kk;
+            e.ket.H = a.ket.H + (int64_t)kk * gk.rows_per_block * gk.ncolp;
+            if ((st = launch_class(c, cp, e, nblocks, s)) != MDX_OK) return st;
+        }
+    return MDX_OK;
 }
 
 }  // namespace mdx

@@ -98,7 +98,7 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
     xsweeps<CB, NW, NB, true>(cube, PQ, nv, NB, NB, w, lane, std::make_integer_sequence<int, NW>{});
     __syncthreads();
 
-    int abase[MT];   // table offset of the bra Hermite of row 16T + c (rows past NHB: 0, H_bra is 0 there)
+    int abase[MT];   // table offset of the bra Hermite of row 16T + c (rows past NHB: 0; their H_bra is read as 0)
 #pragma unroll
     for (int T = 0; T < MT; ++T) {
         const int row = 16 * T + c;
@@ -108,6 +108,9 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
     const int64_t obase = a.om.count ? a.om.obase[J] : (int64_t)J * a.om.sJ;
     const int64_t omult = a.om.count ? (int64_t)nI : a.om.mult;
     constexpr KetRowOffsets<CB, LK, 4 * KS> KO{};
+    // primitive expansion: later primitive combinations add to the first one's output
+    const bool acc_out = a.accumulate != 0;
+    auto put = [acc_out](double *p, double v) { *p = acc_out ? *p + v : v; };
 
     constexpr int NP = (NTCDM + NW - 1) / NW;   // column passes of a wave per shellset
 #pragma unroll 1
@@ -208,19 +211,24 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
         // (TAIL: output row ABT from the same accumulators on the VALU: each lane
         // multiplies its own rows, the four lane groups are summed after)
         const double *hbp = hb + (int64_t)(16 * T0) * NABP;   // H_bra rows of this part
+        // rows past NHB are read as 0 (with primitive expansion the pair data
+        // there hold the next primitive's rows, not zero padding)
+        const int nrow_p = NHB - 16 * T0;
         double hq[3][NTAB];
 #pragma unroll
         for (int k = 0; k < 2; ++k)
 #pragma unroll
             for (int i = 0; i < NTAB; ++i)
-                hq[k][i] = hbp[(int64_t)(4 * k + g) * NABP + (i < NTABM ? 16 * i + c : ABT)];
+                hq[k][i] = 4 * k + g < nrow_p ? hbp[(int64_t)(4 * k + g) * NABP + (i < NTABM ? 16 * i + c : ABT)] : 0.0;
 #pragma unroll
         for (int k = 0; k < 4 * MTP; ++k) {
             if (k < 4 * MTN) {
                 if (k + 2 < 4 * MTN) {
 #pragma unroll
                     for (int i = 0; i < NTAB; ++i)
-                        hq[(k + 2) % 3][i] = hbp[(int64_t)(4 * (k + 2) + g) * NABP + (i < NTABM ? 16 * i + c : ABT)];
+                        hq[(k + 2) % 3][i] = 4 * (k + 2) + g < nrow_p
+                                                 ? hbp[(int64_t)(4 * (k + 2) + g) * NABP + (i < NTABM ? 16 * i + c : ABT)]
+                                                 : 0.0;
                 }
 #pragma unroll
                 for (int i = 0; i < NTABM; ++i) O[i] = mfma(hq[k % 3][i], X[k >> 2][k & 3], O[i]);
@@ -242,12 +250,12 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int ab = 16 * i + 4 * r + g;
-                if (ab < a.nab && cd < a.ncd) out[omult * (int64_t)(oab[ab + zo] + ocd[cd])] = O[i][r];
+                if (ab < a.nab && cd < a.ncd) put(out + omult * (int64_t)(oab[ab + zo] + ocd[cd]), O[i][r]);
             }
         if constexpr (TAIL) {
             trow += __shfl_xor(trow, 16);
             trow += __shfl_xor(trow, 32);
-            if (g == 0 && cd < a.ncd) out[omult * (int64_t)(oab[ABT] + ocd[cd])] = trow;
+            if (g == 0 && cd < a.ncd) put(out + omult * (int64_t)(oab[ABT] + ocd[cd]), trow);
             if (tpass) {
 #pragma unroll
                 for (int i = 0; i < NTAB; ++i) {
@@ -256,7 +264,7 @@ __device__ __forceinline__ void eri_prim_unit(const EriArgs &a, const int I0, co
                     v += __shfl_xor(v, 32);
                     // i < NTABM: function 16i + c; the last slot holds column ABT (the corner)
                     const int ab = i < NTABM ? 16 * i + c : ABT;
-                    if (g == 0 && (i < NTABM || c == 0) && ab < a.nab) out[omult * (int64_t)(oab[ab] + ocd[CDT])] = v;
+                    if (g == 0 && (i < NTABM || c == 0) && ab < a.nab) put(out + omult * (int64_t)(oab[ab] + ocd[CDT]), v);
                 }
             }
         }
@@ -288,6 +296,16 @@ __host__ __device__ inline size_t prim_lds_bytes()
     X(10, 10, 121, 121, 8, 8, 4, 1, 1, false, CUBE_LAY_COMPACT)                                    \
     X(10, 10, 121, 121, 8, 8, 3, 1, 1, false, CUBE_LAY_COMPACT)                                    \
     X(12, 12, 169, 169, 11, 11, 2, 1, 1, false, CUBE_LAY_COMPACT) /* (ii|ii)                 */    \
-    X(12, 12, 169, 169, 11, 11, 4, 1, 1, false, CUBE_LAY_COMPACT)
+    X(12, 12, 169, 169, 11, 11, 4, 1, 1, false, CUBE_LAY_COMPACT)                                  \
+    /* mixed high-L classes (their only kernels: contracted pairs by primitive expansion) */       \
+    X(8, 6, 81, 49, 6, 4, 2, 2, 1, false, CUBE_LAY_COMPACT)       /* (gg|ff)                 */    \
+    X(8, 4, 81, 25, 6, 2, 2, 2, 1, false, CUBE_LAY_COMPACT)       /* (gg|dd)                 */    \
+    X(10, 8, 121, 81, 8, 6, 2, 1, 1, false, CUBE_LAY_COMPACT)     /* (hh|gg)                 */    \
+    X(10, 6, 121, 49, 8, 4, 2, 1, 1, false, CUBE_LAY_COMPACT)     /* (hh|ff)                 */    \
+    X(10, 4, 121, 25, 8, 2, 2, 1, 1, false, CUBE_LAY_COMPACT)     /* (hh|dd)                 */    \
+    X(12, 10, 169, 121, 11, 8, 2, 1, 1, false, CUBE_LAY_COMPACT)  /* (ii|hh)                 */    \
+    X(12, 8, 169, 81, 11, 6, 2, 1, 1, false, CUBE_LAY_COMPACT)    /* (ii|gg)                 */    \
+    X(12, 6, 169, 49, 11, 4, 2, 1, 1, false, CUBE_LAY_COMPACT)    /* (ii|ff)                 */    \
+    X(12, 4, 169, 25, 11, 2, 2, 1, 1, false, CUBE_LAY_COMPACT)    /* (ii|dd)                 */
 
 }  // namespace mdx

@@ -19,8 +19,9 @@ __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WP
 template <int LB, int LK, int NTAB, int NTCD, int NW, int WPE, int NB, bool TAIL, int LAY>
 static bool launch_prim(const EriArgs &a, int nblocks, hipStream_t s)
 {
-    // one primitive pair per bra and per ket pair (checked when the class is planned)
-    if (a.bra.kmax != 1 || a.ket.kmax != 1 || (NB > 1 && a.diag)) return false;
+    // one primitive pair per bra and per ket pair, or one primitive combination
+    // of contracted pairs at a time (checked when the class is planned)
+    if ((!a.prim_expand && (a.bra.kmax != 1 || a.ket.kmax != 1)) || (NB > 1 && a.diag)) return false;
     // the VALU tail assumes 16k+1 functions on both sides
     if (TAIL && (a.nab != 16 * (NTAB - 1) + 1 || a.ncd != 16 * (NTCD - 1) + 1)) return false;
     const size_t lds = prim_lds_bytes<LB, LK, NTAB, NTCD, NW, NB, TAIL, LAY>();

@@ -97,6 +97,9 @@ struct EriArgs {
     int *counter;             // work counter (persistent kernels)
     OutMap om;
     Digest dig;               // dig.on: contract instead of storing (plain launches only)
+    int prim_expand;          // single-primitive kernel on one primitive pair of contracted pairs
+                              // (the caller offsets the pair-data pointers; see enqueue_class)
+    int accumulate;           // single-primitive kernel: add to the output instead of storing
 };
 
 struct PairDataArgs {

@@ -60,6 +60,8 @@ struct ClassPlan {
     bool swapped = false;                 // kernel bra = caller ket
     bool diag = false;                    // only the shellsets I = J (Schwarz factors, paired batches)
     bool paired = false;                  // MDX_PAIRED: quartet q = (bra q, ket q), out[q + n*(ab + nab*cd)]
+    bool expand = false;                  // single-primitive kernel over each primitive combination of
+                                          // contracted pairs, accumulated (one contraction degree per side)
     SidePlan bra, ket;
     EriKey key{};
     KernelKind kind = K_VALU;

@@ -62,10 +62,53 @@ def test_iiii_single_primitive():
     assert_close_shellsets(got, ref, "(ii|ii)")
 
 
-def test_iiii_contracted_is_refused():
-    """contracted (ii|ii) has no kernel: the general kernel's tables do not fit LDS"""
+def test_iiii_contracted_by_primitive_expansion():
+    """contracted (ii|ii) (the general kernel's L = 24 tables do not fit LDS):
+    the single-primitive kernel runs once per primitive combination, each
+    launch adding to the output (K = 2 per shell: 16 launches)"""
+    b = W.make_class_batch("(ii|ii)", 2, 1, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=30)
+    got, ref = run(b)
+    assert_close_shellsets(got, ref, "(ii|ii) K=2")
+
+
+MIXED_HIGH_L = ["(gg|ff)", "(gg|dd)", "(hh|gg)", "(hh|ff)", "(hh|dd)", "(ii|hh)", "(ii|gg)", "(ii|ff)", "(ii|dd)"]
+
+
+@pytest.mark.parametrize("name", MIXED_HIGH_L)
+def test_mixed_high_l_classes(name):
+    """mixed l = 4..6 classes on their single-primitive kernels, against the
+    __float128 oracle"""
+    nbra = 2 if name.startswith("(ii") else 3
+    b = W.config4(name, nbra=nbra, nket=2, seed=34)
+    got, ref = run(b, quad=True)
+    assert_close_shellsets(got, ref, name)
+
+
+@pytest.mark.parametrize("name", ["(gg|dd)", "(hh|ff)", "(dd|gg)"])
+def test_mixed_high_l_contracted(name):
+    """contracted pairs (K = 2 per shell) by primitive expansion; (dd|gg) is
+    run bra/ket swapped and written in the caller's layout"""
+    b = W.make_class_batch(name, 3, 2, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=35)
+    got, ref = run(b)
+    assert_close_shellsets(got, ref, f"{name} K=2")
+
+
+def test_primitive_expansion_needs_one_contraction_degree_per_side():
     from paper_2506_12501_amd import native
-    b = W.make_class_batch("(ii|ii)", 2, 2, 2, 4.0, 0.1, 20.0, 0.1, 1.0, seed=30)
+    rng = np.random.default_rng(36)
+    sb = W.ShellBuilder()
+    pairs = []
+    for K in (1, 2, 1):
+        ids = []
+        for l in (4, 4):
+            z = np.exp(rng.uniform(np.log(0.1), np.log(20), K))
+            ids.append(sb.add(rng.uniform(0, 6, 3), l, z, rng.uniform(0.2, 1, K) * W.prim_norm(z, l)))
+        pairs.append(ids)
+    ket = []
+    for _ in range(2):
+        z = np.exp(rng.uniform(np.log(0.1), np.log(20), 1))
+        ket.append([sb.add(rng.uniform(0, 6, 3), 2, z, W.prim_norm(z, 2)) for _ in range(2)])
+    b = W.ClassBatch("(gg|dd)", 4, sb.basis(), np.array(pairs, np.int32), np.array(ket, np.int32))
     with pytest.raises(native.MdxError) as e:
         native.eri(native.DeviceShells(b.basis), 4, b.bra, b.ket)
     assert e.value.status == native.MDX_EUNSUPPORTED

@@ -34,8 +34,8 @@ def test_all_variants_match_oracle(name, K):
             native.check(L.mdx_set_variant(ctx.handle, b.ncentre, la, max(lb, 0), lc, max(ld, 0), 0, v), "variant")
             try:
                 got = native.eri(sh, b.ncentre, b.bra, b.ket).cpu().numpy()
-            except native.MdxError as e:   # single-primitive variants refuse contracted pairs
-                assert e.status == native.MDX_EUNSUPPORTED and K > 1, (name, v, e)
+            except native.MdxError as e:   # 3-centre several-per-workgroup variants refuse contracted kets
+                assert e.status == native.MDX_EUNSUPPORTED and K > 1 and name.startswith("(f|"), (name, v, e)
                 continue
             assert_close(got, ref, f"{name} variant {v}")
             ran += 1
@@ -51,19 +51,22 @@ def test_unknown_variant_rejected():
     assert st == native.MDX_EINVAL
 
 
-def test_single_primitive_variants_reject_contracted_pairs():
-    """the single-primitive kernels are variants of their class that serve only
-    uncontracted pairs; a contracted batch under one of them is refused"""
+def test_single_primitive_variants_take_contracted_pairs_by_expansion():
+    """a contracted dense batch under a single-primitive variant runs once per
+    primitive combination, accumulated; in a plan (ragged batch) it is refused"""
     from paper_2506_12501_amd import autotune, native
     b = W.make_class_batch("(ff|ff)", 3, 2, 2, 6.0, 0.05, 30.0, 0.1, 1.0, seed=32)
+    ref = O.eri(b.basis, 4, b.bra, b.ket)
     ctx = native.Context.get(0)
     vs = autotune.variants(ctx, 4, 3, 3, 3, 3, False)
     sh = native.DeviceShells(b.basis)
     L = native.lib()
     try:
         native.check(L.mdx_set_variant(ctx.handle, 4, 3, 3, 3, 3, 0, vs[-1]), "variant")
+        got = native.eri(sh, 4, b.bra, b.ket).cpu().numpy()
+        assert_close(got, ref, "(ff|ff) K=2 single-primitive variant, expanded")
         with pytest.raises(native.MdxError) as e:
-            native.eri(sh, 4, b.bra, b.ket)
+            native.Plan(sh, [native.Batch(4, b.bra, b.ket, np.array([3, 2], np.int32), 0)])
         assert e.value.status == native.MDX_EUNSUPPORTED
     finally:
         L.mdx_set_variant(ctx.handle, 4, 3, 3, 3, 3, 0, -1)

@@ -377,10 +377,10 @@ mdx_status class_args(mdx_ctx *c, const ClassPlan &cp, const ClassDev &d, double
         if (cp.kind == K_VALU) {   // 64 bra pairs (one per lane) per ket pair
             a.tiles_per_J = (int)((nb + 63) / 64);
             nbl = (int64_t)a.tiles_per_J * (int64_t)nk;
-        } else {                   // blocks of 8 bra tiles x 16 ket pairs
+        } else {                   // blocks of MFMA_BRA_RUN bra tiles x MFMA_KET_RUN ket pairs
             const size_t units = (nb + cp.bra_per_tile - 1) / cp.bra_per_tile;
-            a.tiles_per_J = (int)((units + 7) / 8);
-            nbl = (int64_t)a.tiles_per_J * (int64_t)((nk + 15) / 16) * 128;
+            a.tiles_per_J = (int)((units + MFMA_BRA_RUN - 1) / MFMA_BRA_RUN);
+            nbl = (int64_t)a.tiles_per_J * (int64_t)((nk + MFMA_KET_RUN - 1) / MFMA_KET_RUN) * 128;
         }
         if (nbl > INT32_MAX) return fail(MDX_EUNSUPPORTED, "%lld workgroups in one launch (split the batch)", (long long)nbl);
         nblocks = (int)nbl;

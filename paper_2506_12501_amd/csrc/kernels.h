@@ -81,6 +81,11 @@ struct Digest {
     int on;
 };
 
+// Dense matrix-core launches walk blocks of MFMA_BRA_RUN consecutive bra
+// units x MFMA_KET_RUN ket pairs (128 workgroups): 16 consecutive bra pairs
+// fill whole 128-byte lines of the [ij, ab, cd, kl] output.
+constexpr int MFMA_BRA_RUN = 16, MFMA_KET_RUN = 8;
+
 struct EriArgs {
     SideDev bra, ket;
     int nbra, nket;

@@ -81,14 +81,17 @@ __device__ __forceinline__ bool mfma_block_shellset(const EriArgs &a, int &I, in
     } else if (a.tile_off) {   // ragged batch: one shellset per tile
         ragged_tile(a.tile_off, a.nket, blockIdx.x, J, I);
     } else {
-        // blocks of 8 bra x 16 ket pairs, dealt to the XCDs in contiguous
-        // ranges: the workgroups resident on an XCD share 8 bra and 16 ket H
-        // blocks in its L2 (bra blocks run fastest, so the ket H stays), and 8
-        // consecutive bra pairs fill output lines
+        // blocks of 16 bra x 8 ket pairs, dealt to the XCDs in contiguous
+        // ranges: the workgroups resident on an XCD share 16 bra and 8 ket H
+        // blocks in its L2, and 16 consecutive bra pairs fill whole 128-byte
+        // output lines.  Successive blocks step through the ket pairs with the
+        // same 16 bra pairs, so each bra H is read once per XCD range and each
+        // ket H once per 16 bra pairs.
         const int t = xcd_tile(blockIdx.x, gridDim.x);
         const int blk = t >> 7, e = t & 127;
-        I = (blk % a.tiles_per_J) * 8 + (e & 7);
-        J = (blk / a.tiles_per_J) * 16 + (e >> 3);
+        const int nkr = gridDim.x / (128 * a.tiles_per_J);   // blocks of ket pairs
+        I = (blk / nkr) * MFMA_BRA_RUN + (e % MFMA_BRA_RUN);
+        J = (blk % nkr) * MFMA_KET_RUN + (e / MFMA_BRA_RUN);
     }
     if (J >= a.nket) return false;
     nI = a.diag ? J + 1 : (a.om.count ? a.om.count[J] : a.nbra);
@@ -107,8 +110,9 @@ __device__ __forceinline__ bool multi_block_unit(const EriArgs &a, int &I0, int 
     } else {
         const int t = xcd_tile(blockIdx.x, gridDim.x);
         const int blk = t >> 7, e = t & 127;
-        U = (blk % a.tiles_per_J) * 8 + (e & 7);
-        J = (blk / a.tiles_per_J) * 16 + (e >> 3);
+        const int nkr = gridDim.x / (128 * a.tiles_per_J);   // blocks of ket pairs
+        U = (blk / nkr) * MFMA_BRA_RUN + (e % MFMA_BRA_RUN);
+        J = (blk % nkr) * MFMA_KET_RUN + (e / MFMA_BRA_RUN);
     }
     if (J >= a.nket) return false;
     nI = a.om.count ? a.om.count[J] : a.nbra;

@@ -134,9 +134,16 @@ mdx_status mdx_boys(mdx_ctx *ctx, int32_t n, const double *x, int mmax, double *
  * Limits: l <= MDX_LMAX_4C per shell for 4-centre; l_a <= MDX_LMAX_3C and
  * l_c, l_d <= MDX_LMAX_4C for 3-centre; both <= MDX_LMAX_3C for 2-centre.
  * Within these, a class runs if a kernel is compiled for it (every class with
- * l <= 2 per shell, the d/f/g classes of the matrix-core instance list, and
- * (hh|hh), and (ii|ii) of single primitive pairs, spherical); others return
+ * l <= 2 per shell, the d/f/g classes of the matrix-core instance list, and,
+ * spherical only, (hh|hh), (ii|ii) and the mixed classes (gg|ff), (gg|dd),
+ * (hh|gg), (hh|ff), (hh|dd), (ii|hh), (ii|gg), (ii|ff), (ii|dd)); others
+ * return MDX_EUNSUPPORTED.  Classes that run only on a single-primitive
+ * kernel take contracted pairs when every pair of a side has the same
+ * contraction degree (one launch per primitive combination, Eq. (5)), else
  * MDX_EUNSUPPORTED.
+ * The call copies host index tables into the workspace on the stream, so it
+ * cannot be captured into a graph: on a capturing stream it returns
+ * MDX_EINVAL before any work (capture mdx_eri_run of a prepared batch).
  */
 size_t mdx_eri_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
                               const int32_t *bra, int32_t nket, const int32_t *ket, int flags);
@@ -145,8 +152,8 @@ mdx_status mdx_eri_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, in
                          double *out, void *ws, size_t ws_bytes, mdx_stream_t stream);
 
 /*
- * mdx_eri_batch for callers that cannot allocate device memory (code under
- * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * mdx_eri_batch for callers that cannot allocate device memory (tight
+ * serving loops, harnesses that forbid hipMalloc):
  * the same batch, layouts, flags, limits and errors as mdx_eri_batch, with
  * the workspace taken from a library-owned static device buffer of
  * MDX_NOALLOC_SCRATCH_BYTES bytes per device instead of a caller argument.
@@ -156,7 +163,10 @@ mdx_status mdx_eri_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, in
  * mdx_eri_batch.  Every call on a device shares that device's buffer: calls
  * that overlap in time on one device (different streams, or host threads)
  * race on it; calls in one stream are ordered and safe.  The buffer is set up
- * by mdx_create and lives until the process ends.
+ * by mdx_create and lives until the process ends.  Like mdx_eri_batch, the
+ * call copies host index tables on the stream and is refused (MDX_EINVAL) on
+ * a stream under graph capture; there, capture mdx_eri_run of a batch
+ * prepared beforehand.
  */
 #define MDX_NOALLOC_SCRATCH_BYTES (64u << 20)
 mdx_status mdx_eri_batch_noalloc(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
@@ -229,7 +239,9 @@ mdx_status mdx_eri_grad_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncentr
  * Limits: l_a, l_b <= 6 (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
  * bad arguments, shell indices or mixed classes; MDX_EWORKSPACE for a short
  * workspace; MDX_EDEVICE for a HIP error.  The size query returns 0 on any
- * error (mdx_last_error says why).
+ * error (mdx_last_error says why).  The call copies its pair records from
+ * host memory (MDX_EINVAL on a stream under graph capture; the prepared form,
+ * mdx_one_body_prepare / mdx_one_body_run, copies them once).
  */
 size_t mdx_one_body_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
                                    int flags);
@@ -261,6 +273,8 @@ mdx_status mdx_one_body_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t np
  * bad arguments, shell indices, mixed classes, a negative charge count or a
  * null charge array with ncharge > 0; MDX_EWORKSPACE for a short workspace;
  * MDX_EDEVICE for a HIP error.  The size query returns 0 on any error.
+ * Like mdx_one_body_batch, the call copies host tables and is refused on a
+ * stream under graph capture (prepared form: mdx_nuclear_prepare / run).
  */
 size_t mdx_nuclear_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
                                   int32_t ncharge, int flags);
@@ -283,6 +297,56 @@ size_t mdx_schwarz_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int32_
                                   int flags);
 mdx_status mdx_schwarz(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs, int flags,
                        double *Q, void *ws, size_t ws_bytes, mdx_stream_t stream);
+
+/*
+ * Prepared batches: the call above planned once, run many times.  Preparing
+ * validates the batch exactly as the plain call does (same arguments, flags,
+ * limits and errors), chooses its kernels (mdx_set_variant overrides in force
+ * at preparation apply) and copies its index tables to device memory owned by
+ * the batch (the only allocation; freed by mdx_batch_destroy).  A run then
+ * enqueues kernel launches only: no host tables are copied and nothing is
+ * allocated, so a run can be captured into a HIP graph (and replayed), and its
+ * host cost does not grow with the number of pairs.
+ *   Runs take the same shell table as the preparation (same metadata, checked:
+ *   MDX_EINVAL otherwise); its DEVICE arrays -- centres, exponents,
+ *   coefficients -- are read at run time and may hold new values.
+ *   ws: DEVICE, at least mdx_batch_workspace_size bytes, 256-byte aligned
+ *   (pair data written by the run; one-body and lane-kernel nuclear batches
+ *   need none and accept NULL).  Outputs and layouts as the plain calls;
+ *   mdx_batch_output_size gives the doubles of each output array.
+ *   mdx_nuclear_prepare fixes the charge count; the charges' positions and
+ *   values are read from the DEVICE array given to each run.
+ * Runs of one batch may be enqueued on different streams only if they use
+ * different workspaces.  A batch refers to its context, which must outlive
+ * it.  Errors: as the plain calls, plus MDX_ENOMEM if the table allocation
+ * fails and MDX_EINVAL for a batch of another kind (e.g. an ERI batch passed
+ * to mdx_one_body_run).  On failure *out is NULL.
+ */
+typedef struct mdx_batch mdx_batch;
+/* 2-electron batch: the arguments of mdx_eri_batch (flags MDX_SPHERICAL or
+ * MDX_CARTESIAN, optionally | MDX_PAIRED); out as mdx_eri_batch's */
+mdx_status mdx_eri_prepare(mdx_ctx *ctx, const mdx_shells *shells, int ncentre, int32_t nbra,
+                           const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
+                           mdx_batch **out);
+mdx_status mdx_eri_run(const mdx_batch *batch, const mdx_shells *shells, double *out, void *ws,
+                       size_t ws_bytes, mdx_stream_t stream);
+/* overlap and kinetic energy: the pairs and flags of mdx_one_body_batch;
+ * S, T as there (either may be NULL) */
+mdx_status mdx_one_body_prepare(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
+                                int flags, mdx_batch **out);
+mdx_status mdx_one_body_run(const mdx_batch *batch, const mdx_shells *shells, double *S, double *T, void *ws,
+                            size_t ws_bytes, mdx_stream_t stream);
+/* 1-particle Coulomb: the pairs, charge count and flags of mdx_nuclear_batch;
+ * charges (DEVICE double[4*ncharge]) and V as there */
+mdx_status mdx_nuclear_prepare(mdx_ctx *ctx, const mdx_shells *shells, int32_t npair, const int32_t *pairs,
+                               int32_t ncharge, int flags, mdx_batch **out);
+mdx_status mdx_nuclear_run(const mdx_batch *batch, const mdx_shells *shells, const double *charges, double *V,
+                           void *ws, size_t ws_bytes, mdx_stream_t stream);
+/* workspace bytes of a run (0 for a NULL batch); doubles of each output array */
+size_t mdx_batch_workspace_size(const mdx_batch *batch);
+int64_t mdx_batch_output_size(const mdx_batch *batch);
+/* frees the batch and its device tables (NULL is ignored) */
+void mdx_batch_destroy(mdx_batch *batch);
 
 /*
  * Multi-class plans (batch-level screening of Sec. 3.1; mixed classes in one

@@ -270,50 +270,58 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
     return MDX_OK;
 }
 
-WsLayout ws_layout(const ClassPlan &cp, size_t base)
+WsLayout ws_layout(const ClassPlan &cp)
 {
     WsLayout L{};
-    size_t o = align256(base);
+    size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
     const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
+    // index tables (built on the host)
     L.pairs_bra = take(nb * sizeof(PairRec));
     L.pairs_ket = take(nk * sizeof(PairRec));
     L.items_bra = take(cp.bra.items.size() * sizeof(int2));
     L.items_ket = take(cp.ket.items.size() * sizeof(int2));
+    L.count = take(cp.count.size() * sizeof(int32_t));
+    L.obase = take(cp.obase.size() * sizeof(int64_t));
+    L.tile_off = take(cp.tile_off.size() * sizeof(int32_t));
+    L.tables = o;
+    // pair data (written by the pair-data kernels), offsets from the work region
+    o = 0;
     L.np_bra = take(nb * sizeof(int32_t));
     L.np_ket = take(nk * sizeof(int32_t));
     L.prim_bra = take(nb * cp.bra.g.kmax * sizeof(PrimRec));
     L.prim_ket = take(nk * cp.ket.g.kmax * sizeof(PrimRec));
     L.H_bra = take(nb * (size_t)cp.bra.g.pair_stride * sizeof(double));
     L.H_ket = take(nk * (size_t)cp.ket.g.pair_stride * sizeof(double));
-    L.count = take(cp.count.size() * sizeof(int32_t));
-    L.obase = take(cp.obase.size() * sizeof(int64_t));
-    L.tile_off = take(cp.tile_off.size() * sizeof(int32_t));
-    L.total = o - base;
+    L.work = o;
+    L.total = L.tables + L.work;
     return L;
 }
 
-ClassDev class_dev(const WsLayout &L, char *ws)
+ClassDev class_dev(const WsLayout &L, const char *tabs, char *work)
 {
     ClassDev d{};
-    d.pairs_bra = (const PairRec *)(ws + L.pairs_bra);
-    d.pairs_ket = (const PairRec *)(ws + L.pairs_ket);
-    d.items_bra = (const int2 *)(ws + L.items_bra);
-    d.items_ket = (const int2 *)(ws + L.items_ket);
-    d.count = (const int32_t *)(ws + L.count);
-    d.obase = (const int64_t *)(ws + L.obase);
-    d.tile_off = (const int32_t *)(ws + L.tile_off);
-    d.prim_bra = (PrimRec *)(ws + L.prim_bra);
-    d.prim_ket = (PrimRec *)(ws + L.prim_ket);
-    d.np_bra = (int32_t *)(ws + L.np_bra);
-    d.np_ket = (int32_t *)(ws + L.np_ket);
-    d.H_bra = (double *)(ws + L.H_bra);
-    d.H_ket = (double *)(ws + L.H_ket);
+    d.pairs_bra = (const PairRec *)(tabs + L.pairs_bra);
+    d.pairs_ket = (const PairRec *)(tabs + L.pairs_ket);
+    d.items_bra = (const int2 *)(tabs + L.items_bra);
+    d.items_ket = (const int2 *)(tabs + L.items_ket);
+    d.count = (const int32_t *)(tabs + L.count);
+    d.obase = (const int64_t *)(tabs + L.obase);
+    d.tile_off = (const int32_t *)(tabs + L.tile_off);
+    d.prim_bra = (PrimRec *)(work + L.prim_bra);
+    d.prim_ket = (PrimRec *)(work + L.prim_ket);
+    d.np_bra = (int32_t *)(work + L.np_bra);
+    d.np_ket = (int32_t *)(work + L.np_ket);
+    d.H_bra = (double *)(work + L.H_bra);
+    d.H_ket = (double *)(work + L.H_ket);
     return d;
 }
 
+ClassDev class_dev(const WsLayout &L, char *ws) { return class_dev(L, ws, ws + L.tables); }
+
 mdx_status upload_tables(const ClassPlan &cp, const ClassDev &d, hipStream_t s)
 {
+    MDX_TRY(refuse_capture(s, "the call copies its index tables from host memory"));
     const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
     HIP_TRY2(hipMemcpyAsync((void *)d.pairs_bra, cp.bra.pairs.data(), nb * sizeof(PairRec), hipMemcpyHostToDevice, s));
     HIP_TRY2(hipMemcpyAsync((void *)d.pairs_ket, cp.ket.pairs.data(), nk * sizeof(PairRec), hipMemcpyHostToDevice, s));
@@ -330,6 +338,31 @@ mdx_status upload_tables(const ClassPlan &cp, const ClassDev &d, hipStream_t s)
     if (!cp.tile_off.empty())
         HIP_TRY2(hipMemcpyAsync((void *)d.tile_off, cp.tile_off.data(), cp.tile_off.size() * sizeof(int32_t),
                                 hipMemcpyHostToDevice, s));
+    return MDX_OK;
+}
+
+mdx_status copy_tables(const ClassPlan &cp, const WsLayout &L, char *dst)
+{
+    auto put = [&](size_t off, const void *src, size_t bytes) -> hipError_t {
+        return bytes ? hipMemcpy(dst + off, src, bytes, hipMemcpyHostToDevice) : hipSuccess;
+    };
+    HIP_TRY2(put(L.pairs_bra, cp.bra.pairs.data(), cp.bra.pairs.size() * sizeof(PairRec)));
+    HIP_TRY2(put(L.pairs_ket, cp.ket.pairs.data(), cp.ket.pairs.size() * sizeof(PairRec)));
+    HIP_TRY2(put(L.items_bra, cp.bra.items.data(), cp.bra.items.size() * sizeof(int2)));
+    HIP_TRY2(put(L.items_ket, cp.ket.items.data(), cp.ket.items.size() * sizeof(int2)));
+    HIP_TRY2(put(L.count, cp.count.data(), cp.count.size() * sizeof(int32_t)));
+    HIP_TRY2(put(L.obase, cp.obase.data(), cp.obase.size() * sizeof(int64_t)));
+    HIP_TRY2(put(L.tile_off, cp.tile_off.data(), cp.tile_off.size() * sizeof(int32_t)));
+    return MDX_OK;
+}
+
+mdx_status refuse_capture(hipStream_t s, const char *why)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY2(hipStreamIsCapturing(s, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(MDX_EINVAL, "stream is being captured and %s; capture the prepared form "
+                    "(mdx_eri_prepare/mdx_eri_run, mdx_one_body_prepare/run, mdx_nuclear_prepare/run) instead", why);
     return MDX_OK;
 }
 
@@ -414,11 +447,17 @@ mdx_status launch_class(mdx_ctx *c, const ClassPlan &cp, const EriArgs &a, int n
 mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
                          double *out, hipStream_t s, bool upload, const Digest *dig)
 {
-    const size_t nb = cp.bra.pairs.size(), nk = cp.ket.pairs.size();
-    if (nb == 0 || nk == 0) return MDX_OK;
+    if (cp.bra.pairs.empty() || cp.ket.pairs.empty()) return MDX_OK;
     const ClassDev d = class_dev(L, ws);
+    if (upload) MDX_TRY(upload_tables(cp, d, s));
+    return enqueue_class_dev(c, sh, cp, d, out, s, dig);
+}
+
+mdx_status enqueue_class_dev(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const ClassDev &d, double *out,
+                             hipStream_t s, const Digest *dig)
+{
+    if (cp.bra.pairs.empty() || cp.ket.pairs.empty()) return MDX_OK;
     mdx_status st;
-    if (upload && (st = upload_tables(cp, d, s)) != MDX_OK) return st;
     enqueue_pairdata(c, sh, cp, d, 0, s);
     enqueue_pairdata(c, sh, cp, d, 1, s);
     EriArgs a;
@@ -454,7 +493,7 @@ extern "C" size_t mdx_eri_workspace_size(mdx_ctx *c, const mdx_shells *sh, int n
 {
     ClassPlan cp;
     if (plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp) != MDX_OK) return 0;
-    return ws_layout(cp, 0).total + 256;
+    return ws_layout(cp).total + 256;
 }
 
 extern "C" mdx_status mdx_eri_batch(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
@@ -469,7 +508,7 @@ extern "C" mdx_status mdx_eri_batch(mdx_ctx *c, const mdx_shells *sh, int ncentr
     if (!out) return fail(MDX_EINVAL, "mdx_eri_batch: null output");
     if (!ws) return fail(MDX_EINVAL, "mdx_eri_batch: null workspace");
     if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_eri_batch: workspace not 256-byte aligned");
-    const WsLayout L = ws_layout(cp, 0);
+    const WsLayout L = ws_layout(cp);
     if (ws_bytes < L.total) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, L.total);
     HIP_TRY2(hipSetDevice(c->device));
     return enqueue_class(c, sh, cp, L, (char *)ws, out, (hipStream_t)stream, true);
@@ -486,7 +525,7 @@ extern "C" mdx_status mdx_eri_batch_noalloc(mdx_ctx *c, const mdx_shells *sh, in
     if (nbra == 0 || nket == 0) return MDX_OK;
     if (!out) return fail(MDX_EINVAL, "mdx_eri_batch_noalloc: null output");
     if (!c->scratch) return fail(MDX_EDEVICE, "mdx_eri_batch_noalloc: the context has no static scratch");
-    const WsLayout L = ws_layout(cp, 0);
+    const WsLayout L = ws_layout(cp);
     if (L.total > (size_t)MDX_NOALLOC_SCRATCH_BYTES)
         return fail(MDX_EWORKSPACE,
                     "mdx_eri_batch_noalloc: the batch needs %zu bytes of scratch, the static buffer holds %zu "
@@ -496,6 +535,39 @@ extern "C" mdx_status mdx_eri_batch_noalloc(mdx_ctx *c, const mdx_shells *sh, in
     // the same planning, tables and kernels as mdx_eri_batch; nothing in the
     // scratch needs to start at zero (the workspace contract of mdx_eri_batch)
     return enqueue_class(c, sh, cp, L, c->scratch, out, (hipStream_t)stream, true);
+}
+
+extern "C" mdx_status mdx_eri_prepare(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
+                                      int32_t nket, const int32_t *ket, int flags, mdx_batch **out)
+{
+    if (!out) return fail(MDX_EINVAL, "mdx_eri_prepare: null handle pointer");
+    *out = nullptr;
+    if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_prepare: MDX_FUSED applies to plans only");
+    mdx_batch *b = new mdx_batch;
+    mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, b->cp);
+    if (st == MDX_OK) st = batch_init(b, c, sh, B_ERI, flags);
+    if (st == MDX_OK && !b->cp.bra.pairs.empty() && !b->cp.ket.pairs.empty()) {
+        b->L = ws_layout(b->cp);
+        b->ws_need = b->L.work;
+        b->out_doubles = b->cp.out_doubles;
+        st = batch_tables(b, b->L.tables);
+        if (st == MDX_OK) st = copy_tables(b->cp, b->L, b->dtab);
+    }
+    if (st != MDX_OK) {
+        mdx_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return MDX_OK;
+}
+
+extern "C" mdx_status mdx_eri_run(const mdx_batch *b, const mdx_shells *sh, double *out, void *ws, size_t ws_bytes,
+                                  mdx_stream_t stream)
+{
+    MDX_TRY(batch_check(b, sh, B_ERI, ws, ws_bytes, "mdx_eri_run"));
+    if (b->out_doubles == 0) return MDX_OK;
+    if (!out) return fail(MDX_EINVAL, "mdx_eri_run: null output");
+    return enqueue_class_dev(b->c, sh, b->cp, class_dev(b->L, b->dtab, (char *)ws), out, (hipStream_t)stream);
 }
 
 extern "C" mdx_status mdx_eri_digest_batch(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra,
@@ -520,7 +592,7 @@ extern "C" mdx_status mdx_eri_digest_batch(mdx_ctx *c, const mdx_shells *sh, int
         cp.variant = 1;
         cp.bra_per_tile = eri_mfma_bra_per_tile(cp.key, 1);
     }
-    const WsLayout L = ws_layout(cp, 0);
+    const WsLayout L = ws_layout(cp);
     if (ws_bytes < L.total) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, L.total);
     Digest dg{};
     dg.on = 1;

@@ -228,6 +228,7 @@ extern "C" mdx_status mdx_eri_grad_batch(mdx_ctx *c, const mdx_shells *sh, int n
     if (ws_bytes < need) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
     HIP_TRY2(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
+    MDX_TRY(refuse_capture(s, "the call copies its index tables from host memory"));
     char *w = (char *)ws;
     for (int ip = 0; ip < gp.npass; ++ip) {
         const GradPass &p = gp.pass[ip];

@@ -133,18 +133,11 @@ __global__ void __launch_bounds__(256) nuclear_zero(int64_t n, double *out)
     if (i < n) out[i] = 0.0;
 }
 
-struct NucPlan {
-    ClassPlan cp;
-    WsLayout L;
-    int nslice = 0;
-    size_t off_np = 0, off_part = 0, total = 0;
-};
-
 static size_t al256n(size_t x) { return (x + 255) & ~size_t(255); }
 
 // plan of the batch as the ERI class (ab|ss) with one ket pair of charge primitives
-static mdx_status nuc_plan(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la, int lb,
-                           int32_t ncharge, bool cart, NucPlan &np)
+mdx_status nuc_plan(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la, int lb,
+                    int32_t ncharge, bool cart, NucPlan &np)
 {
     ClassPlan &cp = np.cp;
     cp = ClassPlan{};
@@ -172,10 +165,10 @@ static mdx_status nuc_plan(mdx_ctx *c, const mdx_shells *sh, int32_t npair, cons
     for (int i = 0; i < cp.bra.g.ncol; ++i) cp.om.oab[i] = i;
     cp.om.ocd[0] = 0;
     cp.out_doubles = (int64_t)npair * cp.bra.g.ncol;
-    np.L = ws_layout(cp, 0);
-    np.off_np = np.L.total;
+    np.L = ws_layout(cp);
+    np.off_np = np.L.work;
     np.off_part = al256n(np.off_np + (size_t)std::max(np.nslice, 1) * 4);
-    np.total = np.off_part + (np.nslice > 1 ? al256n((size_t)np.nslice * cp.out_doubles * 8) : 0);
+    np.work = np.off_part + (np.nslice > 1 ? al256n((size_t)np.nslice * cp.out_doubles * 8) : 0);
     return MDX_OK;
 }
 
@@ -189,24 +182,14 @@ mdx_status nuclear_mfma_workspace(mdx_ctx *c, const mdx_shells *sh, int32_t npai
                                   int lb, int32_t ncharge, bool cart, size_t &bytes)
 {
     NucPlan np;
-    mdx_status st = nuc_plan(c, sh, npair, pairs, la, lb, ncharge, cart, np);
-    if (st != MDX_OK) return st;
-    bytes = np.total;
+    MDX_TRY(nuc_plan(c, sh, npair, pairs, la, lb, ncharge, cart, np));
+    bytes = np.L.tables + np.work;
     return MDX_OK;
 }
 
-mdx_status nuclear_mfma_enqueue(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la, int lb,
-                                int32_t ncharge, const double *charges, bool cart, double *V, void *ws,
-                                size_t ws_bytes, hipStream_t s)
+mdx_status nuclear_mfma_run(mdx_ctx *c, const mdx_shells *sh, const NucPlan &np, const char *tabs, char *work,
+                            int32_t ncharge, const double *charges, double *V, hipStream_t s)
 {
-    NucPlan np;
-    mdx_status st = nuc_plan(c, sh, npair, pairs, la, lb, ncharge, cart, np);
-    if (st != MDX_OK) return st;
-    if (!V) return fail(MDX_EINVAL, "mdx_nuclear_batch: null output");
-    if (!ws) return fail(MDX_EINVAL, "mdx_nuclear_batch: null workspace");
-    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_nuclear_batch: workspace not 256-byte aligned");
-    if (ws_bytes < np.total) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, np.total);
-    HIP_TRY2(hipSetDevice(c->device));
     const ClassPlan &cp = np.cp;
     const int64_t nout = cp.out_doubles;
     hipEvent_t ev1 = nullptr;
@@ -218,34 +201,49 @@ mdx_status nuclear_mfma_enqueue(mdx_ctx *c, const mdx_shells *sh, int32_t npair,
     if (ncharge == 0) {
         hipLaunchKernelGGL(nuclear_zero, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, nout, V);
     } else {
-        char *w = (char *)ws;
-        const ClassDev d = class_dev(np.L, w);
-        if ((st = upload_tables(cp, d, s)) != MDX_OK) return st;
+        const ClassDev d = class_dev(np.L, tabs, work);
         enqueue_pairdata(c, sh, cp, d, 0, s);
-        int32_t *nps = (int32_t *)(w + np.off_np);
+        int32_t *nps = (int32_t *)(work + np.off_np);
         const int nthr = std::max(ncharge, np.nslice);
         hipLaunchKernelGGL(nuclear_charge_ket, dim3((nthr + 255) / 256), dim3(256), 0, s, charges, ncharge,
                            d.prim_ket, d.H_ket, nps);
         for (int sl = 0; sl < np.nslice; ++sl) {
-            double *out = np.nslice > 1 ? (double *)(w + np.off_part) + (int64_t)sl * nout : V;
+            double *out = np.nslice > 1 ? (double *)(work + np.off_part) + (int64_t)sl * nout : V;
             EriArgs a;
             int nblocks = 0;
-            if ((st = class_args(c, cp, d, out, a, nblocks)) != MDX_OK) return st;
+            MDX_TRY(class_args(c, cp, d, out, a, nblocks));
             a.ket.prim = d.prim_ket + (int64_t)sl * NUC_SLICE;
             a.ket.H = d.H_ket + (int64_t)sl * NUC_SLICE * 16;
             a.ket.nprim = nps + sl;
             a.ket.kmax = std::min(ncharge, NUC_SLICE);
             if (!nuc_launch(cp.key.LB, cp.key.NAB, a, nblocks, s))
                 return fail(MDX_EUNSUPPORTED, "1-particle Coulomb kernel of class (%d|%d): LDS need beyond the device limit",
-                            la, lb);
+                            cp.la, cp.lb);
         }
         if (np.nslice > 1)
             hipLaunchKernelGGL(nuclear_sum_slices, dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s,
-                               (const double *)(w + np.off_part), np.nslice, nout, V);
+                               (const double *)(work + np.off_part), np.nslice, nout, V);
     }
     HIP_TRY2(hipGetLastError());
     if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
     return MDX_OK;
+}
+
+mdx_status nuclear_mfma_enqueue(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la, int lb,
+                                int32_t ncharge, const double *charges, bool cart, double *V, void *ws,
+                                size_t ws_bytes, hipStream_t s)
+{
+    NucPlan np;
+    MDX_TRY(nuc_plan(c, sh, npair, pairs, la, lb, ncharge, cart, np));
+    if (!V) return fail(MDX_EINVAL, "mdx_nuclear_batch: null output");
+    if (!ws) return fail(MDX_EINVAL, "mdx_nuclear_batch: null workspace");
+    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_nuclear_batch: workspace not 256-byte aligned");
+    const size_t need = np.L.tables + np.work;
+    if (ws_bytes < need) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+    HIP_TRY2(hipSetDevice(c->device));
+    char *w = (char *)ws;
+    if (ncharge > 0) MDX_TRY(upload_tables(np.cp, class_dev(np.L, w), s));
+    return nuclear_mfma_run(c, sh, np, w, w + np.L.tables, ncharge, charges, V, s);
 }
 
 }  // namespace mdx

@@ -539,31 +539,47 @@ extern "C" size_t mdx_one_body_workspace_size(mdx_ctx *c, const mdx_shells *sh, 
     return al256((size_t)npair * sizeof(PairRec)) + 256;
 }
 
-// the lane records of a validated batch, uploaded to the head of ws; then
-// the profiling hook's opening event.  *ev1 is the event to record after the
-// launch (null without the hook).
-static mdx_status stage_pairs(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, void *ws,
-                              size_t ws_bytes, hipStream_t s, const char *who, hipEvent_t *ev1)
+namespace mdx {
+
+void onebody_records(const mdx_shells *sh, int32_t npair, const int32_t *pairs, std::vector<PairRec> &pr)
 {
-    *ev1 = nullptr;
-    if (!ws) return fail(MDX_EINVAL, "%s: null workspace", who);
-    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "%s: workspace not 256-byte aligned", who);
-    const size_t need = al256((size_t)npair * sizeof(PairRec));
-    if (ws_bytes < need) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
-    std::vector<PairRec> pr((size_t)npair);
+    pr.resize((size_t)npair);
     for (int32_t i = 0; i < npair; ++i) {
         const int32_t sa = pairs[2 * i], sb = pairs[2 * i + 1];
         pr[i] = PairRec{sa, sb, sh->nprim[sa], sh->nprim[sb], sh->prim_offset[sa], sh->prim_offset[sb]};
     }
+}
+
+// the lane records of a validated batch, uploaded to the head of ws
+static mdx_status stage_pairs(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, void *ws,
+                              size_t ws_bytes, hipStream_t s, const char *who)
+{
+    if (!ws) return fail(MDX_EINVAL, "%s: null workspace", who);
+    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "%s: workspace not 256-byte aligned", who);
+    const size_t need = al256((size_t)npair * sizeof(PairRec));
+    if (ws_bytes < need) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);
+    MDX_TRY(refuse_capture(s, "the call copies its pair records from host memory"));
+    std::vector<PairRec> pr;
+    onebody_records(sh, npair, pairs, pr);
     HIP_TRY2(hipSetDevice(c->device));
     HIP_TRY2(hipMemcpyAsync(ws, pr.data(), pr.size() * sizeof(PairRec), hipMemcpyHostToDevice, s));
-    if (c->prof_events.size() >= 2) {   // profiling hook, as for the other integral kernels
+    return MDX_OK;
+}
+
+// profiling hook, as for the other integral kernels: records the opening
+// event; *ev1 is the event to record after the launch (null without the hook)
+static mdx_status prof_open(mdx_ctx *c, hipStream_t s, hipEvent_t *ev1)
+{
+    *ev1 = nullptr;
+    if (c->prof_events.size() >= 2) {
         const size_t np = c->prof_events.size() / 2, i = c->prof_count++ % np;
         *ev1 = c->prof_events[2 * i + 1];
         HIP_TRY2(hipEventRecord(c->prof_events[2 * i], s));
     }
     return MDX_OK;
 }
+
+}  // namespace mdx
 
 // one case per (l_a, l_b): l <= ONEBODY_LANE_LMAX (MDX_ONEBODY_SWITCH) or
 // l <= ONEBODY_LMAX (MDX_ONEBODY_SWITCH7)
@@ -640,6 +656,56 @@ static mdx_status stage_pairs(mdx_ctx *c, const mdx_shells *sh, int32_t npair, c
     default: LAUNCH<6, 6>(__VA_ARGS__); break; \
     }
 
+namespace mdx {
+
+mdx_status onebody_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *pairs, int32_t npair, int la, int lb,
+                          bool cart, double *S, double *T, hipStream_t s)
+{
+    if (npair == 0 || (!S && !T)) return MDX_OK;
+    hipEvent_t ev1;
+    MDX_TRY(prof_open(c, s, &ev1));
+    OneBodyArgs a{};
+    a.pairs = pairs;
+    a.npair = npair;
+    a.center = sh->center;
+    a.expo = sh->exponent;
+    a.coef = sh->coef;
+    a.Ca = c->solid + c->solid_off[la];
+    a.Cb = c->solid + c->solid_off[lb];
+    a.S = S;
+    a.T = T;
+    MDX_ONEBODY_SWITCH7(launch_onebody, la, lb, a, cart, s)
+    HIP_TRY2(hipGetLastError());
+    if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
+    return MDX_OK;
+}
+
+mdx_status nuclear_lane_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *pairs, int32_t npair, int la,
+                               int lb, bool cart, int32_t ncharge, const double *charges, double *V, hipStream_t s)
+{
+    if (npair == 0) return MDX_OK;
+    hipEvent_t ev1;
+    MDX_TRY(prof_open(c, s, &ev1));
+    NuclearArgs a{};
+    a.pairs = pairs;
+    a.npair = npair;
+    a.center = sh->center;
+    a.expo = sh->exponent;
+    a.coef = sh->coef;
+    a.charges = charges;
+    a.ncharge = ncharge;
+    a.boys = c->boys;
+    a.Ca = c->solid + c->solid_off[la];
+    a.Cb = c->solid + c->solid_off[lb];
+    a.V = V;
+    MDX_ONEBODY_SWITCH(launch_nuclear, la, lb, a, cart, s)
+    HIP_TRY2(hipGetLastError());
+    if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
+    return MDX_OK;
+}
+
+}  // namespace mdx
+
 extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
                                          int flags, double *S, double *T, void *ws, size_t ws_bytes,
                                          mdx_stream_t stream)
@@ -649,23 +715,8 @@ extern "C" mdx_status mdx_one_body_batch(mdx_ctx *c, const mdx_shells *sh, int32
     if (st != MDX_OK) return st;
     if (npair == 0 || (!S && !T)) return MDX_OK;
     hipStream_t s = (hipStream_t)stream;
-    hipEvent_t ev1;
-    st = stage_pairs(c, sh, npair, pairs, ws, ws_bytes, s, "mdx_one_body_batch", &ev1);
-    if (st != MDX_OK) return st;
-    OneBodyArgs a{};
-    a.pairs = (const PairRec *)ws;
-    a.npair = npair;
-    a.center = sh->center;
-    a.expo = sh->exponent;
-    a.coef = sh->coef;
-    a.Ca = c->solid + c->solid_off[l[0]];
-    a.Cb = c->solid + c->solid_off[l[1]];
-    a.S = S;
-    a.T = T;
-    MDX_ONEBODY_SWITCH7(launch_onebody, l[0], l[1], a, (flags & MDX_CARTESIAN) != 0, s)
-    HIP_TRY2(hipGetLastError());
-    if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
-    return MDX_OK;
+    MDX_TRY(stage_pairs(c, sh, npair, pairs, ws, ws_bytes, s, "mdx_one_body_batch"));
+    return onebody_launch(c, sh, (const PairRec *)ws, npair, l[0], l[1], (flags & MDX_CARTESIAN) != 0, S, T, s);
 }
 
 extern "C" size_t mdx_nuclear_workspace_size(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
@@ -702,23 +753,99 @@ extern "C" mdx_status mdx_nuclear_batch(mdx_ctx *c, const mdx_shells *sh, int32_
         return nuclear_mfma_enqueue(c, sh, npair, pairs, l[0], l[1], ncharge, charges, (flags & MDX_CARTESIAN) != 0, V,
                                     ws, ws_bytes, s);
     if (!V) return fail(MDX_EINVAL, "mdx_nuclear_batch: null output");
-    hipEvent_t ev1;
-    st = stage_pairs(c, sh, npair, pairs, ws, ws_bytes, s, "mdx_nuclear_batch", &ev1);
-    if (st != MDX_OK) return st;
-    NuclearArgs a{};
-    a.pairs = (const PairRec *)ws;
-    a.npair = npair;
-    a.center = sh->center;
-    a.expo = sh->exponent;
-    a.coef = sh->coef;
-    a.charges = charges;
-    a.ncharge = ncharge;
-    a.boys = c->boys;
-    a.Ca = c->solid + c->solid_off[l[0]];
-    a.Cb = c->solid + c->solid_off[l[1]];
-    a.V = V;
-    MDX_ONEBODY_SWITCH(launch_nuclear, l[0], l[1], a, (flags & MDX_CARTESIAN) != 0, s)
-    HIP_TRY2(hipGetLastError());
-    if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
+    MDX_TRY(stage_pairs(c, sh, npair, pairs, ws, ws_bytes, s, "mdx_nuclear_batch"));
+    return nuclear_lane_launch(c, sh, (const PairRec *)ws, npair, l[0], l[1], (flags & MDX_CARTESIAN) != 0, ncharge,
+                               charges, V, s);
+}
+
+extern "C" mdx_status mdx_one_body_prepare(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
+                                           int flags, mdx_batch **out)
+{
+    if (!out) return fail(MDX_EINVAL, "mdx_one_body_prepare: null handle pointer");
+    *out = nullptr;
+    int l[2];
+    MDX_TRY(check_pairs(c, sh, npair, pairs, flags, l));
+    mdx_batch *b = new mdx_batch;
+    mdx_status st = batch_init(b, c, sh, B_ONEBODY, flags);
+    b->la = l[0];
+    b->lb = l[1];
+    b->npair = npair;
+    const bool cart = (flags & MDX_CARTESIAN) != 0;
+    b->out_doubles = npair > 0 ? (int64_t)npair * nfunc(l[0], cart) * nfunc(l[1], cart) : 0;
+    if (st == MDX_OK && npair > 0) {
+        std::vector<PairRec> pr;
+        onebody_records(sh, npair, pairs, pr);
+        st = batch_tables(b, pr.size() * sizeof(PairRec));
+        if (st == MDX_OK && hipMemcpy(b->dtab, pr.data(), pr.size() * sizeof(PairRec), hipMemcpyHostToDevice) !=
+                                hipSuccess)
+            st = fail(MDX_EDEVICE, "mdx_one_body_prepare: copy of the pair records failed");
+    }
+    if (st != MDX_OK) {
+        mdx_batch_destroy(b);
+        return st;
+    }
+    *out = b;
     return MDX_OK;
+}
+
+extern "C" mdx_status mdx_one_body_run(const mdx_batch *b, const mdx_shells *sh, double *S, double *T, void *ws,
+                                       size_t ws_bytes, mdx_stream_t stream)
+{
+    MDX_TRY(batch_check(b, sh, B_ONEBODY, ws, ws_bytes, "mdx_one_body_run"));
+    return onebody_launch(b->c, sh, (const PairRec *)b->dtab, b->npair, b->la, b->lb,
+                          (b->flags & MDX_CARTESIAN) != 0, S, T, (hipStream_t)stream);
+}
+
+extern "C" mdx_status mdx_nuclear_prepare(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs,
+                                          int32_t ncharge, int flags, mdx_batch **out)
+{
+    if (!out) return fail(MDX_EINVAL, "mdx_nuclear_prepare: null handle pointer");
+    *out = nullptr;
+    int l[2];
+    MDX_TRY(check_pairs(c, sh, npair, pairs, flags, l));
+    if (ncharge < 0) return fail(MDX_EINVAL, "negative charge count");
+    const bool cart = (flags & MDX_CARTESIAN) != 0;
+    const bool mfma = npair > 0 && nuclear_on_mfma(l[0], l[1]);
+    mdx_batch *b = new mdx_batch;
+    mdx_status st = batch_init(b, c, sh, mfma ? B_NUC_MFMA : B_NUC_LANE, flags);
+    b->la = l[0];
+    b->lb = l[1];
+    b->npair = npair;
+    b->ncharge = ncharge;
+    b->out_doubles = npair > 0 ? (int64_t)npair * nfunc(l[0], cart) * nfunc(l[1], cart) : 0;
+    if (st == MDX_OK && mfma) {
+        st = nuc_plan(c, sh, npair, pairs, l[0], l[1], ncharge, cart, b->np);
+        if (st == MDX_OK) {
+            b->ws_need = b->np.work;
+            st = batch_tables(b, b->np.L.tables);
+        }
+        if (st == MDX_OK) st = copy_tables(b->np.cp, b->np.L, b->dtab);
+    } else if (st == MDX_OK && npair > 0) {
+        std::vector<PairRec> pr;
+        onebody_records(sh, npair, pairs, pr);
+        st = batch_tables(b, pr.size() * sizeof(PairRec));
+        if (st == MDX_OK && hipMemcpy(b->dtab, pr.data(), pr.size() * sizeof(PairRec), hipMemcpyHostToDevice) !=
+                                hipSuccess)
+            st = fail(MDX_EDEVICE, "mdx_nuclear_prepare: copy of the pair records failed");
+    }
+    if (st != MDX_OK) {
+        mdx_batch_destroy(b);
+        return st;
+    }
+    *out = b;
+    return MDX_OK;
+}
+
+extern "C" mdx_status mdx_nuclear_run(const mdx_batch *b, const mdx_shells *sh, const double *charges, double *V,
+                                      void *ws, size_t ws_bytes, mdx_stream_t stream)
+{
+    MDX_TRY(batch_check(b, sh, B_NUC_LANE, ws, ws_bytes, "mdx_nuclear_run"));
+    if (b->npair == 0) return MDX_OK;
+    if (b->ncharge > 0 && !charges) return fail(MDX_EINVAL, "mdx_nuclear_run: null charge array");
+    if (!V) return fail(MDX_EINVAL, "mdx_nuclear_run: null output");
+    hipStream_t s = (hipStream_t)stream;
+    if (b->kind == B_NUC_MFMA)
+        return nuclear_mfma_run(b->c, sh, b->np, b->dtab, (char *)ws, b->ncharge, charges, V, s);
+    return nuclear_lane_launch(b->c, sh, (const PairRec *)b->dtab, b->npair, b->la, b->lb,
+                               (b->flags & MDX_CARTESIAN) != 0, b->ncharge, charges, V, s);
 }

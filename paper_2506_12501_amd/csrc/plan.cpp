@@ -522,7 +522,7 @@ extern "C" size_t mdx_schwarz_workspace_size(mdx_ctx *c, const mdx_shells *sh, i
     ClassPlan cp;
     if (plan_schwarz(c, sh, npair, pairs, flags, cp) != MDX_OK) return 0;
     const size_t nab = cp.bra.g.ncol;
-    return al256(ws_layout(cp, 0).total) + al256((size_t)npair * nab * nab * 8) + 256;
+    return al256(ws_layout(cp).total) + al256((size_t)npair * nab * nab * 8) + 256;
 }
 
 extern "C" mdx_status mdx_schwarz(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int flags,
@@ -535,7 +535,7 @@ extern "C" mdx_status mdx_schwarz(mdx_ctx *c, const mdx_shells *sh, int32_t npai
     if (!Q) return fail(MDX_EINVAL, "mdx_schwarz: null Q");
     if (!ws) return fail(MDX_EINVAL, "mdx_schwarz: null workspace");
     if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_schwarz: workspace not 256-byte aligned");
-    const WsLayout L = ws_layout(cp, 0);
+    const WsLayout L = ws_layout(cp);
     const size_t nab = cp.bra.g.ncol;
     const size_t need = al256(L.total) + al256((size_t)npair * nab * nab * 8);
     if (ws_bytes < need) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, need);

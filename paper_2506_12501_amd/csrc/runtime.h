@@ -37,6 +37,12 @@ struct mdx_ctx {
         if (e_ != hipSuccess) return mdx::fail(MDX_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+#define MDX_TRY(expr)                          \
+    do {                                       \
+        const mdx_status st_ = (expr);         \
+        if (st_ != MDX_OK) return st_;         \
+    } while (0)
+
 namespace mdx {
 
 mdx_status fail(mdx_status s, const char *fmt, ...);
@@ -77,11 +83,14 @@ struct ClassPlan {
     const double *tket = nullptr;
 };
 
-// workspace layout of one class
+// device layout of one class: the index tables built on the host (offsets
+// from the table region), then the pair data the pair-data kernels write
+// (offsets from the work region).  A plain call puts both in its workspace,
+// tables first; a prepared batch keeps the tables in memory of its own.
 struct WsLayout {
-    size_t pairs_bra, pairs_ket, items_bra, items_ket, np_bra, np_ket, prim_bra, prim_ket, H_bra, H_ket;
-    size_t count, obase, tile_off;
-    size_t total;
+    size_t pairs_bra, pairs_ket, items_bra, items_ket, count, obase, tile_off;   // table region
+    size_t np_bra, np_ket, prim_bra, prim_ket, H_bra, H_ket;                     // work region
+    size_t tables, work, total;                                                  // total = tables + work
 };
 
 SideGeom make_geom(int la, int lb, bool cart, int role, int npair, int kmax, bool allow_grouped);
@@ -95,7 +104,7 @@ mdx_status check_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nb
 int grad_class_variants(int ncentre, int la, int lb, int lc, int ld, bool cart);
 mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
                       int32_t nket, const int32_t *ket, const int32_t *bra_count, int flags, ClassPlan &cp);
-WsLayout ws_layout(const ClassPlan &cp, size_t base);
+WsLayout ws_layout(const ClassPlan &cp);
 // device addresses of one class's tables and pair data
 struct ClassDev {
     const PairRec *pairs_bra, *pairs_ket;
@@ -107,8 +116,15 @@ struct ClassDev {
     int32_t *np_bra, *np_ket;
     double *H_bra, *H_ket;
 };
-ClassDev class_dev(const WsLayout &L, char *ws);
+ClassDev class_dev(const WsLayout &L, const char *tabs, char *work);
+ClassDev class_dev(const WsLayout &L, char *ws);   // tables at ws, work region after them
+// copies the index tables from host memory (refused while the stream is captured)
 mdx_status upload_tables(const ClassPlan &cp, const ClassDev &d, hipStream_t s);
+// device copy of the index tables into dst (L.tables bytes), synchronous
+mdx_status copy_tables(const ClassPlan &cp, const WsLayout &L, char *dst);
+// MDX_EINVAL if s is being captured into a graph: calls that copy host tables
+// per call cannot be replayed (their prepared forms can)
+mdx_status refuse_capture(hipStream_t s, const char *why);
 void enqueue_pairdata(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const ClassDev &d, int side,
                       hipStream_t s);
 mdx_status class_args(mdx_ctx *c, const ClassPlan &cp, const ClassDev &d, double *out, EriArgs &a, int &nblocks);
@@ -116,5 +132,72 @@ mdx_status launch_class(mdx_ctx *c, const ClassPlan &cp, const EriArgs &a, int n
 mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const WsLayout &L, char *ws,
                          double *out, hipStream_t s, bool upload,
                          const Digest *dig = nullptr);
+// the same with the tables already on the device at d (no upload)
+mdx_status enqueue_class_dev(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const ClassDev &d, double *out,
+                             hipStream_t s, const Digest *dig = nullptr);
+
+// 1-particle Coulomb integrals of l >= 4 as the class (ab|ss) with one ket pair
+// of point-charge primitives; the charge slices and partial sums after the
+// class's own work region
+struct NucPlan {
+    ClassPlan cp;
+    WsLayout L;
+    int nslice = 0;
+    size_t off_np = 0, off_part = 0;   // from the work region
+    size_t work = 0;                   // work region bytes (pair data, slice counts, partial sums)
+};
+bool nuclear_on_mfma(int la, int lb);
+mdx_status nuc_plan(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la, int lb,
+                    int32_t ncharge, bool cart, NucPlan &np);
+// enqueues a planned batch, tables at tabs (device), work region at work
+mdx_status nuclear_mfma_run(mdx_ctx *c, const mdx_shells *sh, const NucPlan &np, const char *tabs, char *work,
+                            int32_t ncharge, const double *charges, double *V, hipStream_t s);
+
+// the lane records of a 1-particle batch (pairs validated)
+void onebody_records(const mdx_shells *sh, int32_t npair, const int32_t *pairs, std::vector<PairRec> &pr);
+// one launch of the overlap/kinetic or nuclear kernels of class (la, lb) over
+// resident lane records (nuclear: l_a, l_b <= 3)
+mdx_status onebody_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *pairs, int32_t npair, int la, int lb,
+                          bool cart, double *S, double *T, hipStream_t s);
+mdx_status nuclear_lane_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *pairs, int32_t npair, int la,
+                               int lb, bool cart, int32_t ncharge, const double *charges, double *V, hipStream_t s);
 
 }  // namespace mdx
+
+// A prepared batch (mdx_eri_prepare, mdx_one_body_prepare, mdx_nuclear_prepare):
+// the host planning of one call done once, its index tables resident in
+// device memory of its own, so that a run enqueues kernels only.
+enum BatchKind { B_ERI = 1, B_ONEBODY = 2, B_NUC_LANE = 3, B_NUC_MFMA = 4 };
+
+struct mdx_batch {
+    mdx_ctx *c = nullptr;
+    int kind = 0;
+    int flags = 0;
+    int32_t nshell = 0;                      // basis metadata at preparation
+    std::vector<int32_t> l, nprim, poff;
+    char *dtab = nullptr;                    // device index tables
+    size_t ws_need = 0;                      // workspace bytes of a run
+    int64_t out_doubles = 0;                 // doubles per output array
+    mdx::ClassPlan cp;                       // B_ERI
+    mdx::WsLayout L{};
+    mdx::NucPlan np;                         // B_NUC_MFMA
+    int la = -1, lb = -1;                    // 1-particle classes
+    int32_t npair = 0, ncharge = 0;
+    ~mdx_batch()
+    {
+        if (dtab) hipFree(dtab);
+    }
+};
+
+namespace mdx {
+// records the context, kind and basis metadata of a new batch
+mdx_status batch_init(mdx_batch *b, mdx_ctx *c, const mdx_shells *sh, int kind, int flags);
+// allocates `bytes` of device memory for the batch's index tables (MDX_ENOMEM
+// on failure; nothing for 0 bytes)
+mdx_status batch_tables(mdx_batch *b, size_t bytes);
+// run-time checks shared by the run calls: kind, shell table against the
+// metadata at preparation, workspace; makes the context's device current
+mdx_status batch_check(const mdx_batch *b, const mdx_shells *sh, int kind, const void *ws, size_t ws_bytes,
+                       const char *who);
+}  // namespace mdx
+

@@ -72,6 +72,18 @@ EXPORTS = {
     "mdx_schwarz_workspace_size": (ctypes.c_size_t, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int]),
     "mdx_schwarz": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int, _p, _p,
                                    ctypes.c_size_t, _p]),
+    "mdx_eri_prepare": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int, _i32, _pi32, _i32, _pi32,
+                                       ctypes.c_int, ctypes.POINTER(_p)]),
+    "mdx_eri_run": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _p, _p, ctypes.c_size_t, _p]),
+    "mdx_one_body_prepare": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, ctypes.c_int,
+                                            ctypes.POINTER(_p)]),
+    "mdx_one_body_run": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _p, _p, _p, ctypes.c_size_t, _p]),
+    "mdx_nuclear_prepare": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _i32, _pi32, _i32, ctypes.c_int,
+                                           ctypes.POINTER(_p)]),
+    "mdx_nuclear_run": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _p, _p, _p, ctypes.c_size_t, _p]),
+    "mdx_batch_workspace_size": (ctypes.c_size_t, [_p]),
+    "mdx_batch_output_size": (ctypes.c_int64, [_p]),
+    "mdx_batch_destroy": (None, [_p]),
     "mdx_plan_create": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.c_int,
                                        ctypes.POINTER(MdxBatchDesc), ctypes.c_int, ctypes.POINTER(_p)]),
     "mdx_plan_workspace_size": (ctypes.c_size_t, [_p]),
@@ -453,3 +465,79 @@ class Plan:
                 self.handle = None
         except Exception:
             pass
+
+
+class Prepared:
+    """A prepared batch (mdx_eri_prepare, mdx_one_body_prepare,
+    mdx_nuclear_prepare): planned and its index tables copied to the device
+    once; run() enqueues kernels only, so it can be captured into a graph.
+    kind: "eri" (args ncentre, bra, ket; paired), "one_body" (args pairs) or
+    "nuclear" (args pairs, ncharge).  Output buffers and the workspace are
+    allocated here once and reused by every run."""
+
+    def __init__(self, kind, shells: DeviceShells, *args, cartesian: bool = False, paired: bool = False,
+                 ctx: Context | None = None):
+        import torch
+        self.kind = kind
+        self.shells = shells
+        dev = shells.center.device
+        self.ctx = ctx or Context.get(dev.index or 0)
+        flags = (MDX_CARTESIAN if cartesian else MDX_SPHERICAL) | (MDX_PAIRED if paired else 0)
+        L = lib()
+        h = _p()
+        sp = ctypes.byref(shells.struct)
+        if kind == "eri":
+            ncentre, bra, ket = args
+            self.bra, self.ket = _pairs(bra), _pairs(ket)
+            self.ncentre, self.paired = ncentre, paired
+            self.nab, self.ncd = _class_sizes(shells, ncentre, self.bra, self.ket, cartesian)
+            st = L.mdx_eri_prepare(self.ctx.handle, sp, ncentre, self.bra.shape[0], _i32p(self.bra),
+                                   self.ket.shape[0], _i32p(self.ket), flags, ctypes.byref(h))
+        elif kind == "one_body":
+            (pairs,) = args
+            self.pairs = _pairs(pairs)
+            st = L.mdx_one_body_prepare(self.ctx.handle, sp, self.pairs.shape[0], _i32p(self.pairs), flags,
+                                        ctypes.byref(h))
+        elif kind == "nuclear":
+            pairs, ncharge = args
+            self.pairs = _pairs(pairs)
+            self.ncharge = int(ncharge)
+            st = L.mdx_nuclear_prepare(self.ctx.handle, sp, self.pairs.shape[0], _i32p(self.pairs), self.ncharge,
+                                       flags, ctypes.byref(h))
+        else:
+            raise ValueError(f"unknown kind {kind!r}")
+        check(st, f"mdx_{kind}_prepare")
+        self.handle = h
+        self.ws_bytes = L.mdx_batch_workspace_size(h)
+        self.out_size = L.mdx_batch_output_size(h)
+        self.ws = torch.empty(self.ws_bytes // 8 + 32, dtype=torch.float64, device=dev)
+        self.wsp = (_ptr(self.ws) + 255) // 256 * 256
+        nout = 2 if kind == "one_body" else 1
+        self.out = [torch.empty(max(self.out_size, 1), dtype=torch.float64, device=dev) for _ in range(nout)]
+
+    def run(self, charges=None):
+        """Enqueues the batch on the current stream into self.out; returns
+        the output tensors (flat, the plain calls' layouts)."""
+        import torch
+        L = lib()
+        sp = ctypes.byref(self.shells.struct)
+        ws = ctypes.c_void_p(self.wsp)
+        if self.kind == "eri":
+            check(L.mdx_eri_run(self.handle, sp, _ptr(self.out[0]), ws, self.ws_bytes, _stream(torch)),
+                  "mdx_eri_run")
+        elif self.kind == "one_body":
+            check(L.mdx_one_body_run(self.handle, sp, _ptr(self.out[0]), _ptr(self.out[1]), ws, self.ws_bytes,
+                                     _stream(torch)), "mdx_one_body_run")
+        else:
+            check(L.mdx_nuclear_run(self.handle, sp, _ptr(charges) if charges is not None else None,
+                                    _ptr(self.out[0]), ws, self.ws_bytes, _stream(torch)), "mdx_nuclear_run")
+        return self.out
+
+    def __del__(self):
+        try:
+            if getattr(self, "handle", None):
+                lib().mdx_batch_destroy(self.handle)
+                self.handle = None
+        except Exception:
+            pass
+

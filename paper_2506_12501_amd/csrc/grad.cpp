@@ -121,10 +121,11 @@ mdx_status make_pass(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra
     p.key.LD = p.d.g.L;
     p.key.LW = p.w.g.L;
     p.key.NTN = p.d.g.ncolp / 16;
+    p.key.NTW = p.w.g.ncolp / 16;
     const int nv = eri_grad_variants(p.key);
     if (nv == 0)
-        return fail(MDX_EUNSUPPORTED, "gradient: no kernel for orders (%d, %d) with %d functions", p.key.LD, p.key.LW,
-                    p.d.g.ncol);
+        return fail(MDX_EUNSUPPORTED, "gradient: no kernel for orders (%d, %d) with %d and %d functions", p.key.LD,
+                    p.key.LW, p.d.g.ncol, p.w.g.ncol);
     auto it = c->grad_variant.find(std::make_tuple(ncentre, l[0], bra2 ? l[1] : -1, l[2], ket2 ? l[3] : -1, cart ? 1 : 0));
     p.variant = (it != c->grad_variant.end() && it->second >= 1 && it->second <= nv) ? it->second : 1;
     p.tw = c->tket + (p.w.g.lb >= 0 ? c->tket_off[cart][p.w.g.la][p.w.g.lb] : c->tket1_off[cart][p.w.g.la]);
@@ -189,10 +190,12 @@ int grad_class_variants(int ncentre, int la, int lb, int lc, int ld, bool cart)
     const int Lb = la + (bra2 ? lb : 0), Lk = lc + (ket2 ? ld : 0);
     const int nab = nfunc(la, cart) * (bra2 ? nfunc(lb, cart) : 1);
     const int ncd = nfunc(lc, cart) * (ket2 ? nfunc(ld, cart) : 1);
-    auto nv = [](int LD, int LW, int nfn) { return eri_grad_variants(GradKey{LD, LW, round_up(nfn, 16) / 16}); };
-    if (ncentre == 4) return std::max(nv(Lb, Lk, nab), nv(Lk, Lb, ncd));
-    if (ncentre == 3) return nv(Lk, Lb, ncd);
-    return Lb <= Lk ? nv(Lb, Lk, nab) : nv(Lk, Lb, ncd);
+    auto nv = [](int LD, int LW, int nd, int nw) {
+        return eri_grad_variants(GradKey{LD, LW, round_up(nd, 16) / 16, round_up(nw, 16) / 16});
+    };
+    if (ncentre == 4) return std::max(nv(Lb, Lk, nab, ncd), nv(Lk, Lb, ncd, nab));
+    if (ncentre == 3) return nv(Lk, Lb, ncd, nab);
+    return Lb <= Lk ? nv(Lb, Lk, nab, ncd) : nv(Lk, Lb, ncd, nab);
 }
 
 }  // namespace mdx

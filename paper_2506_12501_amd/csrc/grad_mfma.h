@@ -6,18 +6,19 @@
 //   d/dA_i phi_a = 2 zeta_a phi_{a+1_i} - a_i phi_{a-1_i},
 // and the product of that with phi_b is again a Hermite expansion about the
 // same P, of order l_a + l_b + 1.  The pair-data kernel stores these six
-// expansions (A_x, A_y, A_z, B_x, B_y, B_z) as matrices Hd[d][(kb, p)][ab].
+// expansions (A_x, A_y, A_z, B_x, B_y, B_z) as matrices Hd[d][ab][(kb, p)].
 // For a shellset (I, J) with adjoint block W[ab][cd] the six derivatives are
-//   g_d = sum_{ab,cd} W[ab][cd] sum_p Hd[d][p][ab] sum_q [p+q] H_ket[q][cd]
-//       = sum_{(kb,p), ab} Hd[d][(kb,p)][ab] X'[(kb,p)][ab],
-//   X'[(kb,p)][ab] = sum_{kk,q} [p+q]_{kb,kk} H'[kk][q][ab],
-//   H'[kk][q][ab]  = sum_cd H_ket[kk][q][cd] W[ab][cd]   (adjoint folded into the ket).
-// X' is the ket transform of Eq. (32) with the adjoint-folded ket, for bra
-// Hermite rows up to order l_a + l_b + 1 ([r] of Eq. (31) to L + 1), with
-// the partial early contraction of the terminal ket Hermites (Eqs. (38)-(40)).
-// The fold and the ket transform run on the FP64 matrix cores; the six
-// Frobenius products with Hd are VALU dot products over the accumulator tiles.
-// A second launch with the roles swapped gives the other pair's centres.
+//   g_d = sum_{ab,cd} W[ab][cd] sum_p Hd[d][ab][p] X[p][cd],
+//   X[(kb,p)][cd] = sum_{kk,q} [p+q]_{kb,kk} H_ket[kk][q][cd],
+// X being the ket transform of Eq. (32) for bra Hermite rows up to order
+// l_a + l_b + 1 ([r] of Eq. (31) to L + 1), with the partial early
+// contraction of the terminal ket Hermites (Eqs. (38)-(40)).  The kernel
+// forms X transposed on the FP64 matrix cores, X^T = H_ket^T [p+q]^T: the
+// accumulator tiles of X^T are then, element for element, the right operand
+// of the adjoint fold X'^T = W X^T, which runs once per shellset after the
+// ket primitives; the six Frobenius products of X' with Hd are VALU dot
+// products over its accumulator tiles.  A second launch with the roles
+// swapped gives the other pair's centres.
 #pragma once
 
 #include <algorithm>
@@ -28,7 +29,10 @@ namespace mdx {
 
 constexpr int GRAD_NWP_MAX = 48;   // other side's column stride bound (36 Cartesian functions)
 
-template <int LD, int LW, int NTN, int MTW, int NW, int WPE, int LAY>
+// NTN / NTW: 16-function tiles of the derivative side / the other side;
+// MTW: 16-row tiles per wave per chunk; NW waves; LAY: table layout; KP: ket
+// primitives per sweep round
+template <int LD, int LW, int NTN, int NTW, int MTW, int NW, int WPE, int LAY, int KP>
 __global__ void __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(WPE)))
 eri_grad_kernel(GradArgs a)
 {
@@ -42,12 +46,15 @@ eri_grad_kernel(GradArgs a)
     constexpr int NKT = ncart(LW);
     constexpr int KT = round_up(NKT, 4) / 4;
     constexpr int RPB = NTPAD + NKT;
-    constexpr int NP = NTN * 16;
+    constexpr int NP = NTN * 16;       // derivative-side functions, padded
+    constexpr int NQW = NTW * 16;      // other side's functions, padded (= its column stride)
+    constexpr int WLD = NQW + 1;       // adjoint row stride in LDS (odd: rows spread over banks)
     constexpr int NT = 64 * NW;
-    constexpr int MK = (NTPAD + 15) / 16;   // 16-row tiles of the adjoint fold
-    constexpr int HKR = (NTPAD * GRAD_NWP_MAX + NT - 1) / NT;
-    constexpr bool YSER = MTW * NTN * 4 + MTW * KT > 48;   // large accumulator set: sweep columns one branch each
-    constexpr int NQCT = (NW * MTW * 16) / NHD + 2;   // bound on quartets per chunk (host: nqmax)
+    constexpr int HKR = (NTPAD * NQW + NT - 1) / NT;
+    constexpr int TKR = (4 * KT * NQW + NT - 1) / NT;
+    constexpr bool YSER = MTW * NTW * 4 + MTW * KT > 48;   // large accumulator set: sweep columns one branch each
+    constexpr int NQCT = (NW * MTW * 16) / NHD + 2;         // bound on quartets per chunk (host: nqmax)
+    static_assert(KP >= 1 && KP * NQCT <= 64 && KP * NQCT <= CB::QMAX, "tables of one sweep round");
     const int tid = threadIdx.x;
     const int w = tid >> 6, lane = tid & 63, g = lane >> 4, c = lane & 15;
 
@@ -63,39 +70,35 @@ eri_grad_kernel(GradArgs a)
     const int nch = (MT + NW * MTW - 1) / (NW * MTW);
     const int nqmax = a.nqmax;
     const int kkmax = a.wside.kmax;
-    const int nw = a.nw, nwq = (nw + 3) & ~3, nwp = a.nwp;
+    const int nw = a.nw;
 
     extern __shared__ double smem[];
-    double *cube = smem;                       // nqmax tables
-    double *S = cube + CB::words(nqmax);       // [kkmax][nqmax][D]
-    double *PQ = S + kkmax * nqmax * D;        // [kkmax][nqmax][4]
-    double *Wt = PQ + kkmax * nqmax * 4;       // [kkmax]
-    double *Hk = Wt + kkmax;                   // [NTPAD][NP]   adjoint-folded ket block
-    double *Tk = Hk + NTPAD * NP;              // [4*KT][NP]    adjoint-folded terminal matrix
-    double *Wl = Tk + 4 * KT * NP;             // [NP][nwq]     adjoint block W[i][j]
-    double *Hr = Wl + NP * nwq;                // [NTPAD][nwp]  raw ket block
-    double *red = Hr + NTPAD * nwp;            // [NW][6]
-    int *kq = (int *)(red + NW * 6);           // [NTPAD]
-    int *kt = kq + NTPAD;                      // [4*KT]
-    int *rowt = kt + 4 * KT;                   // [NHD] table offsets of the derivative-side rows
+    double *cube = smem;                          // KP blocks of nqmax tables
+    double *S = cube + CB::words(KP * nqmax);     // [kkmax][nqmax][D]
+    double *PQ = S + kkmax * nqmax * D;           // [kkmax][nqmax][4]
+    double *Wt = PQ + kkmax * nqmax * 4;          // [kkmax]
+    double *Hk = Wt + kkmax;                      // [KP][NTPAD][NQW]  ket rows of a sweep round
+    double *Tk = Hk + KP * NTPAD * NQW;           // [4*KT][NQW]       terminal matrix of the other side
+    double *Wl = Tk + 4 * KT * NQW;               // [NP][WLD]         adjoint block W[ab][cd]
+    double *red = Wl + NP * WLD;                  // [NW][6]
+    int *kq = (int *)(red + NW * 6);              // [NTPAD]
+    int *kt = kq + NTPAD;                         // [4*KT]
+    int *rowt = kt + 4 * KT;                      // [NHD] table offsets of the derivative-side rows
 
     for (int k = tid; k < NHD; k += NT) rowt[k] = CB::off(k);
     for (int k = tid; k < NTPAD; k += NT) kq[k] = k < NKN ? CB::off(k) : 0;
     for (int k = tid; k < 4 * KT; k += NT) kt[k] = k < NKT ? CB::off(NKN + k) : 0;
     {
         const double *Wg = a.W + (int64_t)I * a.wsI + (int64_t)J * a.wsJ;
-        for (int e = tid; e < NP * nwq; e += NT) {
-            const int i = e / nwq, j = e - i * nwq;
+        for (int e = tid; e < NP * WLD; e += NT) {
+            const int i = e / WLD, j = e - i * WLD;
             Wl[e] = (i < a.nd && j < nw) ? Wg[(int64_t)i * a.wsd + (int64_t)j * a.wsw] : 0.0;
         }
-    }
-    __syncthreads();
-    // terminal matrix folded with the adjoint: Tk[q][i] = sum_j T[q][j] W[i][j]
-    for (int e = tid; e < 4 * KT * NP; e += NT) {
-        const int q = e / NP, i = e - q * NP;
-        double v = 0.0;
-        for (int j = 0; j < nw; ++j) v = fma(a.Tw[q * nwp + j], Wl[i * nwq + j], v);
-        Tk[e] = v;
+#pragma unroll
+        for (int i = 0; i < TKR; ++i) {
+            const int e = tid + i * NT;
+            if (e < 4 * KT * NQW) Tk[e] = a.Tw[e];
+        }
     }
 
     const PrimRec *bp = a.dside.prim + (int64_t)I * a.dside.kmax;
@@ -103,6 +106,7 @@ eri_grad_kernel(GradArgs a)
     const double *HkG = a.wside.H + (int64_t)J * a.wside.pair_stride;
     const double *Hd = a.dside.H + (int64_t)I * a.dside.pair_stride;
     const int64_t dstride = a.dside.pair_stride / 6;
+    const int rpbd = (int)(dstride / NP);   // row stride of Hd[d][ab][.]
 
     double gacc[6];
 #pragma unroll
@@ -127,12 +131,12 @@ eri_grad_kernel(GradArgs a)
             }
             abase[tt] = off;
         }
-        d4 acc[MTW][NTN];
+        d4 acc[MTW][NTW];   // X^T tiles: [cd][row]
         double Y[MTW][KT];
 #pragma unroll
         for (int tt = 0; tt < MTW; ++tt) {
 #pragma unroll
-            for (int n = 0; n < NTN; ++n) acc[tt][n] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int n = 0; n < NTW; ++n) acc[tt][n] = d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int s = 0; s < KT; ++s) Y[tt][s] = 0.0;
         }
@@ -163,98 +167,113 @@ eri_grad_kernel(GradArgs a)
             if (q == 0) Wt[kk] = K.wt;
         }
 
-        for (int kk = 0; kk < nkk; ++kk) {
-            __syncthreads();   // previous reads of the table, Hr and Hk are complete
-            double hv[HKR > 0 ? HKR : 1];
-            {
-                const double *src = HkG + (int64_t)kk * RPB * nwp;   // non-terminal rows are contiguous
+        // rounds of KP ket primitives: one set of sweeps fills the tables of all of them
+        for (int kk0 = 0; kk0 < nkk; kk0 += KP) {
+            const int nk = min(KP, nkk - kk0);
+            __syncthreads();   // previous round's reads of the tables and Hk are complete
+            // ket rows of this round (non-terminal rows are contiguous): global
+            // loads now, LDS stores after the recursion
+            double hv[KP][HKR];
+#pragma unroll
+            for (int j = 0; j < KP; ++j)
 #pragma unroll
                 for (int i = 0; i < HKR; ++i) {
                     const int e = tid + i * NT;
-                    hv[i] = e < NTPAD * nwp ? src[e] : 0.0;
+                    hv[j][i] = (j < nk && e < NTPAD * NQW) ? HkG[(int64_t)(kk0 + j) * RPB * NQW + e] : 0.0;
                 }
-            }
             {
-                const double *Sk = S + kk * nqmax * D, *PQk = PQ + kk * nqmax * 4;
-                ysweeps<CB, NW, YSER>(cube, Sk, PQk, NQ, NQ, nqmax, w, lane, std::make_integer_sequence<int, NW>{});
+                const double *Sk = S + kk0 * nqmax * D, *PQk = PQ + kk0 * nqmax * 4;
+                ysweeps<CB, NW, YSER>(cube, Sk, PQk, NQ, nk * nqmax, nqmax, w, lane,
+                                      std::make_integer_sequence<int, NW>{});
                 __syncthreads();
-                xsweeps<CB, NW, NQCT, YSER>(cube, PQk, NQ, NQ, nqmax, w, lane, std::make_integer_sequence<int, NW>{});
+                xsweeps<CB, NW, KP * NQCT, YSER>(cube, PQk, NQ, nk * nqmax, nqmax, w, lane,
+                                                 std::make_integer_sequence<int, NW>{});
             }
 #pragma unroll
-            for (int i = 0; i < HKR; ++i) {
-                const int e = tid + i * NT;
-                if (e < NTPAD * nwp) Hr[e] = hv[i];
-            }
-            __syncthreads();
-            // adjoint fold on MFMA: Hk[q][i] = sum_j Hr[q][j] W[i][j]  (M = q, K = j, N = i)
-            for (int it = w; it < MK * NTN; it += NW) {
-                const int m = it / NTN, n = it - m * NTN;
-                const int qa = 16 * m + c;
-                d4 f = d4{0.0, 0.0, 0.0, 0.0};
-                for (int s = 0; s < (nwq >> 2); ++s) {
-                    const int j = 4 * s + g;
-                    const double av = qa < NTPAD ? Hr[qa * nwp + j] : 0.0;
-                    f = mfma(av, Wl[(16 * n + c) * nwq + j], f);
-                }
+            for (int j = 0; j < KP; ++j)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int q = 16 * m + 4 * r + g;
-                    if (q < NTPAD) Hk[q * NP + 16 * n + c] = f[r];
+                for (int i = 0; i < HKR; ++i) {
+                    const int e = tid + i * NT;
+                    if (j < nk && e < NTPAD * NQW) Hk[j * NTPAD * NQW + e] = hv[j][i];
                 }
-            }
             __syncthreads();
 
-            // ket transform on MFMA over the non-terminal Hermites
+#pragma unroll
+            for (int j = 0; j < KP; ++j) {
+                if (j >= nk) break;   // uniform
+                const double *cj = cube + j * nqmax * CUBE;
+                const double *Hj = Hk + j * NTPAD * NQW;
+                // X^T += H_ket^T [p+q]^T over the non-terminal Hermites: the ket
+                // rows are the left operand (M = cd), the table gather the right (N = rows)
 #pragma unroll 2
-            for (int s = 0; s < KS; ++s) {
-                const int qo = kq[4 * s + g];
-                double bv[NTN];
+                for (int s = 0; s < KS; ++s) {
+                    const int qo = kq[4 * s + g];
+                    double bv[NTW];
 #pragma unroll
-                for (int n = 0; n < NTN; ++n) bv[n] = Hk[(4 * s + g) * NP + 16 * n + c];
+                    for (int n = 0; n < NTW; ++n) bv[n] = Hj[(4 * s + g) * NQW + 16 * n + c];
 #pragma unroll
-                for (int tt = 0; tt < MTW; ++tt) {
-                    const double av = cube[abase[tt] + qo];
+                    for (int tt = 0; tt < MTW; ++tt) {
+                        const double av = cj[abase[tt] + qo];
 #pragma unroll
-                    for (int n = 0; n < NTN; ++n) acc[tt][n] = mfma(av, bv[n], acc[tt][n]);
+                        for (int n = 0; n < NTW; ++n) acc[tt][n] = mfma(bv[n], av, acc[tt][n]);
+                    }
                 }
-            }
-            // terminal Hermites: early contraction over the ket primitives
-            const double wt = Wt[kk];
+                // terminal Hermites: early contraction over the ket primitives
+                const double wt = Wt[kk0 + j];
 #pragma unroll
-            for (int s = 0; s < KT; ++s) {
-                const int to = kt[4 * s + g];
+                for (int s = 0; s < KT; ++s) {
+                    const int to = kt[4 * s + g];
 #pragma unroll
-                for (int tt = 0; tt < MTW; ++tt) Y[tt][s] = fma(wt, cube[abase[tt] + to], Y[tt][s]);
+                    for (int tt = 0; tt < MTW; ++tt) Y[tt][s] = fma(wt, cj[abase[tt] + to], Y[tt][s]);
+                }
             }
         }
 
-        // terminal block: X' += Y T'
+        // terminal block: X^T += T^T Y^T
 #pragma unroll
         for (int s = 0; s < KT; ++s) {
-            double bv[NTN];
+            double bv[NTW];
 #pragma unroll
-            for (int n = 0; n < NTN; ++n) bv[n] = Tk[(4 * s + g) * NP + 16 * n + c];
+            for (int n = 0; n < NTW; ++n) bv[n] = Tk[(4 * s + g) * NQW + 16 * n + c];
 #pragma unroll
             for (int tt = 0; tt < MTW; ++tt)
 #pragma unroll
-                for (int n = 0; n < NTN; ++n) acc[tt][n] = mfma(Y[tt][s], bv[n], acc[tt][n]);
+                for (int n = 0; n < NTW; ++n) acc[tt][n] = mfma(bv[n], Y[tt][s], acc[tt][n]);
         }
 
-        // Frobenius products with the six derivative expansions (rows past the
-        // last primitive are zero in Hd)
+        // per row tile: adjoint fold X'^T = W X^T on MFMA -- lane (c, g) holds
+        // X^T[16n + 4r + g][row c] in acc[tt][n][r], which is the right operand
+        // of K step 4n + r -- then the Frobenius products with the six
+        // derivative expansions (rows past the last primitive are zero in Hd).
+        // A tile's 6 * 4 * NTN Hd values are loaded together before any is used.
 #pragma unroll
         for (int tt = 0; tt < MTW; ++tt) {
             const int T = tile0 + tt;
             if (T < MT) {
+                double hv[NTN][4][6];
+                const double *h0 = Hd + (int64_t)g * rpbd + 16 * T + c;
 #pragma unroll
-                for (int n = 0; n < NTN; ++n)
+                for (int m = 0; m < NTN; ++m)
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double x = acc[tt][n][r];
-                        const double *h = Hd + (int64_t)(16 * T + 4 * r + g) * NP + 16 * n + c;
+                    for (int r = 0; r < 4; ++r)
 #pragma unroll
-                        for (int d = 0; d < 6; ++d) gacc[d] = fma(h[d * dstride], x, gacc[d]);
-                    }
+                        for (int d = 0; d < 6; ++d) hv[m][r][d] = h0[d * dstride + (int64_t)(16 * m + 4 * r) * rpbd];
+                d4 O[NTN];
+#pragma unroll
+                for (int m = 0; m < NTN; ++m) {
+                    O[m] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int n = 0; n < NTW; ++n)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            O[m] = mfma(Wl[(16 * m + c) * WLD + 16 * n + 4 * r + g], acc[tt][n][r], O[m]);
+                }
+#pragma unroll
+                for (int m = 0; m < NTN; ++m)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+#pragma unroll
+                        for (int d = 0; d < 6; ++d) gacc[d] = fma(hv[m][r][d], O[m][r], gacc[d]);
             }
         }
     }
@@ -282,28 +301,28 @@ eri_grad_kernel(GradArgs a)
     }
 }
 
-template <int LD, int LW, int NTN, int MTW, int NW, int LAY>
-static size_t grad_lds_bytes(int nqmax, int kkmax, int nwq, int nwp)
+template <int LD, int LW, int NTN, int NTW, int MTW, int NW, int LAY, int KP>
+static size_t grad_lds_bytes(int nqmax, int kkmax)
 {
     constexpr int L = LD + LW + 1, D = L + 1;
     constexpr int NTPAD = round_up(nherm(LW - 1), 4);
     constexpr int KT = round_up(ncart(LW), 4) / 4;
-    constexpr int NP = NTN * 16;
-    const size_t dbl = (size_t)Cube<D, LAY>::words(nqmax) + (size_t)kkmax * nqmax * (D + 4) + kkmax + (size_t)NTPAD * NP +
-                       (size_t)4 * KT * NP + (size_t)NP * nwq + (size_t)NTPAD * nwp + (size_t)NW * 6;
+    constexpr int NP = NTN * 16, NQW = NTW * 16;
+    const size_t dbl = (size_t)Cube<D, LAY>::words(KP * nqmax) + (size_t)kkmax * nqmax * (D + 4) + kkmax +
+                       (size_t)KP * NTPAD * NQW + (size_t)4 * KT * NQW + (size_t)NP * (NQW + 1) + (size_t)NW * 6;
     return dbl * 8 + (size_t)(NTPAD + 4 * KT + nherm(LD + 1)) * 4;
 }
 
-template <int LD, int LW, int NTN, int MTW, int NW, int WPE, int LAY>
+template <int LD, int LW, int NTN, int NTW, int MTW, int NW, int WPE, int LAY, int KP>
 static bool launch_grad(const GradArgs &a0, int nblocks, hipStream_t s)
 {
     GradArgs a = a0;
     constexpr int NHD = nherm(LD + 1);
-    if (a.nwp > GRAD_NWP_MAX || a.nd > NTN * 16) return false;
+    if (a.nwp != NTW * 16 || a.nw > NTW * 16 || a.nd > NTN * 16) return false;
     a.nqmax = std::min(a.dside.kmax, (NW * MTW * 16) / NHD + 2);
-    const size_t lds = grad_lds_bytes<LD, LW, NTN, MTW, NW, LAY>(a.nqmax, a.wside.kmax, (a.nw + 3) & ~3, a.nwp);
+    const size_t lds = grad_lds_bytes<LD, LW, NTN, NTW, MTW, NW, LAY, KP>(a.nqmax, a.wside.kmax);
     if (lds > 160 * 1024) return false;
-    auto kern = eri_grad_kernel<LD, LW, NTN, MTW, NW, WPE, LAY>;
+    auto kern = eri_grad_kernel<LD, LW, NTN, NTW, MTW, NW, WPE, LAY, KP>;
     static size_t lds_set = 0;   // largest dynamic LDS granted to this instance so far
     if (lds > 64 * 1024 && lds > lds_set) {
         if (hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
@@ -314,9 +333,9 @@ static bool launch_grad(const GradArgs &a0, int nblocks, hipStream_t s)
     return true;
 }
 
-// Dispatch over an instance list X(LD, LW, NTN, MTW, NW, WPE, LAY); several
-// tile shapes or table layouts for one key are variants 1, 2, ... in listing
-// order.
+// Dispatch over an instance list X(LD, LW, NTN, NTW, MTW, NW, WPE, LAY, KP);
+// several tile shapes, table layouts or sweep rounds for one key are variants
+// 1, 2, ... in listing order.
 #define MDX_GRAD_DISPATCH(SUFFIX, LIST)                                                          \
     int eri_grad_variants_##SUFFIX(const GradKey &k)                                             \
     {                                                                                            \
@@ -331,10 +350,10 @@ static bool launch_grad(const GradArgs &a0, int nblocks, hipStream_t s)
         LIST(MDX_GRAD_TRY)                                                                       \
         return false;                                                                            \
     }
-#define MDX_GRAD_COUNT(ld, lw, ntn, mtw, nw, wpe, lay) \
-    if (k.LD == ld && k.LW == lw && k.NTN == ntn) ++n;
-#define MDX_GRAD_TRY(ld, lw, ntn, mtw, nw, wpe, lay)                            \
-    if (k.LD == ld && k.LW == lw && k.NTN == ntn && ++n == variant)             \
-        return launch_grad<ld, lw, ntn, mtw, nw, wpe, lay>(a, nblocks, s);
+#define MDX_GRAD_COUNT(ld, lw, ntn, ntw, mtw, nw, wpe, lay, kp) \
+    if (k.LD == ld && k.LW == lw && k.NTN == ntn && k.NTW == ntw) ++n;
+#define MDX_GRAD_TRY(ld, lw, ntn, ntw, mtw, nw, wpe, lay, kp)                           \
+    if (k.LD == ld && k.LW == lw && k.NTN == ntn && k.NTW == ntw && ++n == variant)     \
+        return launch_grad<ld, lw, ntn, ntw, mtw, nw, wpe, lay, kp>(a, nblocks, s);
 
 }  // namespace mdx

@@ -164,9 +164,9 @@ struct GradArgs {
 };
 
 // class key of a backward kernel: Hermite orders of the two sides and
-// 16-column tiles of the derivative side's functions
+// 16-column tiles of the derivative side's and the other side's functions
 struct GradKey {
-    int LD, LW, NTN;
+    int LD, LW, NTN, NTW;
 };
 int eri_grad_variants(const GradKey &k);
 bool eri_grad_launch(const GradKey &k, const GradArgs &a, int nblocks, int variant, hipStream_t s);

@@ -270,10 +270,12 @@ __global__ void __launch_bounds__(PD_THREADS) pairdata_kernel(PairDataArgs a)
         auto e1 = [&](int ax, int i, int j, int t) -> double {
             return (i >= 0 && j >= 0 && t <= i + j) ? E(ax, i, j, t) : 0.0;
         };
+        // stored transposed, Hd[d][col][row] (rows contiguous): the backward
+        // kernel reads 16 consecutive rows of one function per lane group
         const int64_t dstride = (int64_t)g.rows_per_block * g.ncolp;
         for (int e = lt; e < 6 * nrows * g.ncolp; e += T) {
             const int d = e / (nrows * g.ncolp), rem = e - d * nrows * g.ncolp;
-            const int row = row0 + rem / g.ncolp, col = rem % g.ncolp;
+            const int row = row0 + rem % nrows, col = rem / nrows;
             const int rk = row - k * g.nh;
             double v = 0.0;
             if (valid && rk < g.nh && col < g.ncol) {
@@ -298,7 +300,7 @@ __global__ void __launch_bounds__(PD_THREADS) pairdata_kernel(PairDataArgs a)
                     }
                 v = pref * s;
             }
-            Hp[d * dstride + (int64_t)row * g.ncolp + col] = v;
+            Hp[d * dstride + (int64_t)col * g.rows_per_block + row] = v;
         }
         return;
     }

@@ -210,8 +210,13 @@ mdx_status mdx_eri_digest_batch(mdx_ctx *ctx, const mdx_shells *shells, int ncen
  *       X = 0..3 for the centres of a, b, c, d; i = x, y, z.  A slot whose
  *       function is absent (3-/2-centre) is written as 0.  Centres that
  *       coincide are still reported separately; the caller sums them.
- * Same other arguments, limits and workspace query as mdx_eri_batch
- * (mdx_eri_grad_workspace_size).
+ * Same other arguments and workspace query as mdx_eri_batch
+ * (mdx_eri_grad_workspace_size).  Limits: each side whose centres are
+ * differentiated (both pairs of a 4-centre class, the ket pair of a
+ * 3-centre class, the lower-l function of a 2-centre class) of total order
+ * l_a + l_b <= 6; the other side of order <= 6; at most 64 functions per
+ * side (so (ff|ff) spherical, not Cartesian); MDX_EUNSUPPORTED beyond.  The
+ * call copies host tables and is refused on a stream under graph capture.
  */
 size_t mdx_eri_grad_workspace_size(mdx_ctx *ctx, const mdx_shells *shells, int ncentre,
                                    int32_t nbra, const int32_t *bra, int32_t nket,

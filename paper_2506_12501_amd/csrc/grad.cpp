@@ -19,44 +19,35 @@
 
 namespace mdx {
 
-int eri_grad_variants_l0(const GradKey &);
-int eri_grad_variants_l1(const GradKey &);
-int eri_grad_variants_l2(const GradKey &);
-int eri_grad_variants_l3(const GradKey &);
-int eri_grad_variants_l4(const GradKey &);
-bool eri_grad_launch_l0(const GradKey &, const GradArgs &, int, int, hipStream_t);
-bool eri_grad_launch_l1(const GradKey &, const GradArgs &, int, int, hipStream_t);
-bool eri_grad_launch_l2(const GradKey &, const GradArgs &, int, int, hipStream_t);
-bool eri_grad_launch_l3(const GradKey &, const GradArgs &, int, int, hipStream_t);
-bool eri_grad_launch_l4(const GradKey &, const GradArgs &, int, int, hipStream_t);
+// instance files: derivative-side orders 0..4 one file each, 5 and 6 split
+// by the derivative side's function tiles (every key lives in one file)
+#define MDX_GRAD_FILES(F) F(l0) F(l1) F(l2) F(l3) F(l4) F(l5a) F(l5b) F(l6a) F(l6b) F(l6c)
+#define MDX_GRAD_DECL(suf)                                   \
+    int eri_grad_variants_##suf(const GradKey &);            \
+    bool eri_grad_launch_##suf(const GradKey &, const GradArgs &, int, int, hipStream_t);
+MDX_GRAD_FILES(MDX_GRAD_DECL)
 
 int eri_grad_variants(const GradKey &k)
 {
-    switch (k.LD) {
-    case 0: return eri_grad_variants_l0(k);
-    case 1: return eri_grad_variants_l1(k);
-    case 2: return eri_grad_variants_l2(k);
-    case 3: return eri_grad_variants_l3(k);
-    case 4: return eri_grad_variants_l4(k);
-    default: return 0;
-    }
+    int n = 0;
+#define MDX_GRAD_SUM(suf) n += eri_grad_variants_##suf(k);
+    MDX_GRAD_FILES(MDX_GRAD_SUM)
+#undef MDX_GRAD_SUM
+    return n;
 }
 
 bool eri_grad_launch(const GradKey &k, const GradArgs &a, int nblocks, int variant, hipStream_t s)
 {
-    switch (k.LD) {
-    case 0: return eri_grad_launch_l0(k, a, nblocks, variant, s);
-    case 1: return eri_grad_launch_l1(k, a, nblocks, variant, s);
-    case 2: return eri_grad_launch_l2(k, a, nblocks, variant, s);
-    case 3: return eri_grad_launch_l3(k, a, nblocks, variant, s);
-    case 4: return eri_grad_launch_l4(k, a, nblocks, variant, s);
-    default: return false;
-    }
+#define MDX_GRAD_GO(suf) \
+    if (eri_grad_variants_##suf(k) > 0) return eri_grad_launch_##suf(k, a, nblocks, variant, s);
+    MDX_GRAD_FILES(MDX_GRAD_GO)
+#undef MDX_GRAD_GO
+    return false;
 }
 
 namespace {
 
-constexpr int GRAD_LMAX_PAIR = 4;   // derivative side: total order of a pair (or l of a single function)
+constexpr int GRAD_LMAX_PAIR = 6;   // derivative side: total order of a pair (or l of a single function)
 constexpr int GRAD_LMAX_OTHER = 6;  // other side: total order
 
 struct GradPass {

@@ -27,8 +27,6 @@
 
 namespace mdx {
 
-constexpr int GRAD_NWP_MAX = 48;   // other side's column stride bound (36 Cartesian functions)
-
 // NTN / NTW: 16-function tiles of the derivative side / the other side;
 // MTW: 16-row tiles per wave per chunk; NW waves; LAY: table layout; KP: ket
 // primitives per sweep round
@@ -52,7 +50,8 @@ eri_grad_kernel(GradArgs a)
     constexpr int NT = 64 * NW;
     constexpr int HKR = (NTPAD * NQW + NT - 1) / NT;
     constexpr int TKR = (4 * KT * NQW + NT - 1) / NT;
-    constexpr bool YSER = MTW * NTW * 4 + MTW * KT > 48;   // large accumulator set: sweep columns one branch each
+    // large accumulator set or long columns: sweep the columns one branch each
+    constexpr bool YSER = MTW * NTW * 4 + MTW * KT > 48 || D > 12;
     constexpr int NQCT = (NW * MTW * 16) / NHD + 2;         // bound on quartets per chunk (host: nqmax)
     static_assert(KP >= 1 && KP * NQCT <= 64 && KP * NQCT <= CB::QMAX, "tables of one sweep round");
     const int tid = threadIdx.x;
@@ -245,35 +244,42 @@ eri_grad_kernel(GradArgs a)
         // X^T[16n + 4r + g][row c] in acc[tt][n][r], which is the right operand
         // of K step 4n + r -- then the Frobenius products with the six
         // derivative expansions (rows past the last primitive are zero in Hd).
-        // A tile's 6 * 4 * NTN Hd values are loaded together before any is used.
+        // The Hd values of a group of HG function tiles (all of them for up to
+        // two tiles; one at a time beyond, for registers) are loaded together
+        // before any is used.
+        constexpr int HG = NTN <= 2 ? NTN : 1;
 #pragma unroll
         for (int tt = 0; tt < MTW; ++tt) {
             const int T = tile0 + tt;
             if (T < MT) {
-                double hv[NTN][4][6];
                 const double *h0 = Hd + (int64_t)g * rpbd + 16 * T + c;
 #pragma unroll
-                for (int m = 0; m < NTN; ++m)
+                for (int m0 = 0; m0 < NTN; m0 += HG) {
+                    double hv[HG][4][6];
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int d = 0; d < 6; ++d) hv[m][r][d] = h0[d * dstride + (int64_t)(16 * m + 4 * r) * rpbd];
-                d4 O[NTN];
-#pragma unroll
-                for (int m = 0; m < NTN; ++m) {
-                    O[m] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int n = 0; n < NTW; ++n)
+                    for (int mm = 0; mm < HG; ++mm)
 #pragma unroll
                         for (int r = 0; r < 4; ++r)
-                            O[m] = mfma(Wl[(16 * m + c) * WLD + 16 * n + 4 * r + g], acc[tt][n][r], O[m]);
+#pragma unroll
+                            for (int d = 0; d < 6; ++d)
+                                hv[mm][r][d] = h0[d * dstride + (int64_t)(16 * (m0 + mm) + 4 * r) * rpbd];
+                    d4 O[HG];
+#pragma unroll
+                    for (int mm = 0; mm < HG; ++mm) {
+                        O[mm] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                        for (int n = 0; n < NTW; ++n)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                O[mm] = mfma(Wl[(16 * (m0 + mm) + c) * WLD + 16 * n + 4 * r + g], acc[tt][n][r], O[mm]);
+                    }
+#pragma unroll
+                    for (int mm = 0; mm < HG; ++mm)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+#pragma unroll
+                            for (int d = 0; d < 6; ++d) gacc[d] = fma(hv[mm][r][d], O[mm][r], gacc[d]);
                 }
-#pragma unroll
-                for (int m = 0; m < NTN; ++m)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-#pragma unroll
-                        for (int d = 0; d < 6; ++d) gacc[d] = fma(hv[m][r][d], O[m][r], gacc[d]);
             }
         }
     }

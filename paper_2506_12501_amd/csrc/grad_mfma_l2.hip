@@ -4,7 +4,7 @@
 
 namespace mdx {
 
-#define MDX_GRAD_LIST_2(X) \
+#define MDX_GRAD_LIST_L2(X) \
     X(2, 0, 1, 1, 3, 4, 2, 0, 1) \
     X(2, 1, 1, 1, 3, 4, 2, 0, 1) \
     X(2, 2, 1, 1, 3, 4, 2, 0, 1) \
@@ -15,9 +15,13 @@ namespace mdx {
     X(2, 4, 1, 3, 3, 4, 2, 0, 1) \
     X(2, 5, 1, 1, 3, 4, 2, 0, 1) \
     X(2, 5, 1, 2, 3, 4, 2, 0, 1) \
+    X(2, 5, 1, 3, 3, 4, 2, 0, 1) \
+    X(2, 5, 1, 4, 3, 4, 2, 0, 1) \
     X(2, 6, 1, 1, 3, 4, 2, 0, 1) \
-    X(2, 6, 1, 2, 3, 4, 2, 0, 1)
+    X(2, 6, 1, 2, 3, 4, 2, 0, 1) \
+    X(2, 6, 1, 3, 3, 4, 2, 0, 1) \
+    X(2, 6, 1, 4, 3, 4, 2, 0, 1)
 
-MDX_GRAD_DISPATCH(l2, MDX_GRAD_LIST_2)
+MDX_GRAD_DISPATCH(l2, MDX_GRAD_LIST_L2)
 
 }  // namespace mdx

@@ -31,9 +31,9 @@ def nfuncs(batch, cart):
     return f(la) * f(lb), f(lc) * f(ld)
 
 
-def oracle_grad(batch, w, cart):
+def oracle_grad(batch, w, cart, quad=False):
     """reference g[ij, slot, kl] and its term scale sum |W dI|"""
-    D = O.eri(batch.basis, batch.ncentre, batch.bra, batch.ket, cartesian=cart, deriv=True)
+    D = O.eri(batch.basis, batch.ncentre, batch.bra, batch.ket, cartesian=cart, deriv=True, quad=quad)
     nket, _, nbra, nab, ncd = D.shape
     Wf = w.reshape(nket, ncd, nab, nbra)
     g = np.einsum("kcai,kdiac->idk", Wf, D)
@@ -61,10 +61,10 @@ def assert_grad_close(got, ref, scale, what):
     print(f"{what}: max err {err.max():.2e}, max err/scale {np.max(err / np.maximum(scale, 1e-300)):.2e}")
 
 
-def check_class(batch, cart=False, seed=1):
+def check_class(batch, cart=False, seed=1, quad=False):
     nab, ncd = nfuncs(batch, cart)
     w = W.adjoint(batch, nab, ncd, seed=seed)
-    ref, scale = oracle_grad(batch, w, cart)
+    ref, scale = oracle_grad(batch, w, cart, quad=quad)
     got = gpu_grad(batch, w, cart)
     assert_grad_close(got, ref, scale, f"{batch.name} {'cart' if cart else 'sph'}")
     return got, scale
@@ -224,12 +224,46 @@ def test_variants_agree():
         ctx.set_variant(4, 2, 2, 2, 2, native.MDX_GRADIENT, -1)
 
 
+# derivative sides of total order 5 and 6 (L' = l_d + l_w + 1 up to 13); the
+# reference is the __float128 oracle, as for the forward integrals of l >= 4
+HIGH = [("(ff|ff)", 1, 2, 2), ("(fd|dp)", 2, 3, 2), ("(gd|ps)", 1, 3, 2), ("(hp|ss)", 2, 2, 3), ("(is|pp)", 1, 2, 2),
+        ("(gp|gp)", 1, 2, 2), ("(hs|dd)", 2, 2, 2)]
+
+
+@pytest.mark.parametrize("name,K,nb,nk", HIGH, ids=[h[0] for h in HIGH])
+def test_four_centre_high_order(name, K, nb, nk):
+    b = W.make_class_batch(name, nb, nk, K, 5.0, 0.1, 20.0, 0.1, 1.0, seed=61)
+    check_class(b, quad=True)
+
+
+@pytest.mark.parametrize("name", ["(d|ff)", "(i|gd)", "(p|hp)"])
+def test_three_centre_high_order(name):
+    b = W.make_class_batch(name, 3, 2, 1, 5.0, 0.1, 20.0, 0.1, 1.0, seed=62)
+    got, _ = check_class(b, quad=True)
+    assert np.all(got[:, 3:6, :] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["(h|i)", "(i|i)", "(h|h)"])
+def test_two_centre_high_order(name):
+    b = W.make_class_batch(name, 3, 3, 2, 5.0, 0.1, 20.0, 0.1, 1.0, seed=63)
+    got, _ = check_class(b, quad=True)
+    assert np.all(got[:, 3:6, :] == 0.0) and np.all(got[:, 9:12, :] == 0.0)
+
+
+@pytest.mark.parametrize("name", ["(fd|ss)", "(hp|ps)"])
+def test_high_order_cartesian(name):
+    # up to 64 Cartesian functions per pair: (fd) 60, (hp) 63
+    b = W.make_class_batch(name, 2, 2, 1, 5.0, 0.1, 20.0, 0.1, 1.0, seed=64)
+    check_class(b, cart=True, quad=True)
+
+
 def test_unsupported_and_empty():
     from paper_2506_12501_amd import native
+    # a Cartesian (ff) pair has 100 functions, beyond the 64 of the instances
     b = W.make_class_batch("(ff|ff)", 2, 2, 1, 5.0, 0.1, 20.0, None, None, seed=51)
-    w = np.zeros(2 * 49 * 49 * 2)
+    w = np.zeros(2 * 100 * 100 * 2)
     with pytest.raises(native.MdxError) as e:
-        gpu_grad(b, w, False)
+        gpu_grad(b, w, True)
     assert e.value.status == native.MDX_EUNSUPPORTED
     e0 = W.make_class_batch("(dd|dd)", 0, 3, 1, 5.0, 0.1, 20.0, None, None, seed=52)
     assert gpu_grad(e0, np.zeros(0), False).size == 0

@@ -66,6 +66,7 @@ typedef enum {
 #define MDX_FUSED 2        /* plans: one graph launch, persistent kernels */
 #define MDX_GRADIENT 4     /* mdx_set_variant: choose the backward kernel */
 #define MDX_PAIRED 8       /* mdx_eri_batch: quartet q = (bra q, ket q)   */
+#define MDX_DIGEST 16      /* plans: contract with densities (mdx_plan_digest) */
 
 typedef struct mdx_ctx mdx_ctx;
 
@@ -378,7 +379,8 @@ typedef struct {
 
 typedef struct mdx_plan mdx_plan;
 
-/* flags: MDX_SPHERICAL/MDX_CARTESIAN | MDX_FUSED.  Without MDX_FUSED the plan
+/* flags: MDX_SPHERICAL/MDX_CARTESIAN | MDX_FUSED or MDX_DIGEST (mdx_plan_digest
+ * below).  Without MDX_FUSED the plan
  * issues one plain launch per batch (and two pair-data launches per batch);
  * with it, execution is one captured graph: the pair data of all batches,
  * then one persistent work-queue launch per kernel instance, each serving
@@ -403,6 +405,33 @@ int64_t mdx_plan_output_size(const mdx_plan *plan);
  * graph (which synchronises the stream once); the stream may change freely. */
 mdx_status mdx_plan_execute(mdx_plan *plan, const mdx_shells *shells, double *out, void *ws,
                             size_t ws_bytes, mdx_stream_t stream);
+
+/*
+ * Digestion over a screened plan (the "consume" use of Sec. 3.1: a Coulomb
+ * build over a screened molecule never writes its integrals).  A plan created
+ * with MDX_DIGEST (not MDX_FUSED; matrix-core classes then run their first,
+ * general, kernel shape) is run by this call instead of mdx_plan_execute.
+ * Batch b, with bra pairs ij < nbra_b, ket pairs kl < nket_b and ket pair kl
+ * taking the bra prefix ij < n_kl (bra_count), contributes
+ *   Jbra[ij + nbra_b*ab] += sum_{kl: ij < n_kl} sum_cd (ab|cd) Dket[kl + nket_b*cd]
+ *   Jket[kl + nket_b*cd] += sum_{ij < n_kl} sum_ab (ab|cd) Dbra[ij + nbra_b*ab]
+ * with the DEVICE pointers of blocks[b] (a HOST array of nbatch entries);
+ * J blocks are ACCUMULATED with atomic adds (the caller zeroes them; several
+ * batches may share one), either may be NULL (not computed), and a J needs
+ * the other side's density.  With canonical pair lists and a screen these are
+ * the two Coulomb contributions of each computed quartet; symmetry factors
+ * and the gather/scatter of D and J between AO and pair-blocked layouts are
+ * the caller's.  Errors as mdx_plan_execute, plus MDX_EINVAL for a plan made
+ * without MDX_DIGEST or a J without its density.
+ */
+typedef struct {
+    const double *Dbra, *Dket;
+    double *Jbra, *Jket;
+} mdx_digest_block;
+/* blocks: HOST array of one mdx_digest_block per batch of the plan */
+mdx_status mdx_plan_digest(mdx_plan *plan, const mdx_shells *shells, const mdx_digest_block *blocks, void *ws,
+                           size_t ws_bytes, mdx_stream_t stream);
+/* frees the plan, its tables, streams and graph */
 void mdx_plan_destroy(mdx_plan *plan);
 
 /*

@@ -124,6 +124,9 @@ SidePlan make_side(const mdx_shells *sh, const int32_t *lst, int32_t n, bool two
 mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra, const int32_t *bra,
                       int32_t nket, const int32_t *ket, const int32_t *bra_count, int flags, ClassPlan &cp)
 {
+    // MDX_DIGEST (plans only): matrix-core classes take their general shape
+    const bool digest = (flags & MDX_DIGEST) != 0;
+    flags &= ~MDX_DIGEST;
     int lv[4];
     mdx_status st = check_class(c, sh, ncentre, nbra, bra, nket, ket, flags, lv);
     if (st != MDX_OK) return st;
@@ -176,6 +179,13 @@ mdx_status plan_class(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbr
                 break;
             }
         }
+    }
+    if (digest && cp.kind == K_MFMA) {
+        // digestion is compiled for the first (general) shape of each class
+        if (eri_mfma_variant_kind(cp.key, 1) != MFMA_GENERAL)
+            return fail(MDX_EUNSUPPORTED, "digestion of class (%d %d|%d %d): no general matrix-core kernel", cp.la,
+                        cp.lb, cp.lc, cp.ld);
+        cp.variant = 1;
     }
     if (cp.kind == K_MFMA) {
         const int kind = eri_mfma_variant_kind(cp.key, cp.variant);
@@ -491,6 +501,10 @@ using namespace mdx;
 extern "C" size_t mdx_eri_workspace_size(mdx_ctx *c, const mdx_shells *sh, int ncentre, int32_t nbra,
                                          const int32_t *bra, int32_t nket, const int32_t *ket, int flags)
 {
+    if (flags & MDX_DIGEST) {
+        fail(MDX_EINVAL, "mdx_eri_workspace_size: MDX_DIGEST applies to plans only");
+        return 0;
+    }
     ClassPlan cp;
     if (plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp) != MDX_OK) return 0;
     return ws_layout(cp).total + 256;
@@ -500,6 +514,7 @@ extern "C" mdx_status mdx_eri_batch(mdx_ctx *c, const mdx_shells *sh, int ncentr
                                     int32_t nket, const int32_t *ket, int flags, double *out, void *ws,
                                     size_t ws_bytes, mdx_stream_t stream)
 {
+    if (flags & MDX_DIGEST) return fail(MDX_EINVAL, "mdx_eri_batch: MDX_DIGEST applies to plans only");
     if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_batch: MDX_FUSED applies to plans only");
     ClassPlan cp;
     mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp);
@@ -518,6 +533,7 @@ extern "C" mdx_status mdx_eri_batch_noalloc(mdx_ctx *c, const mdx_shells *sh, in
                                             const int32_t *bra, int32_t nket, const int32_t *ket, int flags,
                                             double *out, mdx_stream_t stream)
 {
+    if (flags & MDX_DIGEST) return fail(MDX_EINVAL, "mdx_eri_batch_noalloc: MDX_DIGEST applies to plans only");
     if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_batch_noalloc: MDX_FUSED applies to plans only");
     ClassPlan cp;
     mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, cp);
@@ -542,6 +558,7 @@ extern "C" mdx_status mdx_eri_prepare(mdx_ctx *c, const mdx_shells *sh, int ncen
 {
     if (!out) return fail(MDX_EINVAL, "mdx_eri_prepare: null handle pointer");
     *out = nullptr;
+    if (flags & MDX_DIGEST) return fail(MDX_EINVAL, "mdx_eri_prepare: MDX_DIGEST applies to plans only");
     if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_prepare: MDX_FUSED applies to plans only");
     mdx_batch *b = new mdx_batch;
     mdx_status st = plan_class(c, sh, ncentre, nbra, bra, nket, ket, nullptr, flags, b->cp);
@@ -575,6 +592,7 @@ extern "C" mdx_status mdx_eri_digest_batch(mdx_ctx *c, const mdx_shells *sh, int
                                            const double *Dbra, const double *Dket, double *Jbra, double *Jket,
                                            void *ws, size_t ws_bytes, mdx_stream_t stream)
 {
+    if (flags & MDX_DIGEST) return fail(MDX_EINVAL, "mdx_eri_digest_batch: MDX_DIGEST applies to plans only");
     if (flags & MDX_FUSED) return fail(MDX_EINVAL, "mdx_eri_digest_batch: MDX_FUSED applies to plans only");
     if (flags & MDX_PAIRED) return fail(MDX_EINVAL, "mdx_eri_digest_batch: MDX_PAIRED applies to mdx_eri_batch only");
     ClassPlan cp;

@@ -39,7 +39,9 @@ __global__ void __launch_bounds__(64) eri_valu_kernel(EriArgs a)
 // the last bra pair compute a copy of it and contribute nothing.  Over its
 // 16 ket pairs a lane also keeps reusing its bra pair's data; shellsets of
 // more than 81 integrals take one ket pair per workgroup (their registers are
-// spent on the shellset itself).
+// spent on the shellset itself).  Ragged batches (plans: ket pair J takes the
+// first count[J] bra pairs) go tile by tile as the storing kernel does: one
+// ket pair and 64 bra pairs of its prefix per workgroup.
 template <int NAB, int NCD>
 constexpr int valu_dig_nj() { return NAB * NCD > 81 ? 1 : 16; }
 
@@ -47,17 +49,31 @@ template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
 __global__ void __launch_bounds__(64) eri_valu_digest_kernel(EriArgs a)
 {
     constexpr int NJ = valu_dig_nj<NAB, NCD>();
-    const int tiles = (a.nbra + 63) / 64;
-    const int jc = blockIdx.x / tiles, lane = (int)threadIdx.x;
-    const int I0 = (blockIdx.x % tiles) * 64 + lane;
-    const bool live = I0 < a.nbra;
-    const int I = live ? I0 : a.nbra - 1;
+    const int lane = (int)threadIdx.x;
+    int I0, J0, J1, nI;
+    if (a.tile_off) {
+        int J, t0;
+        ragged_tile(a.tile_off, a.nket, blockIdx.x, J, t0);
+        J = __builtin_amdgcn_readfirstlane(J);
+        I0 = t0 * 64 + lane;
+        J0 = J;
+        J1 = J + 1;
+        nI = load_const(a.om.count + J);   // >= 1: the tile exists
+    } else {
+        const int tiles = (a.nbra + 63) / 64;
+        const int jc = blockIdx.x / tiles;
+        I0 = (blockIdx.x % tiles) * 64 + lane;
+        J0 = jc * NJ;
+        J1 = min(a.nket, (jc + 1) * NJ);
+        nI = a.nbra;
+    }
+    const bool live = I0 < nI;
+    const int I = live ? I0 : nI - 1;
     const Digest &d = a.dig;
     double jb[NAB];
 #pragma unroll
     for (int ab = 0; ab < NAB; ++ab) jb[ab] = 0.0;
-    const int J1 = min(a.nket, (jc + 1) * NJ);
-    for (int J = jc * NJ; J < J1; ++J) {
+    for (int J = J0; J < J1; ++J) {
         int zo = 0;   // large bra sides: an opaque zero keeps the Db loads inside the loop
         if constexpr (NAB > 9) asm volatile("" : "+v"(zo));   // (no NAB registers live across it)
         double out[NAB][NCD];
@@ -115,6 +131,10 @@ static void launch_valu(const EriArgs &a, int nblocks, hipStream_t s)
     if (!a.dig.on && !a.diag && !a.tile_off && NJ > 1 && NAB >= 9 && (int64_t)nblocks >= 65536) {
         const int64_t nb = (int64_t)((a.nbra + 63) / 64) * ((a.nket + NJ - 1) / NJ);
         hipLaunchKernelGGL((eri_valu_multi_kernel<LB, LK, NAB, NCD, GB, GK>), dim3((unsigned)nb), dim3(64), 0, s, a);
+        return;
+    }
+    if (a.dig.on && a.tile_off) {   // ragged: the tiles of the storing kernel
+        hipLaunchKernelGGL((eri_valu_digest_kernel<LB, LK, NAB, NCD, GB, GK>), dim3(nblocks), dim3(64), 0, s, a);
         return;
     }
     if (a.dig.on) {

@@ -232,7 +232,9 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
     if (!c) return fail(MDX_EINVAL, "null context");
     if (!sh) return fail(MDX_EINVAL, "null shell table");
     if (nbatch < 0 || (nbatch > 0 && !batches)) return fail(MDX_EINVAL, "mdx_plan_create: bad batch list");
-    if (flags & ~(MDX_CARTESIAN | MDX_FUSED)) return fail(MDX_EINVAL, "unknown flags 0x%x", flags);
+    if (flags & ~(MDX_CARTESIAN | MDX_FUSED | MDX_DIGEST)) return fail(MDX_EINVAL, "unknown flags 0x%x", flags);
+    if ((flags & MDX_FUSED) && (flags & MDX_DIGEST))
+        return fail(MDX_EINVAL, "mdx_plan_create: MDX_DIGEST plans run as plain launches (no MDX_FUSED)");
     mdx_plan *p = new (std::nothrow) mdx_plan;
     if (!p) return fail(MDX_ENOMEM, "mdx_plan_create: out of host memory");
     p->c = c;
@@ -256,7 +258,7 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
         }
         PlanBatch &pb = p->b[i];
         mdx_status st = plan_class(c, sh, bd.ncentre, bd.nbra, bd.bra, bd.nket, bd.ket, cnt,
-                                   flags & MDX_CARTESIAN, pb.cp);
+                                   flags & (MDX_CARTESIAN | MDX_DIGEST), pb.cp);
         if (st != MDX_OK) {
             const std::string msg = mdx_last_error();
             delete p;
@@ -448,6 +450,7 @@ extern "C" mdx_status mdx_plan_execute(mdx_plan *p, const mdx_shells *sh, double
                                        mdx_stream_t stream)
 {
     if (!p) return fail(MDX_EINVAL, "null plan");
+    if (p->flags & MDX_DIGEST) return fail(MDX_EINVAL, "mdx_plan_execute: a MDX_DIGEST plan runs through mdx_plan_digest");
     if (!sh || sh->nshell != p->nshell ||
         (p->nshell > 0 && (!sh->l || !sh->nprim || !sh->prim_offset || !sh->center || !sh->exponent || !sh->coef)))
         return fail(MDX_EINVAL, "mdx_plan_execute: shell table does not match the plan");
@@ -485,6 +488,55 @@ extern "C" mdx_status mdx_plan_execute(mdx_plan *p, const mdx_shells *sh, double
         if (st != MDX_OK) return st;
     }
     HIP_TRY2(hipGraphLaunch(p->exec, s));
+    return MDX_OK;
+}
+
+extern "C" mdx_status mdx_plan_digest(mdx_plan *p, const mdx_shells *sh, const mdx_digest_block *blk, void *ws,
+                                      size_t ws_bytes, mdx_stream_t stream)
+{
+    if (!p) return fail(MDX_EINVAL, "null plan");
+    if (!(p->flags & MDX_DIGEST)) return fail(MDX_EINVAL, "mdx_plan_digest: the plan was created without MDX_DIGEST");
+    if (!sh || sh->nshell != p->nshell ||
+        (p->nshell > 0 && (!sh->l || !sh->nprim || !sh->prim_offset || !sh->center || !sh->exponent || !sh->coef)))
+        return fail(MDX_EINVAL, "mdx_plan_digest: shell table does not match the plan");
+    if (p->nshell > 0 && (std::memcmp(sh->l, p->l.data(), p->nshell * 4) ||
+                          std::memcmp(sh->nprim, p->nprim.data(), p->nshell * 4) ||
+                          std::memcmp(sh->prim_offset, p->poff.data(), p->nshell * 4)))
+        return fail(MDX_EINVAL, "mdx_plan_digest: shell metadata differ from the plan's");
+    if (p->b.empty()) return MDX_OK;
+    if (!blk) return fail(MDX_EINVAL, "mdx_plan_digest: null block array");
+    for (size_t i = 0; i < p->b.size(); ++i) {
+        if (blk[i].Jbra && !blk[i].Dket) return fail(MDX_EINVAL, "mdx_plan_digest: batch %zu: Jbra needs Dket", i);
+        if (blk[i].Jket && !blk[i].Dbra) return fail(MDX_EINVAL, "mdx_plan_digest: batch %zu: Jket needs Dbra", i);
+    }
+    if (!ws) return fail(MDX_EINVAL, "mdx_plan_digest: null workspace");
+    if ((uintptr_t)ws & 255) return fail(MDX_EINVAL, "mdx_plan_digest: workspace not 256-byte aligned");
+    if (ws_bytes < p->ws_total) return fail(MDX_EWORKSPACE, "workspace %zu bytes < %zu required", ws_bytes, p->ws_total);
+    mdx_ctx *c = p->c;
+    HIP_TRY2(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)ws;
+    for (size_t i = 0; i < p->b.size(); ++i) {
+        const PlanBatch &pb = p->b[i];
+        const ClassPlan &cp = pb.cp;
+        if (cp.bra.pairs.empty() || cp.ket.pairs.empty() || cp.tile_off.back() == 0) continue;
+        if (!blk[i].Jbra && !blk[i].Jket) continue;
+        const ClassDev d = batch_dev(p, pb, w);
+        enqueue_pairdata(c, sh, cp, d, 0, s);
+        enqueue_pairdata(c, sh, cp, d, 1, s);
+        EriArgs a;
+        int nbl = 0;
+        mdx_status st = class_args(c, cp, d, nullptr, a, nbl);
+        if (st != MDX_OK) return st;
+        a.dig.on = 1;
+        a.dig.Db = blk[i].Dbra;
+        a.dig.Dk = blk[i].Dket;
+        a.dig.Jb = blk[i].Jbra;
+        a.dig.Jk = blk[i].Jket;
+        a.dig.nb = (int64_t)cp.bra.pairs.size();
+        a.dig.nk = (int64_t)cp.ket.pairs.size();
+        if ((st = launch_class(c, cp, a, nbl, s)) != MDX_OK) return st;
+    }
     return MDX_OK;
 }
 

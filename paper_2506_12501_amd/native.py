@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmdx.so")
 
 MDX_OK, MDX_EINVAL, MDX_EUNSUPPORTED, MDX_EWORKSPACE, MDX_ENOMEM, MDX_EDEVICE = range(6)
-MDX_SPHERICAL, MDX_CARTESIAN, MDX_FUSED, MDX_GRADIENT, MDX_PAIRED = 0, 1, 2, 4, 8
+MDX_SPHERICAL, MDX_CARTESIAN, MDX_FUSED, MDX_GRADIENT, MDX_PAIRED, MDX_DIGEST = 0, 1, 2, 4, 8, 16
 MDX_NOALLOC_SCRATCH_BYTES = 64 << 20     # static scratch of mdx_eri_batch_noalloc, per device
 
 _p = ctypes.c_void_p
@@ -33,6 +33,10 @@ class MdxShells(ctypes.Structure):
 class MdxBatchDesc(ctypes.Structure):
     _fields_ = [("ncentre", ctypes.c_int), ("nbra", _i32), ("bra", _pi32), ("nket", _i32),
                 ("ket", _pi32), ("bra_count", _pi32), ("out_offset", ctypes.c_int64)]
+
+
+class MdxDigestBlock(ctypes.Structure):
+    _fields_ = [("Dbra", _p), ("Dket", _p), ("Jbra", _p), ("Jket", _p)]
 
 
 class MdxError(RuntimeError):
@@ -89,6 +93,8 @@ EXPORTS = {
     "mdx_plan_workspace_size": (ctypes.c_size_t, [_p]),
     "mdx_plan_output_size": (ctypes.c_int64, [_p]),
     "mdx_plan_execute": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), _p, _p, ctypes.c_size_t, _p]),
+    "mdx_plan_digest": (ctypes.c_int, [_p, ctypes.POINTER(MdxShells), ctypes.POINTER(MdxDigestBlock), _p,
+                                       ctypes.c_size_t, _p]),
     "mdx_plan_destroy": (None, [_p]),
     "mdx_set_profile_events": (ctypes.c_int, [_p, ctypes.POINTER(_p), ctypes.c_int]),
     "mdx_set_variant": (ctypes.c_int, [_p, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
@@ -430,7 +436,8 @@ class Plan:
     """mdx_plan over a list of Batch; fused=True -> one captured graph with
     persistent work-queue kernels."""
 
-    def __init__(self, shells: DeviceShells, batches, cartesian=False, fused=False, ctx: Context | None = None):
+    def __init__(self, shells: DeviceShells, batches, cartesian=False, fused=False, ctx: Context | None = None,
+                 digest=False):
         import torch
         self.ctx = ctx or Context.get(shells.center.device.index or 0)
         self.shells = shells
@@ -440,7 +447,7 @@ class Plan:
         for i, b in enumerate(self.batches):
             descs[i] = MdxBatchDesc(b.ncentre, b.bra.shape[0], _i32p(b.bra), b.ket.shape[0], _i32p(b.ket),
                                     _i32p(b.bra_count) if b.bra_count is not None else None, b.out_offset)
-        flags = (MDX_CARTESIAN if cartesian else 0) | (MDX_FUSED if fused else 0)
+        flags = (MDX_CARTESIAN if cartesian else 0) | (MDX_FUSED if fused else 0) | (MDX_DIGEST if digest else 0)
         h = _p()
         check(lib().mdx_plan_create(self.ctx.handle, ctypes.byref(shells.struct), n, descs, flags, ctypes.byref(h)),
               "mdx_plan_create")
@@ -457,6 +464,18 @@ class Plan:
         check(lib().mdx_plan_execute(self.handle, ctypes.byref(self.shells.struct), ctypes.c_void_p(_ptr(out)),
                                      ctypes.c_void_p(self.wsp), self.ws_bytes, _stream(torch)), "mdx_plan_execute")
         return out
+
+    def digest(self, blocks):
+        """mdx_plan_digest (plan made with digest=True): blocks is one
+        (Dbra, Dket, Jbra, Jket) tuple of device tensors (or None) per batch;
+        the J tensors are accumulated in place."""
+        import torch
+        n = len(self.batches)
+        arr = (MdxDigestBlock * max(n, 1))()
+        for i, blk in enumerate(blocks):
+            arr[i] = MdxDigestBlock(*[_ptr(t) for t in blk])
+        check(lib().mdx_plan_digest(self.handle, ctypes.byref(self.shells.struct), arr, ctypes.c_void_p(self.wsp),
+                                    self.ws_bytes, _stream(torch)), "mdx_plan_digest")
 
     def __del__(self):
         try:

@@ -459,9 +459,15 @@ def cluster_leg(native, ctx, torch, reps, sample, tune=True):
         blocks.append((Db, Dk, torch.zeros_like(Db), torch.zeros_like(Dk)))
 
     class _Digest:
+        def __init__(self, plan):
+            self.plan = plan
+
         def execute(self, out=None):
-            dplan.digest(blocks)
-    t_digest = timed(_Digest(), None)
+            self.plan.digest(blocks)
+    t_digest = timed(_Digest(dplan), None)
+    # and as one graph of persistent digesting kernels
+    t_digest_fused = timed(_Digest(native.Plan(sh, nb, digest=True, fused=True)), None)
+    log(f"cluster: digesting plan {min(t_digest):.2f} ms, digesting graph {min(t_digest_fused):.2f} ms")
     identical = bool(torch.equal(o_plain, o_fused))        # expected only where tuning kept the default kernels
     max_diff = float((o_plain - o_fused).abs().max())
     log(f"cluster: plain {min(t_plain):.2f} ms, fused {min(t_fused):.2f} ms")
@@ -515,6 +521,7 @@ def cluster_leg(native, ctx, torch, reps, sample, tune=True):
         "schwarz_ms": schwarz_ms,
         "plain_ms": best_p, "fused_ms": best_f, "plain_ms_all": t_plain, "fused_ms_all": t_fused,
         "digest_plain_ms": min(t_digest), "digest_plain_ms_all": t_digest,
+        "digest_fused_ms": min(t_digest_fused), "digest_fused_ms_all": t_digest_fused,
         "plain_tuned_ms": min(t_plain_tuned) if t_plain_tuned else None, "plain_tuned_ms_all": t_plain_tuned,
         "fused_speedup": best_p / best_f,
         "fusion_only_speedup": min(t_plain_tuned) / best_f if t_plain_tuned else None,
@@ -671,7 +678,8 @@ def compact_record(full, detail_path=None):
     if cl:
         rec["mixed_cluster"] = {k: cl.get(k) for k in ("quartets", "plain_ms", "plain_tuned_ms", "fused_ms",
                                                         "fused_speedup", "fusion_only_speedup",
-                                                        "pct_fp64_peak_fused", "digest_plain_ms")}
+                                                        "pct_fp64_peak_fused", "digest_plain_ms",
+                                                        "digest_fused_ms")}
         ps = cl["parity_sample"]
         rec["mixed_cluster"]["parity"] = {k: ps.get(k) for k in ("checked", "failed", "passed_only_by_QQ_clause",
                                                                  "max_err_over_QQ")}

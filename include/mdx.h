@@ -379,7 +379,7 @@ typedef struct {
 
 typedef struct mdx_plan mdx_plan;
 
-/* flags: MDX_SPHERICAL/MDX_CARTESIAN | MDX_FUSED or MDX_DIGEST (mdx_plan_digest
+/* flags: MDX_SPHERICAL/MDX_CARTESIAN | MDX_FUSED | MDX_DIGEST (mdx_plan_digest
  * below).  Without MDX_FUSED the plan
  * issues one plain launch per batch (and two pair-data launches per batch);
  * with it, execution is one captured graph: the pair data of all batches,
@@ -409,8 +409,11 @@ mdx_status mdx_plan_execute(mdx_plan *plan, const mdx_shells *shells, double *ou
 /*
  * Digestion over a screened plan (the "consume" use of Sec. 3.1: a Coulomb
  * build over a screened molecule never writes its integrals).  A plan created
- * with MDX_DIGEST (not MDX_FUSED; matrix-core classes then run their first,
- * general, kernel shape) is run by this call instead of mdx_plan_execute.
+ * with MDX_DIGEST (matrix-core classes then run their first, general, kernel
+ * shape) is run by this call instead of mdx_plan_execute; with MDX_FUSED as
+ * well it runs as one graph of persistent digesting kernels, whose batch
+ * descriptors hold the blocks' pointers (new pointers rebuild the graph, which
+ * synchronises the stream once).
  * Batch b, with bra pairs ij < nbra_b, ket pairs kl < nket_b and ket pair kl
  * taking the bra prefix ij < n_kl (bra_count), contributes
  *   Jbra[ij + nbra_b*ab] += sum_{kl: ij < n_kl} sum_cd (ab|cd) Dket[kl + nket_b*cd]

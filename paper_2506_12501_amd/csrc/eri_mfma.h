@@ -487,4 +487,25 @@ __host__ __device__ inline size_t mfma_lds_bytes(int nqmax, int kkmax)
     X(4, 1, 25, 3, false, 2, 1, 1, 3, 1, 4, CUBE_LAY_COMPACT, 4)   /* (dd|ps)                 */   \
     X(4, 2, 25, 5, false, 2, 1, 1, 3, 1, 4, CUBE_LAY_COMPACT, 4)   /* (dd|ds)                 */
 
+// The instance rows of the general kernel; digestion (and its persistent
+// form) is compiled for the first row of each class only.
+struct MfmaRow {
+    int lb, lk, nab, ncd;
+    bool gb;
+    int ntab, ntcd, ntg, mtw, nw, wpe, lay, kp;
+};
+constexpr MfmaRow kMfmaRows[] = {
+#define MDX_ROW(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp) \
+    {lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp},
+    MDX_MFMA_INSTANCES(MDX_ROW)
+#undef MDX_ROW
+};
+constexpr bool first_of_class(MfmaRow x)
+{
+    for (const MfmaRow &r : kMfmaRows)
+        if (r.lb == x.lb && r.lk == x.lk && r.nab == x.nab && r.ncd == x.ncd && r.gb == x.gb)
+            return r.ntab == x.ntab && r.ntcd == x.ntcd && r.ntg == x.ntg && r.mtw == x.mtw && r.nw == x.nw &&
+                   r.wpe == x.wpe && r.lay == x.lay && r.kp == x.kp;
+    return false;
+}
 }  // namespace mdx

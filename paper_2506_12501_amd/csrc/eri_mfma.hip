@@ -39,26 +39,8 @@ static bool key_is(const EriKey &k, int lb, int lk, int nab, int ncd, bool gb)
     return !k.GK && k.LB == lb && k.LK == lk && k.NAB == nab && k.NCD == ncd && k.GB == gb;
 }
 
-// Digestion kernels exist for the first shape (variant 1) of each class only.
-struct MfmaRow {
-    int lb, lk, nab, ncd;
-    bool gb;
-    int ntab, ntcd, ntg, mtw, nw, wpe, lay, kp;
-};
-constexpr MfmaRow kMfmaRows[] = {
-#define MDX_ROW(lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp) \
-    {lb, lk, nab, ncd, gb, ntab, ntcd, ntg, mtw, nw, wpe, lay, kp},
-    MDX_MFMA_INSTANCES(MDX_ROW)
-#undef MDX_ROW
-};
-constexpr bool first_of_class(MfmaRow x)
-{
-    for (const MfmaRow &r : kMfmaRows)
-        if (r.lb == x.lb && r.lk == x.lk && r.nab == x.nab && r.ncd == x.ncd && r.gb == x.gb)
-            return r.ntab == x.ntab && r.ntcd == x.ntcd && r.ntg == x.ntg && r.mtw == x.mtw && r.nw == x.nw &&
-                   r.wpe == x.wpe && r.lay == x.lay && r.kp == x.kp;
-    return false;
-}
+// Digestion kernels exist for the first shape (variant 1) of each class only
+// (first_of_class, eri_mfma.h).
 template <bool FIRST, int LB, int LK, int NTAB, int NTCD, int NTG, int MTW, int NW, bool GB, int WPE, int LAY, int KP>
 struct DigestLaunch {
     static bool go(const EriArgs &, int, hipStream_t) { return false; }

@@ -144,6 +144,44 @@ __device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I,
             a.om.out[base + mult * (int64_t)(a.om.oab[ab] + a.om.ocd[j])] = out[ab][j];
 }
 
+// Digestion of shellsets (I0, J), one per lane, J uniform over the wave (a
+// ragged tile: ket pair J and 64 bra pairs of its prefix I < nI): each lane
+// adds its Jb rows with atomics, the Jk terms are summed over groups of 8
+// lanes first.  Every lane of the wave must call it; lanes with I0 >= nI
+// compute a copy of bra pair nI - 1 and contribute nothing.
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
+__device__ __forceinline__ void eri_valu_digest_one(const EriArgs &a, const int I0, const int J, const int nI)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const bool live = I0 < nI;
+    const int I = live ? I0 : nI - 1;
+    const Digest &d = a.dig;
+    double out[NAB][NCD];
+    eri_valu_compute<LB, LK, NAB, NCD, GB, GK>(a, I, J, out);
+    if (d.Jb && live) {
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab) {
+            double v = 0.0;
+#pragma unroll
+            for (int cd = 0; cd < NCD; ++cd) v = fma(out[ab][cd], d.Dk[J + d.nk * cd], v);
+            atomicAdd(d.Jb + I + d.nb * ab, v);
+        }
+    }
+    if (d.Jk) {
+#pragma unroll
+        for (int cd = 0; cd < NCD; ++cd) {
+            double v = 0.0;
+            if (live) {
+#pragma unroll
+                for (int ab = 0; ab < NAB; ++ab) v = fma(out[ab][cd], d.Db[I + d.nb * ab], v);
+            }
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            if ((lane & 7) == 0) atomicAdd(d.Jk + J + d.nk * cd, v);
+        }
+    }
+}
 
 #define MDX_VALU_INSTANCES(X)                                                                       \
     /* 4-centre, spherical and Cartesian, l <= 2 per shell, bra order >= ket order */              \

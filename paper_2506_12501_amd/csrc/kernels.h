@@ -179,11 +179,13 @@ struct QueueArgs {
     int total;             // base[nb]
     int *counter;          // zero before the launch
 };
-bool eri_mfma_config(const EriKey &k, int variant, int bra_kmax, int ket_kmax, int &nqmax, size_t &lds, int &nthreads);
+// dig: the digesting form (first shape of a class only)
+bool eri_mfma_config(const EriKey &k, int variant, int bra_kmax, int ket_kmax, int &nqmax, size_t &lds, int &nthreads,
+                     bool dig = false);
 // sets the dynamic-LDS limit of the queue kernel; returns resident workgroups per CU (0: unusable)
-int eri_queue_prepare(const EriKey &k, bool mfma, int variant, size_t lds);
+int eri_queue_prepare(const EriKey &k, bool mfma, int variant, size_t lds, bool dig = false);
 bool eri_queue_launch(const EriKey &k, bool mfma, int variant, const QueueArgs &q, int nblocks, size_t lds,
-                      hipStream_t s);
+                      hipStream_t s, bool dig = false);
 void launch_schwarz(const double *diag, int npair, int nab, double *Q, hipStream_t s);
 void launch_fill_i32(int32_t *p, int n, int32_t v, hipStream_t s);
 

@@ -75,6 +75,7 @@ struct mdx_plan {
     const void *k_center = nullptr, *k_exp = nullptr, *k_coef = nullptr;
     double *k_out = nullptr;
     void *k_ws = nullptr;
+    std::vector<mdx_digest_block> k_blk;   // digesting graph: the blocks its descriptors hold
     std::vector<EriArgs> descs;
 
     ~mdx_plan()
@@ -126,8 +127,10 @@ ClassDev batch_dev(const mdx_plan *p, const PlanBatch &pb, char *ws)
     return d;
 }
 
-mdx_status build_graph(mdx_plan *p, const mdx_shells *sh, double *out, char *ws, hipStream_t user)
+mdx_status build_graph(mdx_plan *p, const mdx_shells *sh, double *out, char *ws, hipStream_t user,
+                       const mdx_digest_block *blk = nullptr)
 {
+    const bool dig = blk != nullptr;
     mdx_ctx *c = p->c;
     if (p->exec) {
         HIP_TRY2(hipGraphExecDestroy(p->exec));
@@ -140,9 +143,20 @@ mdx_status build_graph(mdx_plan *p, const mdx_shells *sh, double *out, char *ws,
     for (size_t i = 0; i < p->b.size(); ++i) {
         PlanBatch &pb = p->b[i];
         int nbl = 0;
-        mdx_status st = class_args(c, pb.cp, batch_dev(p, pb, ws), out + pb.out_offset, p->descs[i], nbl);
+        mdx_status st = class_args(c, pb.cp, batch_dev(p, pb, ws), out ? out + pb.out_offset : nullptr, p->descs[i],
+                                   nbl);
         if (st != MDX_OK) return st;
         p->descs[i].nqmax = pb.nqmax;
+        if (dig) {
+            Digest &d = p->descs[i].dig;
+            d.on = 1;
+            d.Db = blk[i].Dbra;
+            d.Dk = blk[i].Dket;
+            d.Jb = blk[i].Jbra;
+            d.Jk = blk[i].Jket;
+            d.nb = (int64_t)pb.cp.bra.pairs.size();
+            d.nk = (int64_t)pb.cp.ket.pairs.size();
+        }
     }
     for (const QueueGroup &g : p->q) {
         std::vector<EriArgs> d;
@@ -191,7 +205,7 @@ mdx_status build_graph(mdx_plan *p, const mdx_shells *sh, double *out, char *ws,
             qa.nb = (int)g.batches.size();
             qa.total = g.base.back();
             qa.counter = counters + g.counter;
-            if (!eri_queue_launch(g.key, g.mfma, g.variant, qa, g.nblocks, g.lds, p->cs[rr++ % mdx_plan::NS]))
+            if (!eri_queue_launch(g.key, g.mfma, g.variant, qa, g.nblocks, g.lds, p->cs[rr++ % mdx_plan::NS], dig))
                 return fail(MDX_EUNSUPPORTED, "persistent kernel instance missing");
         }
         for (int k = 1; k < mdx_plan::NS; ++k) {
@@ -233,8 +247,6 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
     if (!sh) return fail(MDX_EINVAL, "null shell table");
     if (nbatch < 0 || (nbatch > 0 && !batches)) return fail(MDX_EINVAL, "mdx_plan_create: bad batch list");
     if (flags & ~(MDX_CARTESIAN | MDX_FUSED | MDX_DIGEST)) return fail(MDX_EINVAL, "unknown flags 0x%x", flags);
-    if ((flags & MDX_FUSED) && (flags & MDX_DIGEST))
-        return fail(MDX_EINVAL, "mdx_plan_create: MDX_DIGEST plans run as plain launches (no MDX_FUSED)");
     mdx_plan *p = new (std::nothrow) mdx_plan;
     if (!p) return fail(MDX_ENOMEM, "mdx_plan_create: out of host memory");
     p->c = c;
@@ -345,7 +357,8 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
             size_t lds = 0;
             if (mfma) {
                 int nt = 0;
-                if (!eri_mfma_config(cp.key, cp.variant, cp.bra.g.kmax, cp.ket.g.kmax, pb.nqmax, lds, nt)) {
+                if (!eri_mfma_config(cp.key, cp.variant, cp.bra.g.kmax, cp.ket.g.kmax, pb.nqmax, lds, nt,
+                                     (flags & MDX_DIGEST) != 0)) {
                     delete p;
                     return fail(MDX_EUNSUPPORTED,
                                 "batch %d: variant %d of its class has no persistent form (fused plans take the "
@@ -380,7 +393,7 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
                 delete p;
                 return fail(MDX_EUNSUPPORTED, "fused launch needs %zu bytes of LDS", g.lds);
             }
-            const int per_cu = eri_queue_prepare(g.key, g.mfma, g.variant, g.lds);
+            const int per_cu = eri_queue_prepare(g.key, g.mfma, g.variant, g.lds, (flags & MDX_DIGEST) != 0);
             if (per_cu <= 0) {
                 delete p;
                 return fail(MDX_EUNSUPPORTED, "persistent kernel cannot be made resident");
@@ -516,6 +529,18 @@ extern "C" mdx_status mdx_plan_digest(mdx_plan *p, const mdx_shells *sh, const m
     HIP_TRY2(hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     char *w = (char *)ws;
+    if (p->fused) {   // the digesting graph; its batch descriptors hold the blocks' pointers
+        const bool same = p->k_blk.size() == p->b.size() &&
+                          std::memcmp(p->k_blk.data(), blk, p->b.size() * sizeof(mdx_digest_block)) == 0;
+        if (!p->exec || !same || p->k_center != sh->center || p->k_exp != sh->exponent || p->k_coef != sh->coef ||
+            p->k_ws != ws) {
+            mdx_status st = build_graph(p, sh, nullptr, w, s, blk);
+            if (st != MDX_OK) return st;
+            p->k_blk.assign(blk, blk + p->b.size());
+        }
+        HIP_TRY2(hipGraphLaunch(p->exec, s));
+        return MDX_OK;
+    }
     for (size_t i = 0; i < p->b.size(); ++i) {
         const PlanBatch &pb = p->b[i];
         const ClassPlan &cp = pb.cp;

@@ -19,6 +19,8 @@
 // pair the lane accumulates sum_I q_I [r]_I^(0) over all charges -- Boys
 // function and recursion per charge -- and only then contracts that one set
 // of Hermite integrals with the pair's E coefficients.
+#include <utility>
+
 #include "eri_common.h"
 #include "runtime.h"
 
@@ -361,6 +363,185 @@ constexpr int nuclear_waves() { return LA + LB <= 2 ? 4 : (LA + LB == 3 ? 2 : 1)
 template <int LA, int LB>
 constexpr bool nuclear_lds_rows() { return true; }
 
+// ---------------------------------------------------------------------------
+// Hermite-to-Cartesian step of the lane kernel for L = l_a + l_b >= 3.
+// The E^{ab}_{tuv} of Eq. (34) are the coefficients of x_A^a x_B^b in the
+// Hermite Gaussians at P, and they factor.  With x_A = x_P + (P - A),
+// x_B = x_P + (P - B) (binomial shifts) and
+//   x_P^e exp(-p x_P^2) = sum_t c^e_t Lambda_t,
+//   c^{e+1}_t = c^e_{t-1} / (2p) + (t + 1) c^e_{t+1}
+// (Eq. (10) at X_PA = 0; closed form c^e_t = e! / (t! k! 2^k) (2p)^-(t+k)
+// for e = t + 2k), the sum of Eq. (34) is taken in two stages:
+//   M_e  = sum_tuv c^{e_x}_t c^{e_y}_u c^{e_z}_v [tuv]        (|e| <= L),
+//   V_ab = sum_{k<=a, k'<=b} C(a,k) C(b,k') (P-A)^{a-k} (P-B)^{b-k'} M_{k+k'}.
+// M replaces the Hermite table in place, one axis at a time, so a lane holds
+// one table of N_H(L) values instead of the pair's three E tables next to it
+// (which spilled to scratch for L >= 3).  Both shifts start from P, so the
+// terms have the magnitudes of the direct sum; a shift from A to B after the
+// primitive sum would multiply rounding errors by up to (|AB| / width)^l_b.
+// ---------------------------------------------------------------------------
+template <int LA, int LB>
+constexpr bool nuclear_factored() { return LA + LB >= 3; }
+
+__host__ __device__ constexpr int binom(int n, int k)
+{
+    int r = 1;
+    for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+    return r;
+}
+
+// e! / (t! k! 2^k), e = t + 2k
+__host__ __device__ constexpr int mono_coef(int e, int t)
+{
+    const int k = (e - t) / 2;
+    int r = 1;
+    for (int i = t + k + 1; i <= e; ++i) r *= i;   // e! / (t+k)!
+    for (int i = 2; i <= k; ++i) r /= i;           // / k!
+    int num = 1;
+    for (int i = t + 1; i <= t + k; ++i) num *= i; // (t+k)! / t!
+    return r * num / (1 << k);
+}
+
+__host__ __device__ constexpr int tuv_axis(Tuv r, int ax) { return ax == 0 ? r.t : (ax == 1 ? r.u : r.v); }
+
+struct MonoTerm {
+    short dst, src;
+    signed char e, t, first, last;
+};
+
+__host__ __device__ constexpr int mono_terms(int L, int ax)
+{
+    int n = 0;
+    for (int k = 0; k < nherm(L); ++k) {
+        const int e = tuv_axis(herm_tuv(k), ax);
+        if (e > 0) n += e / 2 + 1;
+    }
+    return n;
+}
+
+// along axis AX, every slot with axis exponent e >= 1 becomes
+// sum_{t = e, e-2, ...} c^e_t (slot with that exponent t); slots are rewritten
+// in order of decreasing e, so each reads values not yet replaced
+template <int L, int AX>
+struct MonoPlan {
+    static constexpr int N = mono_terms(L, AX);
+    MonoTerm s[N > 0 ? N : 1];
+    constexpr MonoPlan() : s{}
+    {
+        int n = 0;
+        for (int e = L; e >= 1; --e)
+            for (int k = 0; k < nherm(L); ++k) {
+                const Tuv r = herm_tuv(k);
+                if (tuv_axis(r, AX) != e) continue;
+                for (int t = e; t >= 0; t -= 2) {
+                    const int src = herm_index(AX == 0 ? t : r.t, AX == 1 ? t : r.u, AX == 2 ? t : r.v);
+                    s[n].dst = (short)k;
+                    s[n].src = (short)src;
+                    s[n].e = (signed char)e;
+                    s[n].t = (signed char)t;
+                    s[n].first = (signed char)(t == e);
+                    s[n].last = (signed char)(t < 2);
+                    ++n;
+                }
+            }
+    }
+};
+
+template <int L, int AX>
+__device__ __forceinline__ void monomial_axis(double *__restrict__ W, const double (&ch)[L + 1][L + 1])
+{
+    constexpr MonoPlan<L, AX> plan{};
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < plan.N; ++i) {
+        const MonoTerm m = plan.s[i];
+        acc = m.first ? ch[m.e][m.t] * W[m.src] : fma(ch[m.e][m.t], W[m.src], acc);
+        if (m.last) W[m.dst] = acc;
+    }
+}
+
+// [tuv] -> M_e in place (h = 1/(2p))
+template <int L>
+__device__ __forceinline__ void hermite_to_monomial(double *__restrict__ W, double h)
+{
+    double hp[L + 1];
+    hp[0] = 1.0;
+#pragma unroll
+    for (int n = 1; n <= L; ++n) hp[n] = hp[n - 1] * h;
+    double ch[L + 1][L + 1];
+#pragma unroll
+    for (int e = 0; e <= L; ++e)
+#pragma unroll
+        for (int t = 0; t <= L; ++t) ch[e][t] = (t <= e && (e - t) % 2 == 0) ? (double)mono_coef(e, t) * hp[(e + t) / 2] : 0.0;
+    monomial_axis<L, 0>(W, ch);
+    monomial_axis<L, 1>(W, ch);
+    monomial_axis<L, 2>(W, ch);
+}
+
+template <int L>
+struct HermTab {
+    signed char t[nherm(L)], u[nherm(L)], v[nherm(L)];
+    constexpr HermTab() : t{}, u{}, v{}
+    {
+        for (int k = 0; k < nherm(L); ++k) {
+            const Tuv r = herm_tuv(k);
+            t[k] = (signed char)r.t;
+            u[k] = (signed char)r.u;
+            v[k] = (signed char)r.v;
+        }
+    }
+};
+
+// bra function I of the shift: U[k'] = sum_k C(a,k) (P-A)^{a-k} M_{k+k'} over
+// |k'| <= l_b, then V[I][j] += f sum_{k'<=b_j} C(b_j,k') (P-B)^{b_j-k'} U[k']
+template <int LA, int LB, int I>
+__device__ __forceinline__ void shift_bra_function(const double *__restrict__ W, const double (&pa)[3][LA + 1],
+                                                   const double (&pb)[3][LB + 1], double f,
+                                                   double (&V)[ncart(LA)][ncart(LB)])
+{
+    constexpr int ax = cart_exp(LA, I, 0), ay = cart_exp(LA, I, 1), az = cart_exp(LA, I, 2);
+    constexpr int NK = nherm(LB), NB = ncart(LB);
+    constexpr HermTab<LB> hk{};
+    double U[NK];
+#pragma unroll
+    for (int kx = 0; kx <= ax; ++kx)
+#pragma unroll
+        for (int ky = 0; ky <= ay; ++ky)
+#pragma unroll
+            for (int kz = 0; kz <= az; ++kz) {
+                const double c = (double)(binom(ax, kx) * binom(ay, ky) * binom(az, kz)) * pa[0][ax - kx] *
+                                 pa[1][ay - ky] * pa[2][az - kz];
+#pragma unroll
+                for (int q = 0; q < NK; ++q) {
+                    const double w = W[herm_index(kx + hk.t[q], ky + hk.u[q], kz + hk.v[q])];
+                    U[q] = (kx | ky | kz) ? fma(c, w, U[q]) : c * w;
+                }
+            }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const int bx = hk.t[nherm(LB - 1) + j], by = hk.u[nherm(LB - 1) + j], bz = hk.v[nherm(LB - 1) + j];
+        double s = 0.0;
+#pragma unroll
+        for (int kx = 0; kx <= bx; ++kx)
+#pragma unroll
+            for (int ky = 0; ky <= by; ++ky)
+#pragma unroll
+                for (int kz = 0; kz <= bz; ++kz)
+                    s = fma((double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * pb[0][bx - kx] *
+                                pb[1][by - ky] * pb[2][bz - kz],
+                            U[herm_index(kx, ky, kz)], s);
+        V[I][j] = fma(f, s, V[I][j]);
+    }
+}
+
+template <int LA, int LB, int... Is>
+__device__ __forceinline__ void shift_pair(const double *__restrict__ W, const double (&pa)[3][LA + 1],
+                                           const double (&pb)[3][LB + 1], double f,
+                                           double (&V)[ncart(LA)][ncart(LB)], std::integer_sequence<int, Is...>)
+{
+    (shift_bra_function<LA, LB, Is>(W, pa, pb, f, V), ...);
+}
+
 template <int LA, int LB, bool CART, int G, bool LT>
 __global__ void __launch_bounds__(64 * G) nuclear_kernel(NuclearArgs a)
 {
@@ -414,34 +595,49 @@ __global__ void __launch_bounds__(64 * G) nuclear_kernel(NuclearArgs a)
                         S[m] = f * F[m];
                         f *= m2p;
                     }
-                    double R[(L + 1) * NH];
-                    r_recursion<L>(S, X, Y, Z, R);
-#pragma unroll
-                    for (int k = 0; k < NH; ++k) Rs[k] += R[k];
+                    r_accumulate<L>(S, X, Y, Z, Rs);
                 }
-                // E coefficients of the pair and the bra transform, Eq. (34)
-                double E[3][LA + 1][LB + 1][L + 1];
-#pragma unroll
-                for (int ax = 0; ax < 3; ++ax) e_axis<LA, LB>(0.5 * rp, zb * rp * (B[ax] - A[ax]), za * rp * (A[ax] - B[ax]), E[ax]);
                 const double f = -ca * cb * exp(-za * zb * rp * AB2);
+                if constexpr (nuclear_factored<LA, LB>()) {
+                    // Eq. (34) in two stages: monomials at P, then the shifts to A and B
+                    double pa[3][LA + 1], pb[3][LB + 1];
 #pragma unroll
-                for (int i = 0; i < NA; ++i)
+                    for (int ax = 0; ax < 3; ++ax) {
+                        const double xa = zb * rp * (B[ax] - A[ax]), xb = za * rp * (A[ax] - B[ax]);
+                        pa[ax][0] = 1.0;
+                        pb[ax][0] = 1.0;
 #pragma unroll
-                    for (int j = 0; j < NB; ++j) {
-                        const int ix = cart_exp(LA, i, 0), iy = cart_exp(LA, i, 1), iz = cart_exp(LA, i, 2);
-                        const int jx = cart_exp(LB, j, 0), jy = cart_exp(LB, j, 1), jz = cart_exp(LB, j, 2);
-                        double s = 0.0;
+                        for (int n = 1; n <= LA; ++n) pa[ax][n] = pa[ax][n - 1] * xa;
 #pragma unroll
-                        for (int t = 0; t <= ix + jx; ++t)
-#pragma unroll
-                            for (int u = 0; u <= iy + jy; ++u) {
-                                const double etu = E[0][ix][jx][t] * E[1][iy][jy][u];
-#pragma unroll
-                                for (int v = 0; v <= iz + jz; ++v)
-                                    s = fma(etu * E[2][iz][jz][v], Rs[herm_index(t, u, v)], s);
-                            }
-                        V[i][j] = fma(f, s, V[i][j]);
+                        for (int n = 1; n <= LB; ++n) pb[ax][n] = pb[ax][n - 1] * xb;
                     }
+                    hermite_to_monomial<L>(Rs, 0.5 * rp);
+                    shift_pair<LA, LB>(Rs, pa, pb, f, V, std::make_integer_sequence<int, NA>{});
+                } else {
+                    // E coefficients of the pair and the bra transform, Eq. (34)
+                    double E[3][LA + 1][LB + 1][L + 1];
+#pragma unroll
+                    for (int ax = 0; ax < 3; ++ax)
+                        e_axis<LA, LB>(0.5 * rp, zb * rp * (B[ax] - A[ax]), za * rp * (A[ax] - B[ax]), E[ax]);
+#pragma unroll
+                    for (int i = 0; i < NA; ++i)
+#pragma unroll
+                        for (int j = 0; j < NB; ++j) {
+                            const int ix = cart_exp(LA, i, 0), iy = cart_exp(LA, i, 1), iz = cart_exp(LA, i, 2);
+                            const int jx = cart_exp(LB, j, 0), jy = cart_exp(LB, j, 1), jz = cart_exp(LB, j, 2);
+                            double s = 0.0;
+#pragma unroll
+                            for (int t = 0; t <= ix + jx; ++t)
+#pragma unroll
+                                for (int u = 0; u <= iy + jy; ++u) {
+                                    const double etu = E[0][ix][jx][t] * E[1][iy][jy][u];
+#pragma unroll
+                                    for (int v = 0; v <= iz + jz; ++v)
+                                        s = fma(etu * E[2][iz][jz][v], Rs[herm_index(t, u, v)], s);
+                                }
+                            V[i][j] = fma(f, s, V[i][j]);
+                        }
+                }
             }
         }
     }

@@ -355,11 +355,15 @@ __device__ __forceinline__ void boys_eval_rows(double x, double *__restrict__ F,
 // through LDS at the end.  Splitting the charges gives a batch of 65,536
 // pairs G waves per SIMD instead of one, at the price of G transforms per
 // primitive pair -- worth it where registers leave room for more waves
-// (measured: 4 waves up to L = 2, 2 for L = 3; (d|d) needs 256 VGPRs and
-// runs best with one).  LT: Boys rows staged in LDS (else read from the
+// (measured: 4 waves up to L = 2, 2 for L = 3 and 4).  At L = 4 the kernel
+// is held to 256 registers so that two waves share a SIMD ((d|d) K=5 took
+// 14 % less time than with one wave of 264 registers); L = 5, 6 keep one
+// wave of up to 512.  LT: Boys rows staged in LDS (else read from the
 // global table; LDS was faster for every class).
 template <int LA, int LB>
-constexpr int nuclear_waves() { return LA + LB <= 2 ? 4 : (LA + LB == 3 ? 2 : 1); }
+constexpr int nuclear_waves() { return LA + LB <= 2 ? 4 : (LA + LB <= 4 ? 2 : 1); }
+template <int LA, int LB>
+constexpr int nuclear_wpe() { return LA + LB == 4 ? 2 : 1; }
 template <int LA, int LB>
 constexpr bool nuclear_lds_rows() { return true; }
 
@@ -543,7 +547,7 @@ __device__ __forceinline__ void shift_pair(const double *__restrict__ W, const d
 }
 
 template <int LA, int LB, bool CART, int G, bool LT>
-__global__ void __launch_bounds__(64 * G) nuclear_kernel(NuclearArgs a)
+__global__ void __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(nuclear_wpe<LA, LB>()))) nuclear_kernel(NuclearArgs a)
 {
     constexpr int L = LA + LB, NH = nherm(L), NA = ncart(LA), NB = ncart(LB), NF = NA * NB;
     constexpr int NROWT = BOYS_NROW * BOYS_NTERM;

@@ -268,8 +268,8 @@ mdx_status mdx_one_body_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t np
  *   ws      DEVICE, at least mdx_nuclear_workspace_size bytes (which depends
  *           on the charge count), 256-byte aligned.
  *   flags   MDX_SPHERICAL or MDX_CARTESIAN.
- * Classes with l_a, l_b <= 3 run one shell pair per lane.  Classes with a
- * shell of l = 4..6 run on the matrix-core integral kernel: a point charge is
+ * Classes with l_a + l_b <= 6 run one shell pair per lane.  Larger classes
+ * (a shell of l = 4..6) run on the matrix-core integral kernel: a point charge is
  * the infinite-exponent limit of an s Gaussian, so the batch is the 4-centre
  * chain (ab|s s) with one ket pair whose primitives are the charges, and the
  * kernel's contraction over the terminal ket Hermite of each primitive is the

@@ -176,7 +176,8 @@ mdx_status nuc_plan(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32
 // (K = 5, 100 charges: 222 vs 21 ms per 65,536 pairs) -- with no ket Hermites
 // beyond the terminal one, the kernel's time is the per-charge [r]^(0) tables,
 // built a few at a time in LDS
-bool nuclear_on_mfma(int la, int lb) { return std::max(la, lb) >= 4; }
+// the lane kernel (onebody.hip) takes every class with l_a + l_b <= 6
+bool nuclear_on_mfma(int la, int lb) { return la + lb > 6; }
 
 mdx_status nuclear_mfma_workspace(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la,
                                   int lb, int32_t ncharge, bool cart, size_t &bytes)

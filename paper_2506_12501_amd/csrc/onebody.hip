@@ -538,12 +538,55 @@ __device__ __forceinline__ void shift_bra_function(const double *__restrict__ W,
     }
 }
 
+// the same with the roles swapped, for l_b > l_a (the shorter intermediate):
+// U[k] = sum_{k'<=b} C(b,k') (P-B)^{b-k'} M_{k+k'} over |k| <= l_a for ket function J
+template <int LA, int LB, int J>
+__device__ __forceinline__ void shift_ket_function(const double *__restrict__ W, const double (&pa)[3][LA + 1],
+                                                   const double (&pb)[3][LB + 1], double f,
+                                                   double (&V)[ncart(LA)][ncart(LB)])
+{
+    constexpr int bx = cart_exp(LB, J, 0), by = cart_exp(LB, J, 1), bz = cart_exp(LB, J, 2);
+    constexpr int NK = nherm(LA), NA = ncart(LA);
+    constexpr HermTab<LA> hk{};
+    double U[NK];
+#pragma unroll
+    for (int kx = 0; kx <= bx; ++kx)
+#pragma unroll
+        for (int ky = 0; ky <= by; ++ky)
+#pragma unroll
+            for (int kz = 0; kz <= bz; ++kz) {
+                const double c = (double)(binom(bx, kx) * binom(by, ky) * binom(bz, kz)) * pb[0][bx - kx] *
+                                 pb[1][by - ky] * pb[2][bz - kz];
+#pragma unroll
+                for (int q = 0; q < NK; ++q) {
+                    const double w = W[herm_index(kx + hk.t[q], ky + hk.u[q], kz + hk.v[q])];
+                    U[q] = (kx | ky | kz) ? fma(c, w, U[q]) : c * w;
+                }
+            }
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int ax = hk.t[nherm(LA - 1) + i], ay = hk.u[nherm(LA - 1) + i], az = hk.v[nherm(LA - 1) + i];
+        double s = 0.0;
+#pragma unroll
+        for (int kx = 0; kx <= ax; ++kx)
+#pragma unroll
+            for (int ky = 0; ky <= ay; ++ky)
+#pragma unroll
+                for (int kz = 0; kz <= az; ++kz)
+                    s = fma((double)(binom(ax, kx) * binom(ay, ky) * binom(az, kz)) * pa[0][ax - kx] *
+                                pa[1][ay - ky] * pa[2][az - kz],
+                            U[herm_index(kx, ky, kz)], s);
+        V[i][J] = fma(f, s, V[i][J]);
+    }
+}
+
 template <int LA, int LB, int... Is>
 __device__ __forceinline__ void shift_pair(const double *__restrict__ W, const double (&pa)[3][LA + 1],
                                            const double (&pb)[3][LB + 1], double f,
                                            double (&V)[ncart(LA)][ncart(LB)], std::integer_sequence<int, Is...>)
 {
-    (shift_bra_function<LA, LB, Is>(W, pa, pb, f, V), ...);
+    if constexpr (LB > LA) (shift_ket_function<LA, LB, Is>(W, pa, pb, f, V), ...);
+    else (shift_bra_function<LA, LB, Is>(W, pa, pb, f, V), ...);
 }
 
 template <int LA, int LB, bool CART, int G, bool LT>
@@ -616,7 +659,7 @@ __global__ void __launch_bounds__(64 * G) __attribute__((amdgpu_waves_per_eu(nuc
                         for (int n = 1; n <= LB; ++n) pb[ax][n] = pb[ax][n - 1] * xb;
                     }
                     hermite_to_monomial<L>(Rs, 0.5 * rp);
-                    shift_pair<LA, LB>(Rs, pa, pb, f, V, std::make_integer_sequence<int, NA>{});
+                    shift_pair<LA, LB>(Rs, pa, pb, f, V, std::make_integer_sequence<int, (LB > LA ? NB : NA)>{});
                 } else {
                     // E coefficients of the pair and the bra transform, Eq. (34)
                     double E[3][LA + 1][LB + 1][L + 1];
@@ -803,6 +846,40 @@ static mdx_status prof_open(mdx_ctx *c, hipStream_t s, hipEvent_t *ev1)
     default: LAUNCH<3, 3>(__VA_ARGS__); break;           \
     }
 
+// one case per (l_a, l_b) with l_a + l_b <= 6 (the classes of the 1-particle
+// Coulomb lane kernel)
+#define MDX_NUCLEAR_LANE_SWITCH(LAUNCH, la, lb, ...)    \
+    switch ((la) * 7 + (lb)) {                           \
+    case 0: LAUNCH<0, 0>(__VA_ARGS__); break; \
+    case 1: LAUNCH<0, 1>(__VA_ARGS__); break; \
+    case 7: LAUNCH<1, 0>(__VA_ARGS__); break; \
+    case 2: LAUNCH<0, 2>(__VA_ARGS__); break; \
+    case 8: LAUNCH<1, 1>(__VA_ARGS__); break; \
+    case 14: LAUNCH<2, 0>(__VA_ARGS__); break; \
+    case 3: LAUNCH<0, 3>(__VA_ARGS__); break; \
+    case 9: LAUNCH<1, 2>(__VA_ARGS__); break; \
+    case 15: LAUNCH<2, 1>(__VA_ARGS__); break; \
+    case 21: LAUNCH<3, 0>(__VA_ARGS__); break; \
+    case 4: LAUNCH<0, 4>(__VA_ARGS__); break; \
+    case 10: LAUNCH<1, 3>(__VA_ARGS__); break; \
+    case 16: LAUNCH<2, 2>(__VA_ARGS__); break; \
+    case 22: LAUNCH<3, 1>(__VA_ARGS__); break; \
+    case 28: LAUNCH<4, 0>(__VA_ARGS__); break; \
+    case 5: LAUNCH<0, 5>(__VA_ARGS__); break; \
+    case 11: LAUNCH<1, 4>(__VA_ARGS__); break; \
+    case 17: LAUNCH<2, 3>(__VA_ARGS__); break; \
+    case 23: LAUNCH<3, 2>(__VA_ARGS__); break; \
+    case 29: LAUNCH<4, 1>(__VA_ARGS__); break; \
+    case 35: LAUNCH<5, 0>(__VA_ARGS__); break; \
+    case 6: LAUNCH<0, 6>(__VA_ARGS__); break; \
+    case 12: LAUNCH<1, 5>(__VA_ARGS__); break; \
+    case 18: LAUNCH<2, 4>(__VA_ARGS__); break; \
+    case 24: LAUNCH<3, 3>(__VA_ARGS__); break; \
+    case 30: LAUNCH<4, 2>(__VA_ARGS__); break; \
+    case 36: LAUNCH<5, 1>(__VA_ARGS__); break; \
+    default: LAUNCH<6, 0>(__VA_ARGS__); break; \
+    }
+
 #define MDX_ONEBODY_SWITCH7(LAUNCH, la, lb, ...)         \
     switch ((la) * 7 + (lb)) {                           \
     case 0: LAUNCH<0, 0>(__VA_ARGS__); break; \
@@ -898,7 +975,7 @@ mdx_status nuclear_lane_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *
     a.Ca = c->solid + c->solid_off[la];
     a.Cb = c->solid + c->solid_off[lb];
     a.V = V;
-    MDX_ONEBODY_SWITCH(launch_nuclear, la, lb, a, cart, s)
+    MDX_NUCLEAR_LANE_SWITCH(launch_nuclear, la, lb, a, cart, s)
     HIP_TRY2(hipGetLastError());
     if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
     return MDX_OK;

@@ -13,7 +13,7 @@ from tests.gpu_util import assert_close
 
 pytestmark = pytest.mark.gpu
 
-LET = "spdf"
+LET = "spdfghi"
 
 
 def run(basis, pairs, charges, cart, quad=False):
@@ -54,6 +54,29 @@ def test_classes_contracted(la, lb, cart):
     ch = charges_with_edges(basis, pairs, 100, seed=la + 5 * lb)
     got, ref = run(basis, pairs, ch, cart)
     assert_close(got, ref, f"V {la}{lb}")
+
+
+# shells of l = 4..6 in classes with l_a + l_b <= 6 run on the lane kernel too
+LANE_HIGH = [(la, lb) for la in range(7) for lb in range(7) if max(la, lb) >= 4 and la + lb <= 6]
+
+
+@pytest.mark.parametrize("la,lb", LANE_HIGH)
+def test_lane_classes_with_a_high_shell(la, lb):
+    """65 pairs (a full wave and a ragged one), K = 2, 40 charges plus the edge
+    charges, against the __float128 oracle (the fp64 oracle's solid transform
+    of an l >= 5 shell is not accurate to the bar)"""
+    basis, pairs = pair_batch(la, lb, 65, 2, seed=41 + 7 * la + lb)
+    ch = charges_with_edges(basis, pairs, 40, seed=la + 7 * lb)
+    got, ref = run(basis, pairs, ch, False, quad=True)
+    assert_close(got, ref, f"V {la}{lb}")
+
+
+@pytest.mark.parametrize("la,lb", [(4, 2), (0, 6)])
+def test_lane_classes_with_a_high_shell_cartesian(la, lb):
+    basis, pairs = pair_batch(la, lb, 65, 2, seed=43 + 7 * la + lb)
+    ch = charges_with_edges(basis, pairs, 40, seed=la + 5 * lb)
+    got, ref = run(basis, pairs, ch, True, quad=True)
+    assert_close(got, ref, f"V {la}{lb} Cartesian")
 
 
 @pytest.mark.parametrize("npair", [1, 64, 65, 130])

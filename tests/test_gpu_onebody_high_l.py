@@ -2,8 +2,9 @@
 Table 2 beyond f), GPU vs the __float128 oracle (the fp64 oracle's solid
 transform of an l = 6 shell loses up to ~1e-11 of the block maximum), through
 the C-ABI entry points: overlap and kinetic energy on the one-pair-per-wave
-kernel, nuclear attraction on the matrix-core kernel with the charges as
-point-like ket primitives (Eq. (37) as the early contraction over them)."""
+kernel; nuclear attraction on the lane kernel for l_a + l_b <= 6 and, beyond,
+on the matrix-core kernel with the charges as point-like ket primitives
+(Eq. (37) as the early contraction over them)."""
 import numpy as np
 import pytest
 
@@ -86,11 +87,11 @@ def test_nuclear_cartesian(la, lb):
 
 
 def test_nuclear_many_charges_in_slices():
-    """more than 64 charges: the kernel runs in slices whose partial results
-    are added (150 charges: three slices, the last one partial)"""
-    basis, pairs = pair_batch(4, 2, 3, 1, seed=5)
+    """more than 64 charges on the matrix-core kernel: it runs in slices whose
+    partial results are added (150 charges: three slices, the last one partial)"""
+    basis, pairs = pair_batch(4, 3, 3, 1, seed=5)
     got, ref = _nuclear(basis, pairs, _charges(basis, pairs, 147, seed=6), False)
-    assert_close(got, ref, "V (g|d) 150 charges")
+    assert_close(got, ref, "V (g|f) 150 charges")
 
 
 def test_nuclear_no_charges_gives_zero():

@@ -133,10 +133,10 @@ def test_one_body_run_captured_in_graph(la, lb):
     _replays(p, sh, _moved_centres(basis, 3, seed=6), write, plain)
 
 
-@pytest.mark.parametrize("la,lb", [(2, 1), (4, 2)])
+@pytest.mark.parametrize("la,lb", [(2, 1), (4, 2), (4, 3)])
 def test_nuclear_run_captured_in_graph(la, lb):
-    """(d|p): the lane kernel; (g|d): the matrix-core path with the charges as
-    point-limit ket primitives (the charges are read at replay time)"""
+    """(d|p), (g|d): the lane kernel; (g|f): the matrix-core path with the
+    charges as point-limit ket primitives (the charges are read at replay time)"""
     import torch
     native = _native()
     basis, pairs = W.one_body_pairs(la, lb, 9, 7, 2, seed=la * 5 + lb)

@@ -120,6 +120,16 @@ struct PairDataArgs {
     int per_block;       // items per workgroup (set by launch_pairdata)
 };
 void launch_pairdata(const PairDataArgs &a, hipStream_t s);
+// per_block of a record set, its workgroup count returned and LDS bytes in lds
+int pairdata_prepare(PairDataArgs &a, size_t &lds);
+// records recs[0 .. nrec-1] (prepared, in device memory), record r owning
+// workgroups base[r] .. base[r+1]-1 of one launch of nblk = base[nrec]
+struct PairDataMulti {
+    const PairDataArgs *recs;
+    const int32_t *base;
+    int nrec;
+};
+void launch_pairdata_multi(const PairDataMulti &m, int nblk, size_t lds, hipStream_t s);
 
 bool eri_valu_has(const EriKey &k);
 bool eri_valu_launch(const EriKey &k, const EriArgs &a, int nblocks, hipStream_t s);

@@ -63,12 +63,15 @@ __host__ __device__ inline size_t pairdata_lds_bytes(const SideGeom &g, int per_
     return ((size_t)per_block * pd_item_doubles(g) + nf * PD_NTM) * 8 + (nf + nf * PD_NTM * 3) * 4;
 }
 
-// H elements one item writes (rows x padded columns; the derivative role six blocks)
+// H elements a typical item writes (rows x padded columns; the derivative
+// role six blocks).  The last primitive of a pair also zeroes the rows up to
+// the next 16-row tile, in more passes of the same threads; sizing groups by
+// that rare case gave an s item 128 threads for its 16 elements.
 static int pd_item_elements(const SideGeom &g)
 {
     if (g.grouped) return (g.role == 0 ? g.rows_per_block : g.nterm) * g.ncolp;
     if (g.role == 1) return g.rows_per_block * g.ncolp;
-    return (g.role == 2 ? 6 : 1) * (g.nh + 15) * g.ncolp;
+    return (g.role == 2 ? 6 : 1) * g.nh * g.ncolp;
 }
 
 // Items per 256-thread workgroup: each item gets a power-of-two group of
@@ -83,13 +86,14 @@ static int pd_per_block(const SideGeom &g)
     return PD_THREADS / t;
 }
 
-__global__ void __launch_bounds__(PD_THREADS) pairdata_kernel(PairDataArgs a)
+// workgroup blk of the launch of one side record
+__device__ __forceinline__ void pairdata_block(const PairDataArgs &a, int blk)
 {
     const SideGeom &g = a.g;
     const int G = a.per_block;                      // items of this workgroup
     const int T = PD_THREADS / G;                   // threads of one item
     const int slot = (int)threadIdx.x / T, lt = (int)threadIdx.x % T;
-    const int item = blockIdx.x * G + slot;
+    const int item = blk * G + slot;
     const int nitem = g.grouped ? g.npair : a.nitems;
     const bool live = item < nitem;                 // dead slots still reach every barrier
     // one item = one primitive pair of a pair (items), or one pair (grouped side)
@@ -340,14 +344,44 @@ __global__ void __launch_bounds__(PD_THREADS) pairdata_kernel(PairDataArgs a)
 
 #undef E
 
+__global__ void __launch_bounds__(PD_THREADS) pairdata_kernel(PairDataArgs a) { pairdata_block(a, blockIdx.x); }
+
+// Several side records in one launch: workgroups base[r] .. base[r+1]-1 are
+// record r's (records without items own none).  A launch of every record of
+// a plan lets the hardware spread them over the chip instead of running the
+// records one after another on a few streams.
+__global__ void __launch_bounds__(PD_THREADS) pairdata_multi_kernel(PairDataMulti m)
+{
+    const int b = blockIdx.x;
+    int lo = 0, hi = m.nrec;   // base[lo] <= b < base[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (m.base[mid] <= b) lo = mid;
+        else hi = mid;
+    }
+    const PairDataArgs a = m.recs[lo];
+    pairdata_block(a, b - m.base[lo]);
+}
+
+int pairdata_prepare(PairDataArgs &a, size_t &lds)
+{
+    a.per_block = pd_per_block(a.g);
+    const int nitem = a.g.grouped ? a.g.npair : a.nitems;
+    lds = pairdata_lds_bytes(a.g, a.per_block);
+    return (nitem + a.per_block - 1) / a.per_block;
+}
+
 void launch_pairdata(const PairDataArgs &a0, hipStream_t s)
 {
     PairDataArgs a = a0;
-    a.per_block = pd_per_block(a.g);
-    const int nitem = a.g.grouped ? a.g.npair : a.nitems;
-    const int nblk = (nitem + a.per_block - 1) / a.per_block;
-    if (nblk > 0)
-        hipLaunchKernelGGL(pairdata_kernel, dim3(nblk), dim3(PD_THREADS), pairdata_lds_bytes(a.g, a.per_block), s, a);
+    size_t lds = 0;
+    const int nblk = pairdata_prepare(a, lds);
+    if (nblk > 0) hipLaunchKernelGGL(pairdata_kernel, dim3(nblk), dim3(PD_THREADS), lds, s, a);
+}
+
+void launch_pairdata_multi(const PairDataMulti &m, int nblk, size_t lds, hipStream_t s)
+{
+    if (nblk > 0) hipLaunchKernelGGL(pairdata_multi_kernel, dim3(nblk), dim3(PD_THREADS), lds, s, m);
 }
 
 }  // namespace mdx

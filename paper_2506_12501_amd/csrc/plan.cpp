@@ -64,6 +64,7 @@ struct mdx_plan {
     size_t dtab_bytes = 0;
     size_t t_counters = 0;
     int ncounter = 0;
+    size_t t_pd = 0, t_pdbase = 0;   // fused: the side records as one pair-data launch
     // basis metadata at creation
     int32_t nshell = 0;
     std::vector<int32_t> l, nprim, poff;
@@ -163,6 +164,39 @@ mdx_status build_graph(mdx_plan *p, const mdx_shells *sh, double *out, char *ws,
         for (int bi : g.batches) d.push_back(p->descs[bi]);
         HIP_TRY2(hipMemcpy(p->dtab + g.t_desc, d.data(), d.size() * sizeof(EriArgs), hipMemcpyHostToDevice));
     }
+    // pair data of every side record, one launch
+    std::vector<PairDataArgs> pds;
+    std::vector<int32_t> pdbase(1, 0);
+    size_t pd_lds = 0;
+    for (const SideRec &r : p->recs) {
+        PairDataArgs pa{};
+        pa.g = r.sp.g;
+        pa.pairs = (const PairRec *)(p->dtab + r.t_pairs);
+        pa.items = (const int2 *)(p->dtab + r.t_items);
+        pa.nitems = (int)r.sp.items.size();
+        pa.center = sh->center;
+        pa.expo = sh->exponent;
+        pa.coef = sh->coef;
+        pa.Ca = c->solid + c->solid_off[r.sp.g.la];
+        pa.Cb = r.sp.g.lb >= 0 ? c->solid + c->solid_off[r.sp.g.lb] : nullptr;
+        pa.prim = (PrimRec *)(ws + r.w_prim);
+        pa.H = (double *)(ws + r.w_H);
+        pa.nprim = (int32_t *)(ws + r.w_np);
+        size_t lds = 0;
+        const int nblk = std::max(pairdata_prepare(pa, lds), 0);
+        if ((int64_t)pdbase.back() + nblk > INT32_MAX) return fail(MDX_EUNSUPPORTED, "pair data: too many workgroups");
+        pdbase.push_back(pdbase.back() + nblk);
+        if (nblk > 0) pd_lds = std::max(pd_lds, lds);
+        pds.push_back(pa);
+    }
+    if (!pds.empty()) {
+        HIP_TRY2(hipMemcpy(p->dtab + p->t_pd, pds.data(), pds.size() * sizeof(PairDataArgs), hipMemcpyHostToDevice));
+        HIP_TRY2(hipMemcpy(p->dtab + p->t_pdbase, pdbase.data(), pdbase.size() * 4, hipMemcpyHostToDevice));
+    }
+    PairDataMulti pdm{};
+    pdm.recs = (const PairDataArgs *)(p->dtab + p->t_pd);
+    pdm.base = (const int32_t *)(p->dtab + p->t_pdbase);
+    pdm.nrec = (int)pds.size();
 
     hipStream_t s0 = p->cs[0];
     HIP_TRY2(hipStreamBeginCapture(s0, hipStreamCaptureModeThreadLocal));
@@ -170,34 +204,12 @@ mdx_status build_graph(mdx_plan *p, const mdx_shells *sh, double *out, char *ws,
     auto capture = [&]() -> mdx_status {
         int *counters = (int *)(p->dtab + p->t_counters);
         launch_fill_i32(counters, p->ncounter, 0, s0);
-        // fork: pair data of all batches over the side streams
-        HIP_TRY2(hipEventRecord(p->ev[0], s0));
-        for (int k = 1; k < mdx_plan::NS; ++k) HIP_TRY2(hipStreamWaitEvent(p->cs[k], p->ev[0], 0));
-        int rr = 0;
-        for (const SideRec &r : p->recs) {
-            PairDataArgs pa{};
-            pa.g = r.sp.g;
-            pa.pairs = (const PairRec *)(p->dtab + r.t_pairs);
-            pa.items = (const int2 *)(p->dtab + r.t_items);
-            pa.nitems = (int)r.sp.items.size();
-            pa.center = sh->center;
-            pa.expo = sh->exponent;
-            pa.coef = sh->coef;
-            pa.Ca = c->solid + c->solid_off[r.sp.g.la];
-            pa.Cb = r.sp.g.lb >= 0 ? c->solid + c->solid_off[r.sp.g.lb] : nullptr;
-            pa.prim = (PrimRec *)(ws + r.w_prim);
-            pa.H = (double *)(ws + r.w_H);
-            pa.nprim = (int32_t *)(ws + r.w_np);
-            launch_pairdata(pa, p->cs[rr++ % mdx_plan::NS]);
-        }
-        for (int k = 1; k < mdx_plan::NS; ++k) {
-            HIP_TRY2(hipEventRecord(p->ev[k], p->cs[k]));
-            HIP_TRY2(hipStreamWaitEvent(s0, p->ev[k], 0));
-        }
-        // fork again: one persistent launch per kernel instance
+        // pair data of all batches: one launch over every side record
+        launch_pairdata_multi(pdm, pdbase.back(), pd_lds, s0);
+        // fork: one persistent launch per kernel instance over the streams
         HIP_TRY2(hipEventRecord(p->ev[mdx_plan::NS], s0));
         for (int k = 1; k < mdx_plan::NS; ++k) HIP_TRY2(hipStreamWaitEvent(p->cs[k], p->ev[mdx_plan::NS], 0));
-        rr = 0;
+        int rr = 0;
         for (const QueueGroup &g : p->q) {
             QueueArgs qa{};
             qa.desc = (const EriArgs *)(p->dtab + g.t_desc);
@@ -405,6 +417,8 @@ extern "C" mdx_status mdx_plan_create(mdx_ctx *c, const mdx_shells *sh, int nbat
         }
         p->ncounter = (int)p->q.size();
         p->t_counters = ttake(std::max(p->ncounter, 1) * 4);
+        p->t_pd = ttake(std::max(p->recs.size(), (size_t)1) * sizeof(PairDataArgs));
+        p->t_pdbase = ttake((p->recs.size() + 1) * 4);
     }
     p->ws_total = ws;
     p->dtab_bytes = std::max(tab, (size_t)256);

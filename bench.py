@@ -360,9 +360,8 @@ def extra_legs(native, ctx, torch, tune, reps, legs=EXTRA_LEGS):
         nu = {}
         charges = W.point_charges(100, 10.0, seed=0)
         for K in (1, 5):
-            # l_a + l_b <= 6: 256 x 256 pairs, one per lane; beyond, on the
-            # matrix-core kernel: 64 x 64 pairs, K = 1 only (at K = 5 the (i|i)
-            # pair data alone takes 0.36 s per call)
+            # l_a + l_b <= 6: 256 x 256 pairs, one per lane; beyond, one pair per
+            # wave: 64 x 64 pairs, K = 1 only
             for la, lb in [(0, 0), (1, 0), (1, 1), (2, 0), (2, 1), (2, 2), (3, 0), (3, 1), (3, 3), (4, 2), (6, 0),
                            (4, 4), (5, 5), (6, 6)]:
                 if K > 1 and la + lb > 6:

@@ -265,17 +265,13 @@ mdx_status mdx_one_body_batch(mdx_ctx *ctx, const mdx_shells *shells, int32_t np
  *   charges DEVICE double[4*ncharge]: x, y, z (bohr), q of charge I at
  *           charges[4I .. 4I+3].  ncharge = 0 gives V = 0.
  *   V       DEVICE double, [ij, ab] column-major: V[ij + npair*ab].
- *   ws      DEVICE, at least mdx_nuclear_workspace_size bytes (which depends
- *           on the charge count), 256-byte aligned.
+ *   ws      DEVICE, at least mdx_nuclear_workspace_size bytes (the pair
+ *           records), 256-byte aligned.
  *   flags   MDX_SPHERICAL or MDX_CARTESIAN.
  * Classes with l_a + l_b <= 6 run one shell pair per lane.  Larger classes
- * (a shell of l = 4..6) run on the matrix-core integral kernel: a point charge is
- * the infinite-exponent limit of an s Gaussian, so the batch is the 4-centre
- * chain (ab|s s) with one ket pair whose primitives are the charges, and the
- * kernel's contraction over the terminal ket Hermite of each primitive is the
- * charge sum of Eq. (37).
- * Limits: l_a, l_b <= 6; Cartesian classes up to 225 functions per pair
- * (MDX_EUNSUPPORTED otherwise).  Errors: MDX_EINVAL for
+ * run one shell pair per wave, the lanes sharing the Hermite table of order
+ * l_a + l_b by columns (u, v) of it.
+ * Limits: l_a, l_b <= 6.  Errors: MDX_EINVAL for
  * bad arguments, shell indices, mixed classes, a negative charge count or a
  * null charge array with ncharge > 0; MDX_EWORKSPACE for a short workspace;
  * MDX_EDEVICE for a HIP error.  The size query returns 0 on any error.

@@ -30,15 +30,8 @@ static inline size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 constexpr int ONEBODY_LMAX = 6;        // per shell, overlap / kinetic / nuclear attraction
 constexpr int ONEBODY_LANE_LMAX = 3;   // one pair per lane up to here; beyond, one pair per wave
-                                       // (overlap, kinetic) or the matrix-core kernel (nuclear)
+                                       // (overlap, kinetic; nuclear attraction by l_a + l_b instead)
 
-// 1-particle Coulomb integrals of shells with l >= 4 (nuclear_mfma.hip)
-bool nuclear_on_mfma(int la, int lb);
-mdx_status nuclear_mfma_workspace(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la,
-                                  int lb, int32_t ncharge, bool cart, size_t &bytes);
-mdx_status nuclear_mfma_enqueue(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la, int lb,
-                                int32_t ncharge, const double *charges, bool cart, double *V, void *ws,
-                                size_t ws_bytes, hipStream_t s);
 
 struct OneBodyArgs {
     const PairRec *pairs;
@@ -721,6 +714,331 @@ static void launch_nuclear(const NuclearArgs &a, bool cart, hipStream_t s)
     else hipLaunchKernelGGL((nuclear_kernel<LA, LB, false, G, LT>), dim3(nblk), dim3(64 * G), 0, s, a);
 }
 
+// ---------------------------------------------------------------------------
+// 1-particle Coulomb integrals of the classes with l_a + l_b >= 7: one shell
+// pair per wave, lanes over the Hermite columns (u, v) of order L.
+//
+// The charge-summed table of one primitive pair, sum_I [tuv]_I^(0), has
+// N_H(L) values (455 at L = 12), too many for one lane, so the lanes share
+// it: lane c owns column (u_c, v_c) and accumulates its L - u_c - v_c + 1
+// entries over the charges.  A column needs no other lane's values: the
+// recursion of Eq. (31) has the closed form
+//   [tuv]^(0) = sum_{i,j,k} h_{t,i} h_{u,j} h_{v,k} X^{t-2i} Y^{u-2j} Z^{v-2k} S_{t+u+v-i-j-k},
+//   h_{t,i} = t! / (i! (t-2i)! 2^i),  S_n = [000]^(n) (Eq. (30) times the charge),
+// (the derivative d/dX of [000]^(n) is X [000]^(n+1)), which a lane takes as
+//   D_d = sum_{j+k=d} h_{u,j} Y^{u-2j} h_{v,k} Z^{v-2k},   W_n = sum_d D_d S_{n+u+v-d},
+//   [tuv] = sum_i h_{t,i} X^{t-2i} W_{t-i}.
+// The S_n of a charge reach every lane through a small LDS buffer (each lane
+// reads them at its own offset u + v).  After the charges, the transform of
+// Eq. (34) runs in the factored order of the lane kernel, through the wave's
+// LDS table: monomials at P along x (in each lane's column), y and z (lanes
+// over lines), then the binomial shifts to A and B with lanes over the
+// Cartesian function pairs.  Waves synchronise only within themselves (the
+// pairs of a workgroup have different primitive counts).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// h_{t,i} = t! / (i! (t-2i)! 2^i)
+__host__ __device__ constexpr double herm_poly_coef(int t, int i)
+{
+    double r = 1.0;
+    for (int k = 1; k <= t; ++k) r *= k;
+    for (int k = 1; k <= i; ++k) r /= 2 * k;          // i! 2^i
+    for (int k = 1; k <= t - 2 * i; ++k) r /= k;
+    return r;
+}
+
+// compile-time tables of h_{t,i} (i <= t/2) and of the monomial coefficients
+// e! / (t! k! 2^k) (e = t + 2k), both up to order L
+template <int L>
+struct NucCoefTab {
+    double h[L + 1][L / 2 + 1], m[L + 1][L + 1];
+    constexpr NucCoefTab() : h{}, m{}
+    {
+        for (int t = 0; t <= L; ++t)
+            for (int i = 0; 2 * i <= t; ++i) h[t][i] = herm_poly_coef(t, i);
+        for (int e = 0; e <= L; ++e)
+            for (int t = e; t >= 0; t -= 2) m[e][t] = (double)mono_coef(e, t);
+    }
+};
+
+// per-wave LDS (doubles): two S buffers, then a region that holds the
+// Hermite/monomial table and the two shift tables [axis][i][k] during the
+// primitive loop, and the Cartesian block and [NA][2 l_b + 1] for the
+// solid transform after it
+template <int LA, int LB>
+struct NucWaveLds {
+    static constexpr int L = LA + LB, H2 = L / 2;
+    static constexpr int SB = 2 * L + H2 + 1;
+    static constexpr int NH = nherm(L), NG = 3 * 7 * 7;
+    static constexpr int NA = ncart(LA), NB = ncart(LB), NF = NA * NB;
+    static constexpr int RA = NH + 2 * NG > NF + NA * (2 * LB + 1) ? NH + 2 * NG : NF + NA * (2 * LB + 1);
+    static constexpr int OFF_S = 0, OFF_M = 2 * SB, OFF_GA = OFF_M + NH, OFF_GB = OFF_GA + NG, OFF_V = OFF_M;
+    static constexpr int SIZE = 2 * SB + RA;
+    // pairs (waves) per workgroup: as many as 64 KB of static LDS hold next to the Boys rows
+    static constexpr int ROWS_BYTES = BOYS_NROW * BOYS_NTERM * 8;
+    static constexpr int WAVES_FIT = (65536 - ROWS_BYTES) / (SIZE * 8);
+    static constexpr int WAVES = WAVES_FIT >= 4 ? 4 : (WAVES_FIT < 1 ? 1 : WAVES_FIT);
+};
+
+template <int LA, int LB, bool CART>
+__global__ void __launch_bounds__((64 * NucWaveLds<LA, LB>::WAVES))
+__attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(NuclearArgs a)
+{
+    constexpr int L = LA + LB, H2 = L / 2, NA = ncart(LA), NB = ncart(LB), NF = NA * NB;
+    constexpr int NCOL = (L + 1) * (L + 2) / 2;   // columns (u, v), also the lines of the y and z stages
+    constexpr int NCS = (NCOL + 63) / 64, NVS = (NF + 63) / 64;
+    constexpr int NROWT = BOYS_NROW * BOYS_NTERM;
+    using LY = NucWaveLds<LA, LB>;
+    constexpr int NWV = LY::WAVES;
+    constexpr NucCoefTab<L> ct{};
+    static_assert(LY::WAVES_FIT >= 1, "per-wave LDS too large");
+    __shared__ double rows[NROWT];
+    __shared__ double wlds[NWV][LY::SIZE];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < NROWT; i += 64 * NWV)
+        rows[i] = a.boys[(i / BOYS_NTERM) * BOYS_NCOL + L + i % BOYS_NTERM];
+    __syncthreads();   // the only workgroup barrier: the waves below run independently
+
+    const int ij = blockIdx.x * NWV + w;
+    if (ij >= a.npair) return;
+    double *sbuf = wlds[w] + LY::OFF_S, *mt = wlds[w] + LY::OFF_M, *ga = wlds[w] + LY::OFF_GA,
+           *gb = wlds[w] + LY::OFF_GB, *vb = wlds[w] + LY::OFF_V;   // vb: after the primitive loop
+    for (int i = lane; i < 2 * LY::SB; i += 64) sbuf[i] = 0.0;
+
+    // the lane's columns: c = lane + 64 s -> (u, v), u + v = q, c = q (q + 1) / 2 + v
+    int cu[NCS], cv[NCS], cn[NCS];
+    double hy[NCS][H2 + 1], hz[NCS][H2 + 1];
+#pragma unroll
+    for (int s = 0; s < NCS; ++s) {
+        const int c = lane + 64 * s;
+        int q = 0;
+        while ((q + 1) * (q + 2) / 2 <= c) ++q;
+        cv[s] = c - q * (q + 1) / 2;
+        cu[s] = q - cv[s];
+        cn[s] = c < NCOL ? L - q : -1;
+#pragma unroll
+        for (int j = 0; j <= H2; ++j) {
+            hy[s][j] = 2 * j <= cu[s] ? herm_poly_coef(cu[s], j) : 0.0;
+            hz[s][j] = 2 * j <= cv[s] ? herm_poly_coef(cv[s], j) : 0.0;
+        }
+    }
+    double V[NVS];
+#pragma unroll
+    for (int s = 0; s < NVS; ++s) V[s] = 0.0;
+
+    const PairRec pr = a.pairs[ij];
+    const double A[3] = {a.center[3 * pr.sa], a.center[3 * pr.sa + 1], a.center[3 * pr.sa + 2]};
+    const double B[3] = {a.center[3 * pr.sb], a.center[3 * pr.sb + 1], a.center[3 * pr.sb + 2]};
+    const double AB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
+    int parity = 0;
+    for (int ka = 0; ka < pr.ka; ++ka) {
+        const double za = a.expo[pr.offa + ka], ca = a.coef[pr.offa + ka];
+        for (int kb = 0; kb < pr.kb; ++kb) {
+            const double zb = a.expo[pr.offb + kb], cb = a.coef[pr.offb + kb];
+            const double p = za + zb, rp = 1.0 / p;
+            const double P[3] = {A[0] + zb * rp * (B[0] - A[0]), A[1] + zb * rp * (B[1] - A[1]),
+                                 A[2] + zb * rp * (B[2] - A[2])};
+            double Rs[NCS][L + 1];
+#pragma unroll
+            for (int s = 0; s < NCS; ++s)
+#pragma unroll
+                for (int t = 0; t <= L; ++t) Rs[s][t] = 0.0;
+            const double g = 2.0 * M_PI * rp, m2p = -2.0 * p;
+            for (int I = 0; I < a.ncharge; ++I) {
+                const double *ch = a.charges + 4 * I;
+                const double X = P[0] - ch[0], Y = P[1] - ch[1], Z = P[2] - ch[2];
+                double *sb = sbuf + parity * LY::SB;
+                parity ^= 1;
+                {
+                    double F[L + 1];
+                    boys_eval_rows<L>(p * (X * X + Y * Y + Z * Z), F, rows);
+                    double f = ch[3] * g;
+                    if (lane == 0) {
+#pragma unroll
+                        for (int m = 0; m <= L; ++m) {
+                            sb[H2 + m] = f * F[m];
+                            f *= m2p;
+                        }
+                    }
+                }
+                wave_lds_sync();
+                double Xp[L + 1];
+                Xp[0] = 1.0;
+#pragma unroll
+                for (int n = 1; n <= L; ++n) Xp[n] = Xp[n - 1] * X;
+                const double Y2 = Y * Y, Z2 = Z * Z;
+#pragma unroll
+                for (int s = 0; s < NCS; ++s) {
+                    if (cn[s] < 0) continue;
+                    // y and z factors h_{u,j} Y^{u-2j}, h_{v,k} Z^{v-2k}
+                    double yv[H2 + 1], zv[H2 + 1];
+                    double yp = (cu[s] & 1) ? Y : 1.0, zp = (cv[s] & 1) ? Z : 1.0;
+#pragma unroll
+                    for (int j = H2; j >= 0; --j) {
+                        yv[j] = hy[s][j] * yp;
+                        zv[j] = hz[s][j] * zp;
+                        if (2 * j <= cu[s]) yp *= Y2;
+                        if (2 * j <= cv[s]) zp *= Z2;
+                    }
+                    double D[H2 + 1];
+#pragma unroll
+                    for (int d = 0; d <= H2; ++d) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int j = 0; j <= d; ++j) v = fma(yv[j], zv[d - j], v);
+                        D[d] = v;
+                    }
+                    // S_{n + u + v - d} = sb[H2 + n + u + v - d] = Sh[H2 + n - d]
+                    const double *Sh = sb + cu[s] + cv[s];
+                    double W[L + 1];
+#pragma unroll
+                    for (int n = 0; n <= L; ++n) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int d = 0; d <= H2; ++d) v = fma(D[d], Sh[H2 + n - d], v);
+                        W[n] = v;
+                    }
+#pragma unroll
+                    for (int t = 0; t <= L; ++t) {
+                        double v = Rs[s][t];
+#pragma unroll
+                        for (int i = 0; 2 * i <= t; ++i) v = fma(ct.h[t][i] * Xp[t - 2 * i], W[t - i], v);
+                        Rs[s][t] = v;
+                    }
+                }
+            }
+            // Eq. (34), factored: monomials at P along x in each lane's column
+            const double h = 0.5 * rp;
+            double hp[L + 1];
+            hp[0] = 1.0;
+#pragma unroll
+            for (int n = 1; n <= L; ++n) hp[n] = hp[n - 1] * h;
+#pragma unroll
+            for (int s = 0; s < NCS; ++s) {
+                if (cn[s] < 0) continue;
+#pragma unroll
+                for (int e = L; e >= 0; --e) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int t = e; t >= 0; t -= 2) v = fma(ct.m[e][t] * hp[(e + t) / 2], Rs[s][t], v);
+                    if (e <= cn[s]) mt[herm_index(e, cu[s], cv[s])] = v;
+                }
+            }
+            // the binomial shift tables of this primitive pair, [axis][i][k] = C(i,k) (P - centre)^(i-k)
+            for (int e = lane; e < 2 * 3 * 7 * 7; e += 64) {
+                const int side = e / (3 * 7 * 7), ax = (e / 49) % 3, i = (e / 7) % 7, k = e % 7;
+                const double d = side == 0 ? P[ax] - A[ax] : P[ax] - B[ax];
+                double v = 0.0;
+                if (k <= i) {
+                    v = (double)binom(i, k);
+                    for (int n = 0; n < i - k; ++n) v *= d;
+                }
+                (side == 0 ? ga : gb)[e % (3 * 7 * 7)] = v;
+            }
+            wave_lds_sync();
+            // y stage (lines (e_x, v) along u), then z stage (lines (e_x, e_y) along v)
+#pragma unroll
+            for (int stage = 1; stage <= 2; ++stage) {
+#pragma unroll
+                for (int s = 0; s < NCS; ++s) {
+                    if (cn[s] < 0) continue;
+                    const int c0 = cu[s], c1 = cv[s], n = cn[s];   // line (c0, c1): e_x = c0, and v or e_y = c1
+                    double y[L + 1];
+#pragma unroll
+                    for (int k = 0; k <= L; ++k)
+                        y[k] = k <= n ? mt[stage == 1 ? herm_index(c0, k, c1) : herm_index(c0, c1, k)] : 0.0;
+#pragma unroll
+                    for (int e = L; e >= 0; --e) {
+                        double v = 0.0;
+#pragma unroll
+                        for (int t = e; t >= 0; t -= 2) v = fma(ct.m[e][t] * hp[(e + t) / 2], y[t], v);
+                        if (e <= n) mt[stage == 1 ? herm_index(c0, e, c1) : herm_index(c0, c1, e)] = v;
+                    }
+                }
+                wave_lds_sync();
+            }
+            // shifts: V_ab += f sum_{k<=a, k'<=b} C(a,k) C(b,k') (P-A)^{a-k} (P-B)^{b-k'} M_{k+k'}
+            const double f = -ca * cb * exp(-za * zb * rp * AB2);
+#pragma unroll
+            for (int s = 0; s < NVS; ++s) {
+                const int fp = lane + 64 * s;
+                if (fp >= NF) continue;
+                const int ia = fp / NB, ib = fp % NB;
+                const int ax = cart_exp(LA, ia, 0), ay = cart_exp(LA, ia, 1), az = cart_exp(LA, ia, 2);
+                const int bx = cart_exp(LB, ib, 0), by = cart_exp(LB, ib, 1), bz = cart_exp(LB, ib, 2);
+                double sum = 0.0;
+                for (int kx = 0; kx <= ax; ++kx) {
+                    const double cx = ga[(0 * 7 + ax) * 7 + kx];
+                    for (int ky = 0; ky <= ay; ++ky) {
+                        const double cxy = cx * ga[(1 * 7 + ay) * 7 + ky];
+                        for (int kz = 0; kz <= az; ++kz) {
+                            const double cxyz = cxy * ga[(2 * 7 + az) * 7 + kz];
+                            double t = 0.0;
+                            for (int qx = 0; qx <= bx; ++qx) {
+                                const double dx = gb[(0 * 7 + bx) * 7 + qx];
+                                for (int qy = 0; qy <= by; ++qy) {
+                                    const double dxy = dx * gb[(1 * 7 + by) * 7 + qy];
+                                    for (int qz = 0; qz <= bz; ++qz)
+                                        t = fma(dxy * gb[(2 * 7 + bz) * 7 + qz],
+                                                mt[herm_index(kx + qx, ky + qy, kz + qz)], t);
+                                }
+                            }
+                            sum = fma(cxyz, t, sum);
+                        }
+                    }
+                }
+                V[s] = fma(f, sum, V[s]);
+            }
+            wave_lds_sync();   // the table and shift tables are rewritten by the next primitive pair
+        }
+    }
+    // store: Cartesian directly; solid harmonics through the wave's LDS (Eq. (18), ket index first)
+    if constexpr (CART) {
+#pragma unroll
+        for (int s = 0; s < NVS; ++s) {
+            const int fp = lane + 64 * s;
+            if (fp < NF) a.V[ij + (int64_t)a.npair * fp] = V[s];
+        }
+    } else {
+        constexpr int MA = 2 * LA + 1, MB = 2 * LB + 1;
+        double *ub = vb + NF;   // [NA][MB]
+#pragma unroll
+        for (int s = 0; s < NVS; ++s) {
+            const int fp = lane + 64 * s;
+            if (fp < NF) vb[fp] = V[s];
+        }
+        wave_lds_sync();
+        for (int e = lane; e < NA * MB; e += 64) {
+            const int i = e / MB, n = e % MB;
+            double u = 0.0;
+            for (int j = 0; j < NB; ++j) u = fma(a.Cb[n * NB + j], vb[i * NB + j], u);
+            ub[e] = u;
+        }
+        wave_lds_sync();
+        for (int e = lane; e < MA * MB; e += 64) {
+            const int m = e / MB, n = e % MB;
+            double v = 0.0;
+            for (int i = 0; i < NA; ++i) v = fma(a.Ca[m * NA + i], ub[i * MB + n], v);
+            a.V[ij + (int64_t)a.npair * e] = v;
+        }
+    }
+}
+
+template <int LA, int LB>
+static void launch_nuclear_wave(const NuclearArgs &a, bool cart, hipStream_t s)
+{
+    constexpr int NWV = NucWaveLds<LA, LB>::WAVES;
+    const int nblk = (a.npair + NWV - 1) / NWV;
+    if (cart) hipLaunchKernelGGL((nuclear_wave_kernel<LA, LB, true>), dim3(nblk), dim3(64 * NWV), 0, s, a);
+    else hipLaunchKernelGGL((nuclear_wave_kernel<LA, LB, false>), dim3(nblk), dim3(64 * NWV), 0, s, a);
+}
+
 template <int LA, int LB, int PART>
 static void launch_onebody_part(const OneBodyArgs &a, bool cart, hipStream_t s)
 {
@@ -880,6 +1198,33 @@ static mdx_status prof_open(mdx_ctx *c, hipStream_t s, hipEvent_t *ev1)
     default: LAUNCH<6, 0>(__VA_ARGS__); break; \
     }
 
+// one case per (l_a, l_b) with l_a + l_b >= 7, l <= 6 (the one-pair-per-wave
+// 1-particle Coulomb kernel)
+#define MDX_NUCLEAR_WAVE_SWITCH(LAUNCH, la, lb, ...)    \
+    switch ((la) * 7 + (lb)) {                           \
+    case 13: LAUNCH<1, 6>(__VA_ARGS__); break; \
+    case 19: LAUNCH<2, 5>(__VA_ARGS__); break; \
+    case 20: LAUNCH<2, 6>(__VA_ARGS__); break; \
+    case 25: LAUNCH<3, 4>(__VA_ARGS__); break; \
+    case 26: LAUNCH<3, 5>(__VA_ARGS__); break; \
+    case 27: LAUNCH<3, 6>(__VA_ARGS__); break; \
+    case 31: LAUNCH<4, 3>(__VA_ARGS__); break; \
+    case 32: LAUNCH<4, 4>(__VA_ARGS__); break; \
+    case 33: LAUNCH<4, 5>(__VA_ARGS__); break; \
+    case 34: LAUNCH<4, 6>(__VA_ARGS__); break; \
+    case 37: LAUNCH<5, 2>(__VA_ARGS__); break; \
+    case 38: LAUNCH<5, 3>(__VA_ARGS__); break; \
+    case 39: LAUNCH<5, 4>(__VA_ARGS__); break; \
+    case 40: LAUNCH<5, 5>(__VA_ARGS__); break; \
+    case 41: LAUNCH<5, 6>(__VA_ARGS__); break; \
+    case 43: LAUNCH<6, 1>(__VA_ARGS__); break; \
+    case 44: LAUNCH<6, 2>(__VA_ARGS__); break; \
+    case 45: LAUNCH<6, 3>(__VA_ARGS__); break; \
+    case 46: LAUNCH<6, 4>(__VA_ARGS__); break; \
+    case 47: LAUNCH<6, 5>(__VA_ARGS__); break; \
+    default: LAUNCH<6, 6>(__VA_ARGS__); break; \
+    }
+
 #define MDX_ONEBODY_SWITCH7(LAUNCH, la, lb, ...)         \
     switch ((la) * 7 + (lb)) {                           \
     case 0: LAUNCH<0, 0>(__VA_ARGS__); break; \
@@ -975,7 +1320,11 @@ mdx_status nuclear_lane_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *
     a.Ca = c->solid + c->solid_off[la];
     a.Cb = c->solid + c->solid_off[lb];
     a.V = V;
-    MDX_NUCLEAR_LANE_SWITCH(launch_nuclear, la, lb, a, cart, s)
+    if (la + lb <= 6) {
+        MDX_NUCLEAR_LANE_SWITCH(launch_nuclear, la, lb, a, cart, s)
+    } else {
+        MDX_NUCLEAR_WAVE_SWITCH(launch_nuclear_wave, la, lb, a, cart, s)
+    }
     HIP_TRY2(hipGetLastError());
     if (ev1) HIP_TRY2(hipEventRecord(ev1, s));
     return MDX_OK;
@@ -1005,13 +1354,6 @@ extern "C" size_t mdx_nuclear_workspace_size(mdx_ctx *c, const mdx_shells *sh, i
         fail(MDX_EINVAL, "negative charge count");
         return 0;
     }
-    if (npair > 0 && nuclear_on_mfma(l[0], l[1])) {
-        size_t bytes = 0;
-        if (nuclear_mfma_workspace(c, sh, npair, pairs, l[0], l[1], ncharge, (flags & MDX_CARTESIAN) != 0, bytes) !=
-            MDX_OK)
-            return 0;
-        return bytes + 256;
-    }
     return al256((size_t)npair * sizeof(PairRec)) + 256;
 }
 
@@ -1026,9 +1368,6 @@ extern "C" mdx_status mdx_nuclear_batch(mdx_ctx *c, const mdx_shells *sh, int32_
     if (ncharge > 0 && !charges) return fail(MDX_EINVAL, "null charge array");
     if (npair == 0) return MDX_OK;
     hipStream_t s = (hipStream_t)stream;
-    if (nuclear_on_mfma(l[0], l[1]))   // plans first (unsupported classes), then checks the buffers
-        return nuclear_mfma_enqueue(c, sh, npair, pairs, l[0], l[1], ncharge, charges, (flags & MDX_CARTESIAN) != 0, V,
-                                    ws, ws_bytes, s);
     if (!V) return fail(MDX_EINVAL, "mdx_nuclear_batch: null output");
     MDX_TRY(stage_pairs(c, sh, npair, pairs, ws, ws_bytes, s, "mdx_nuclear_batch"));
     return nuclear_lane_launch(c, sh, (const PairRec *)ws, npair, l[0], l[1], (flags & MDX_CARTESIAN) != 0, ncharge,
@@ -1082,22 +1421,14 @@ extern "C" mdx_status mdx_nuclear_prepare(mdx_ctx *c, const mdx_shells *sh, int3
     MDX_TRY(check_pairs(c, sh, npair, pairs, flags, l));
     if (ncharge < 0) return fail(MDX_EINVAL, "negative charge count");
     const bool cart = (flags & MDX_CARTESIAN) != 0;
-    const bool mfma = npair > 0 && nuclear_on_mfma(l[0], l[1]);
     mdx_batch *b = new mdx_batch;
-    mdx_status st = batch_init(b, c, sh, mfma ? B_NUC_MFMA : B_NUC_LANE, flags);
+    mdx_status st = batch_init(b, c, sh, B_NUC, flags);
     b->la = l[0];
     b->lb = l[1];
     b->npair = npair;
     b->ncharge = ncharge;
     b->out_doubles = npair > 0 ? (int64_t)npair * nfunc(l[0], cart) * nfunc(l[1], cart) : 0;
-    if (st == MDX_OK && mfma) {
-        st = nuc_plan(c, sh, npair, pairs, l[0], l[1], ncharge, cart, b->np);
-        if (st == MDX_OK) {
-            b->ws_need = b->np.work;
-            st = batch_tables(b, b->np.L.tables);
-        }
-        if (st == MDX_OK) st = copy_tables(b->np.cp, b->np.L, b->dtab);
-    } else if (st == MDX_OK && npair > 0) {
+    if (st == MDX_OK && npair > 0) {
         std::vector<PairRec> pr;
         onebody_records(sh, npair, pairs, pr);
         st = batch_tables(b, pr.size() * sizeof(PairRec));
@@ -1116,13 +1447,11 @@ extern "C" mdx_status mdx_nuclear_prepare(mdx_ctx *c, const mdx_shells *sh, int3
 extern "C" mdx_status mdx_nuclear_run(const mdx_batch *b, const mdx_shells *sh, const double *charges, double *V,
                                       void *ws, size_t ws_bytes, mdx_stream_t stream)
 {
-    MDX_TRY(batch_check(b, sh, B_NUC_LANE, ws, ws_bytes, "mdx_nuclear_run"));
+    MDX_TRY(batch_check(b, sh, B_NUC, ws, ws_bytes, "mdx_nuclear_run"));
     if (b->npair == 0) return MDX_OK;
     if (b->ncharge > 0 && !charges) return fail(MDX_EINVAL, "mdx_nuclear_run: null charge array");
     if (!V) return fail(MDX_EINVAL, "mdx_nuclear_run: null output");
     hipStream_t s = (hipStream_t)stream;
-    if (b->kind == B_NUC_MFMA)
-        return nuclear_mfma_run(b->c, sh, b->np, b->dtab, (char *)ws, b->ncharge, charges, V, s);
     return nuclear_lane_launch(b->c, sh, (const PairRec *)b->dtab, b->npair, b->la, b->lb,
                                (b->flags & MDX_CARTESIAN) != 0, b->ncharge, charges, V, s);
 }

@@ -40,8 +40,7 @@ mdx_status batch_check(const mdx_batch *b, const mdx_shells *sh, int kind, const
                        const char *who)
 {
     if (!b) return fail(MDX_EINVAL, "%s: null batch", who);
-    const bool nuc = kind == B_NUC_LANE || kind == B_NUC_MFMA;
-    if (!(b->kind == kind || (nuc && (b->kind == B_NUC_LANE || b->kind == B_NUC_MFMA))))
+    if (b->kind != kind)
         return fail(MDX_EINVAL, "%s: the batch was prepared for another integral kind", who);
     if (!sh || sh->nshell != b->nshell ||
         (b->nshell > 0 && (!sh->l || !sh->nprim || !sh->prim_offset || !sh->center || !sh->exponent || !sh->coef)))

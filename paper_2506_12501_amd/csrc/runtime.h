@@ -136,27 +136,10 @@ mdx_status enqueue_class(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, 
 mdx_status enqueue_class_dev(mdx_ctx *c, const mdx_shells *sh, const ClassPlan &cp, const ClassDev &d, double *out,
                              hipStream_t s, const Digest *dig = nullptr);
 
-// 1-particle Coulomb integrals of l >= 4 as the class (ab|ss) with one ket pair
-// of point-charge primitives; the charge slices and partial sums after the
-// class's own work region
-struct NucPlan {
-    ClassPlan cp;
-    WsLayout L;
-    int nslice = 0;
-    size_t off_np = 0, off_part = 0;   // from the work region
-    size_t work = 0;                   // work region bytes (pair data, slice counts, partial sums)
-};
-bool nuclear_on_mfma(int la, int lb);
-mdx_status nuc_plan(mdx_ctx *c, const mdx_shells *sh, int32_t npair, const int32_t *pairs, int la, int lb,
-                    int32_t ncharge, bool cart, NucPlan &np);
-// enqueues a planned batch, tables at tabs (device), work region at work
-mdx_status nuclear_mfma_run(mdx_ctx *c, const mdx_shells *sh, const NucPlan &np, const char *tabs, char *work,
-                            int32_t ncharge, const double *charges, double *V, hipStream_t s);
-
 // the lane records of a 1-particle batch (pairs validated)
 void onebody_records(const mdx_shells *sh, int32_t npair, const int32_t *pairs, std::vector<PairRec> &pr);
 // one launch of the overlap/kinetic or nuclear kernels of class (la, lb) over
-// resident lane records (nuclear: l_a, l_b <= 3)
+// resident lane records
 mdx_status onebody_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *pairs, int32_t npair, int la, int lb,
                           bool cart, double *S, double *T, hipStream_t s);
 mdx_status nuclear_lane_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *pairs, int32_t npair, int la,
@@ -167,7 +150,7 @@ mdx_status nuclear_lane_launch(mdx_ctx *c, const mdx_shells *sh, const PairRec *
 // A prepared batch (mdx_eri_prepare, mdx_one_body_prepare, mdx_nuclear_prepare):
 // the host planning of one call done once, its index tables resident in
 // device memory of its own, so that a run enqueues kernels only.
-enum BatchKind { B_ERI = 1, B_ONEBODY = 2, B_NUC_LANE = 3, B_NUC_MFMA = 4 };
+enum BatchKind { B_ERI = 1, B_ONEBODY = 2, B_NUC = 3 };
 
 struct mdx_batch {
     mdx_ctx *c = nullptr;
@@ -180,7 +163,6 @@ struct mdx_batch {
     int64_t out_doubles = 0;                 // doubles per output array
     mdx::ClassPlan cp;                       // B_ERI
     mdx::WsLayout L{};
-    mdx::NucPlan np;                         // B_NUC_MFMA
     int la = -1, lb = -1;                    // 1-particle classes
     int32_t npair = 0, ncharge = 0;
     ~mdx_batch()

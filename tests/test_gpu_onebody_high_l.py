@@ -3,8 +3,7 @@ Table 2 beyond f), GPU vs the __float128 oracle (the fp64 oracle's solid
 transform of an l = 6 shell loses up to ~1e-11 of the block maximum), through
 the C-ABI entry points: overlap and kinetic energy on the one-pair-per-wave
 kernel; nuclear attraction on the lane kernel for l_a + l_b <= 6 and, beyond,
-on the matrix-core kernel with the charges as point-like ket primitives
-(Eq. (37) as the early contraction over them)."""
+on the one-pair-per-wave kernel (lanes over Hermite columns)."""
 import numpy as np
 import pytest
 
@@ -87,8 +86,7 @@ def test_nuclear_cartesian(la, lb):
 
 
 def test_nuclear_many_charges_in_slices():
-    """more than 64 charges on the matrix-core kernel: it runs in slices whose
-    partial results are added (150 charges: three slices, the last one partial)"""
+    """150 charges on the one-pair-per-wave kernel (l_a + l_b >= 7)"""
     basis, pairs = pair_batch(4, 3, 3, 1, seed=5)
     got, ref = _nuclear(basis, pairs, _charges(basis, pairs, 147, seed=6), False)
     assert_close(got, ref, "V (g|f) 150 charges")
@@ -103,14 +101,12 @@ def test_nuclear_no_charges_gives_zero():
     assert bool(torch.all(V == 0.0))
 
 
-def test_cartesian_beyond_225_functions_is_refused():
-    import torch
-    from paper_2506_12501_amd import native
-    basis, pairs = pair_batch(6, 5, 2, 1, seed=1)
-    sh = native.DeviceShells(basis)
-    with pytest.raises(native.MdxError) as e:
-        native.nuclear(sh, pairs, torch.as_tensor(W.point_charges(3, 6.0, seed=1), device="cuda"), cartesian=True)
-    assert e.value.status == native.MDX_EUNSUPPORTED
+@pytest.mark.parametrize("la,lb", [(6, 5), (6, 6)])
+def test_nuclear_cartesian_largest(la, lb):
+    """the largest Cartesian classes (588 and 784 functions per pair)"""
+    basis, pairs = pair_batch(la, lb, 3, 2, seed=95 + la + lb)
+    got, ref = _nuclear(basis, pairs, _charges(basis, pairs, 5, seed=la * lb), True)
+    assert_close(got, ref, f"V ({la}|{lb}) Cartesian")
 
 
 def test_l7_is_refused():

@@ -135,8 +135,8 @@ def test_one_body_run_captured_in_graph(la, lb):
 
 @pytest.mark.parametrize("la,lb", [(2, 1), (4, 2), (4, 3)])
 def test_nuclear_run_captured_in_graph(la, lb):
-    """(d|p), (g|d): the lane kernel; (g|f): the matrix-core path with the
-    charges as point-limit ket primitives (the charges are read at replay time)"""
+    """(d|p), (g|d): the lane kernel; (g|f): the one-pair-per-wave kernel (the
+    charges are read at replay time)"""
     import torch
     native = _native()
     basis, pairs = W.one_body_pairs(la, lb, 9, 7, 2, seed=la * 5 + lb)

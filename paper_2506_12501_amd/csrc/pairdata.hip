@@ -75,14 +75,15 @@ static int pd_item_elements(const SideGeom &g)
 }
 
 // Items per 256-thread workgroup: each item gets a power-of-two group of
-// threads, about one thread per two H elements (at least 16, so that the
-// three E recursions and the term tables have lanes; at most the whole
-// workgroup).  Small s/p items share a workgroup instead of idling 128 lanes.
+// threads, about one thread per four H elements (at least 4, for the three
+// E recursions; at most the whole workgroup).  Small s/p items share a
+// workgroup: a workgroup's fixed latency (record loads, recursion, barrier)
+// is paid once for up to 64 items.
 static int pd_per_block(const SideGeom &g)
 {
     const int e = pd_item_elements(g);
-    int t = 16;
-    while (t < PD_THREADS && 2 * t < e) t *= 2;
+    int t = 4;
+    while (t < PD_THREADS && 4 * t < e) t *= 2;
     return PD_THREADS / t;
 }
 

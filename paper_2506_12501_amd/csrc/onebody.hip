@@ -716,22 +716,21 @@ static void launch_nuclear(const NuclearArgs &a, bool cart, hipStream_t s)
 
 // ---------------------------------------------------------------------------
 // 1-particle Coulomb integrals of the classes with l_a + l_b >= 7: one shell
-// pair per wave, lanes over the Hermite columns (u, v) of order L.
+// pair per wave.
 //
 // The charge-summed table of one primitive pair, sum_I [tuv]_I^(0), has
 // N_H(L) values (455 at L = 12), too many for one lane, so the lanes share
-// it: lane c owns column (u_c, v_c) and accumulates its L - u_c - v_c + 1
-// entries over the charges.  A column needs no other lane's values: the
-// recursion of Eq. (31) has the closed form
+// it: lane c owns column (u_c, v_c), the L - u_c - v_c + 1 entries with
+// those u, v.  The charges go through the wave 64 at a time, one per lane;
+// a lane forms every column of its charge from the closed form of the
+// recursion of Eq. (31),
 //   [tuv]^(0) = sum_{i,j,k} h_{t,i} h_{u,j} h_{v,k} X^{t-2i} Y^{u-2j} Z^{v-2k} S_{t+u+v-i-j-k},
 //   h_{t,i} = t! / (i! (t-2i)! 2^i),  S_n = [000]^(n) (Eq. (30) times the charge),
-// (the derivative d/dX of [000]^(n) is X [000]^(n+1)), which a lane takes as
-//   D_d = sum_{j+k=d} h_{u,j} Y^{u-2j} h_{v,k} Z^{v-2k},   W_n = sum_d D_d S_{n+u+v-d},
-//   [tuv] = sum_i h_{t,i} X^{t-2i} W_{t-i}.
-// The S_n of a charge reach every lane through a small LDS buffer (each lane
-// reads them at its own offset u + v).  After the charges, the transform of
-// Eq. (34) runs in the factored order of the lane kernel, through the wave's
-// LDS table: monomials at P along x (in each lane's column), y and z (lanes
+// (the derivative d/dX of [000]^(n) is X [000]^(n+1)), column by column with
+// compile-time indices, and each entry is summed over the lanes (charges)
+// into its column's owner.  After the charges, the transform of Eq. (34)
+// runs in the factored order of the lane kernel, through the wave's LDS
+// table: monomials at P along x (in each lane's column), y and z (lanes
 // over lines), then the binomial shifts to A and B with lanes over the
 // Cartesian function pairs.  Waves synchronise only within themselves (the
 // pairs of a workgroup have different primitive counts).
@@ -767,24 +766,84 @@ struct NucCoefTab {
     }
 };
 
-// per-wave LDS (doubles): two S buffers, then a region that holds the
-// Hermite/monomial table and the two shift tables [axis][i][k] during the
-// primitive loop, and the Cartesian block and [NA][2 l_b + 1] for the
-// solid transform after it
+// per-wave LDS (doubles): the Hermite/monomial table and the two shift
+// tables [axis][i][k] during the primitive loop, the Cartesian block and
+// [NA][2 l_b + 1] for the solid transform after it
 template <int LA, int LB>
 struct NucWaveLds {
-    static constexpr int L = LA + LB, H2 = L / 2;
-    static constexpr int SB = 2 * L + H2 + 1;
+    static constexpr int L = LA + LB;
     static constexpr int NH = nherm(L), NG = 3 * 7 * 7;
     static constexpr int NA = ncart(LA), NB = ncart(LB), NF = NA * NB;
     static constexpr int RA = NH + 2 * NG > NF + NA * (2 * LB + 1) ? NH + 2 * NG : NF + NA * (2 * LB + 1);
-    static constexpr int OFF_S = 0, OFF_M = 2 * SB, OFF_GA = OFF_M + NH, OFF_GB = OFF_GA + NG, OFF_V = OFF_M;
-    static constexpr int SIZE = 2 * SB + RA;
+    static constexpr int OFF_M = 0, OFF_GA = OFF_M + NH, OFF_GB = OFF_GA + NG, OFF_V = OFF_M;
+    static constexpr int SIZE = RA;
     // pairs (waves) per workgroup: as many as 64 KB of static LDS hold next to the Boys rows
     static constexpr int ROWS_BYTES = BOYS_NROW * BOYS_NTERM * 8;
     static constexpr int WAVES_FIT = (65536 - ROWS_BYTES) / (SIZE * 8);
     static constexpr int WAVES = WAVES_FIT >= 4 ? 4 : (WAVES_FIT < 1 ? 1 : WAVES_FIT);
 };
+
+// sum over the wave's lanes; every lane gets the total
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// column C = q (q + 1) / 2 + v of the order-L table (u = q - v): each lane
+// forms its own charge's [t u v] for t <= L - u - v from the closed form
+//   D_d = sum_{j+k=d} h_{u,j} h_{v,k} Y^{u-2j} Z^{v-2k},  W_n = sum_d D_d S_{n+u+v-d},
+//   [tuv] = sum_i h_{t,i} X^{t-2i} W_{t-i},
+// the wave sums them over its charges, and the lane owning the column
+// (lane C mod 64, slot C / 64) adds the sums to its table
+__host__ __device__ constexpr int col_level(int c)
+{
+    int q = 0;
+    while ((q + 1) * (q + 2) / 2 <= c) ++q;
+    return q;
+}
+
+template <int L, int NCS, int C>
+__device__ __forceinline__ void nuc_column(const double (&S)[L + 1], const double (&Xp)[L + 1],
+                                           const double (&Yp)[L + 1], const double (&Zp)[L + 1],
+                                           double (&Rs)[NCS][L + 1], int lane)
+{
+    constexpr int q = col_level(C), v = C - q * (q + 1) / 2, u = q - v, n = L - q;
+    constexpr int DM = u / 2 + v / 2;
+    constexpr NucCoefTab<L> ct{};
+    double D[DM + 1];
+#pragma unroll
+    for (int d = 0; d <= DM; ++d) D[d] = 0.0;
+#pragma unroll
+    for (int j = 0; 2 * j <= u; ++j)
+#pragma unroll
+        for (int k = 0; 2 * k <= v; ++k) D[j + k] = fma(ct.h[u][j] * ct.h[v][k] * Yp[u - 2 * j], Zp[v - 2 * k], D[j + k]);
+    double W[n + 1];
+#pragma unroll
+    for (int m = 0; m <= n; ++m) {
+        double x = 0.0;
+#pragma unroll
+        for (int d = 0; d <= DM; ++d) x = fma(D[d], S[m + q - d], x);
+        W[m] = x;
+    }
+#pragma unroll
+    for (int t = 0; t <= n; ++t) {
+        double x = 0.0;
+#pragma unroll
+        for (int i = 0; 2 * i <= t; ++i) x = fma(ct.h[t][i] * Xp[t - 2 * i], W[t - i], x);
+        x = wave_sum(x);
+        if (lane == C % 64) Rs[C / 64][t] += x;
+    }
+}
+
+template <int L, int NCS, int... Cs>
+__device__ __forceinline__ void nuc_columns(const double (&S)[L + 1], const double (&Xp)[L + 1],
+                                            const double (&Yp)[L + 1], const double (&Zp)[L + 1],
+                                            double (&Rs)[NCS][L + 1], int lane, std::integer_sequence<int, Cs...>)
+{
+    (nuc_column<L, NCS, Cs>(S, Xp, Yp, Zp, Rs, lane), ...);
+}
 
 template <int LA, int LB, bool CART>
 __global__ void __launch_bounds__((64 * NucWaveLds<LA, LB>::WAVES))
@@ -807,13 +866,11 @@ __attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(N
 
     const int ij = blockIdx.x * NWV + w;
     if (ij >= a.npair) return;
-    double *sbuf = wlds[w] + LY::OFF_S, *mt = wlds[w] + LY::OFF_M, *ga = wlds[w] + LY::OFF_GA,
-           *gb = wlds[w] + LY::OFF_GB, *vb = wlds[w] + LY::OFF_V;   // vb: after the primitive loop
-    for (int i = lane; i < 2 * LY::SB; i += 64) sbuf[i] = 0.0;
+    double *mt = wlds[w] + LY::OFF_M, *ga = wlds[w] + LY::OFF_GA, *gb = wlds[w] + LY::OFF_GB,
+           *vb = wlds[w] + LY::OFF_V;   // vb: after the primitive loop
 
     // the lane's columns: c = lane + 64 s -> (u, v), u + v = q, c = q (q + 1) / 2 + v
     int cu[NCS], cv[NCS], cn[NCS];
-    double hy[NCS][H2 + 1], hz[NCS][H2 + 1];
 #pragma unroll
     for (int s = 0; s < NCS; ++s) {
         const int c = lane + 64 * s;
@@ -822,11 +879,6 @@ __attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(N
         cv[s] = c - q * (q + 1) / 2;
         cu[s] = q - cv[s];
         cn[s] = c < NCOL ? L - q : -1;
-#pragma unroll
-        for (int j = 0; j <= H2; ++j) {
-            hy[s][j] = 2 * j <= cu[s] ? herm_poly_coef(cu[s], j) : 0.0;
-            hz[s][j] = 2 * j <= cv[s] ? herm_poly_coef(cv[s], j) : 0.0;
-        }
     }
     double V[NVS];
 #pragma unroll
@@ -836,7 +888,6 @@ __attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(N
     const double A[3] = {a.center[3 * pr.sa], a.center[3 * pr.sa + 1], a.center[3 * pr.sa + 2]};
     const double B[3] = {a.center[3 * pr.sb], a.center[3 * pr.sb + 1], a.center[3 * pr.sb + 2]};
     const double AB2 = (A[0] - B[0]) * (A[0] - B[0]) + (A[1] - B[1]) * (A[1] - B[1]) + (A[2] - B[2]) * (A[2] - B[2]);
-    int parity = 0;
     for (int ka = 0; ka < pr.ka; ++ka) {
         const double za = a.expo[pr.offa + ka], ca = a.coef[pr.offa + ka];
         for (int kb = 0; kb < pr.kb; ++kb) {
@@ -850,68 +901,28 @@ __attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(N
 #pragma unroll
                 for (int t = 0; t <= L; ++t) Rs[s][t] = 0.0;
             const double g = 2.0 * M_PI * rp, m2p = -2.0 * p;
-            for (int I = 0; I < a.ncharge; ++I) {
-                const double *ch = a.charges + 4 * I;
+            // the charges 64 at a time, one per lane
+            for (int I0 = 0; I0 < a.ncharge; I0 += 64) {
+                const bool live = I0 + lane < a.ncharge;
+                const double *ch = a.charges + 4 * (live ? I0 + lane : 0);
                 const double X = P[0] - ch[0], Y = P[1] - ch[1], Z = P[2] - ch[2];
-                double *sb = sbuf + parity * LY::SB;
-                parity ^= 1;
-                {
-                    double F[L + 1];
-                    boys_eval_rows<L>(p * (X * X + Y * Y + Z * Z), F, rows);
-                    double f = ch[3] * g;
-                    if (lane == 0) {
+                double F[L + 1], S[L + 1];
+                boys_eval_rows<L>(p * (X * X + Y * Y + Z * Z), F, rows);
+                double f = live ? ch[3] * g : 0.0;
 #pragma unroll
-                        for (int m = 0; m <= L; ++m) {
-                            sb[H2 + m] = f * F[m];
-                            f *= m2p;
-                        }
-                    }
+                for (int m = 0; m <= L; ++m) {
+                    S[m] = f * F[m];
+                    f *= m2p;
                 }
-                wave_lds_sync();
-                double Xp[L + 1];
-                Xp[0] = 1.0;
+                double Xp[L + 1], Yp[L + 1], Zp[L + 1];
+                Xp[0] = Yp[0] = Zp[0] = 1.0;
 #pragma unroll
-                for (int n = 1; n <= L; ++n) Xp[n] = Xp[n - 1] * X;
-                const double Y2 = Y * Y, Z2 = Z * Z;
-#pragma unroll
-                for (int s = 0; s < NCS; ++s) {
-                    if (cn[s] < 0) continue;
-                    // y and z factors h_{u,j} Y^{u-2j}, h_{v,k} Z^{v-2k}
-                    double yv[H2 + 1], zv[H2 + 1];
-                    double yp = (cu[s] & 1) ? Y : 1.0, zp = (cv[s] & 1) ? Z : 1.0;
-#pragma unroll
-                    for (int j = H2; j >= 0; --j) {
-                        yv[j] = hy[s][j] * yp;
-                        zv[j] = hz[s][j] * zp;
-                        if (2 * j <= cu[s]) yp *= Y2;
-                        if (2 * j <= cv[s]) zp *= Z2;
-                    }
-                    double D[H2 + 1];
-#pragma unroll
-                    for (int d = 0; d <= H2; ++d) {
-                        double v = 0.0;
-#pragma unroll
-                        for (int j = 0; j <= d; ++j) v = fma(yv[j], zv[d - j], v);
-                        D[d] = v;
-                    }
-                    // S_{n + u + v - d} = sb[H2 + n + u + v - d] = Sh[H2 + n - d]
-                    const double *Sh = sb + cu[s] + cv[s];
-                    double W[L + 1];
-#pragma unroll
-                    for (int n = 0; n <= L; ++n) {
-                        double v = 0.0;
-#pragma unroll
-                        for (int d = 0; d <= H2; ++d) v = fma(D[d], Sh[H2 + n - d], v);
-                        W[n] = v;
-                    }
-#pragma unroll
-                    for (int t = 0; t <= L; ++t) {
-                        double v = Rs[s][t];
-#pragma unroll
-                        for (int i = 0; 2 * i <= t; ++i) v = fma(ct.h[t][i] * Xp[t - 2 * i], W[t - i], v);
-                        Rs[s][t] = v;
-                    }
+                for (int n = 1; n <= L; ++n) {
+                    Xp[n] = Xp[n - 1] * X;
+                    Yp[n] = Yp[n - 1] * Y;
+                    Zp[n] = Zp[n - 1] * Z;
                 }
+                nuc_columns<L, NCS>(S, Xp, Yp, Zp, Rs, lane, std::make_integer_sequence<int, NCOL>{});
             }
             // Eq. (34), factored: monomials at P along x in each lane's column
             const double h = 0.5 * rp;

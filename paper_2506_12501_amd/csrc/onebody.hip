@@ -729,11 +729,14 @@ static void launch_nuclear(const NuclearArgs &a, bool cart, hipStream_t s)
 // (the derivative d/dX of [000]^(n) is X [000]^(n+1)), column by column with
 // compile-time indices, and each entry is summed over the lanes (charges)
 // into its column's owner.  After the charges, the transform of Eq. (34)
-// runs in the factored order of the lane kernel, through the wave's LDS
-// table: monomials at P along x (in each lane's column), y and z (lanes
-// over lines), then the binomial shifts to A and B with lanes over the
-// Cartesian function pairs.  Waves synchronise only within themselves (the
-// pairs of a workgroup have different primitive counts).
+// runs through the wave's LDS table: monomials at P along x (in each lane's
+// column), y and z (lanes over lines), then both binomial shifts at once as
+// per-axis products G[i][j][e] (the coefficient of x_P^e in x_A^i x_B^j),
+// V_ab = sum_e G_x G_y G_z M_e, with lanes over the Cartesian function pairs
+// and loops of compile-time bounds over the whole table (G's zeros drop the
+// terms beyond a + b; per-lane bounds would make a wave run the product of
+// the lanes' maxima).  Waves synchronise only within themselves (the pairs
+// of a workgroup have different primitive counts).
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ void wave_lds_sync()
 {
@@ -766,20 +769,20 @@ struct NucCoefTab {
     }
 };
 
-// per-wave LDS (doubles): the Hermite/monomial table and the two shift
-// tables [axis][i][k] during the primitive loop, the Cartesian block and
-// [NA][2 l_b + 1] for the solid transform after it
+// per-wave LDS (doubles): the Hermite/monomial table, the per-axis shift
+// products G[3][l_a+1][l_b+1][L+1] and the powers [2][3][7] during the
+// primitive loop; the Cartesian block and [NA][2 l_b + 1] for the solid
+// transform after it
 template <int LA, int LB>
 struct NucWaveLds {
     static constexpr int L = LA + LB;
-    static constexpr int NH = nherm(L), NG = 3 * 7 * 7;
+    static constexpr int NH = nherm(L), NGD = 3 * (LA + 1) * (LB + 1) * (L + 1), NPW = 2 * 3 * 7;
     static constexpr int NA = ncart(LA), NB = ncart(LB), NF = NA * NB;
-    static constexpr int RA = NH + 2 * NG > NF + NA * (2 * LB + 1) ? NH + 2 * NG : NF + NA * (2 * LB + 1);
-    static constexpr int OFF_M = 0, OFF_GA = OFF_M + NH, OFF_GB = OFF_GA + NG, OFF_V = OFF_M;
+    static constexpr int RA = NH + NGD + NPW > NF + NA * (2 * LB + 1) ? NH + NGD + NPW : NF + NA * (2 * LB + 1);
+    static constexpr int OFF_M = 0, OFF_G = NH, OFF_PW = NH + NGD, OFF_V = 0;
     static constexpr int SIZE = RA;
-    // pairs (waves) per workgroup: as many as 64 KB of static LDS hold next to the Boys rows
-    static constexpr int ROWS_BYTES = BOYS_NROW * BOYS_NTERM * 8;
-    static constexpr int WAVES_FIT = (65536 - ROWS_BYTES) / (SIZE * 8);
+    // pairs (waves) per workgroup: as many as 64 KB of static LDS hold
+    static constexpr int WAVES_FIT = 65536 / (SIZE * 8);
     static constexpr int WAVES = WAVES_FIT >= 4 ? 4 : (WAVES_FIT < 1 ? 1 : WAVES_FIT);
 };
 
@@ -847,26 +850,21 @@ __device__ __forceinline__ void nuc_columns(const double (&S)[L + 1], const doub
 
 template <int LA, int LB, bool CART>
 __global__ void __launch_bounds__((64 * NucWaveLds<LA, LB>::WAVES))
-__attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(NuclearArgs a)
+__attribute__((amdgpu_waves_per_eu(2))) nuclear_wave_kernel(NuclearArgs a)
 {
     constexpr int L = LA + LB, H2 = L / 2, NA = ncart(LA), NB = ncart(LB), NF = NA * NB;
     constexpr int NCOL = (L + 1) * (L + 2) / 2;   // columns (u, v), also the lines of the y and z stages
     constexpr int NCS = (NCOL + 63) / 64, NVS = (NF + 63) / 64;
-    constexpr int NROWT = BOYS_NROW * BOYS_NTERM;
     using LY = NucWaveLds<LA, LB>;
     constexpr int NWV = LY::WAVES;
     constexpr NucCoefTab<L> ct{};
     static_assert(LY::WAVES_FIT >= 1, "per-wave LDS too large");
-    __shared__ double rows[NROWT];
-    __shared__ double wlds[NWV][LY::SIZE];
+    __shared__ double wlds[NWV][LY::SIZE];   // the waves run independently: no workgroup barrier
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < NROWT; i += 64 * NWV)
-        rows[i] = a.boys[(i / BOYS_NTERM) * BOYS_NCOL + L + i % BOYS_NTERM];
-    __syncthreads();   // the only workgroup barrier: the waves below run independently
 
     const int ij = blockIdx.x * NWV + w;
     if (ij >= a.npair) return;
-    double *mt = wlds[w] + LY::OFF_M, *ga = wlds[w] + LY::OFF_GA, *gb = wlds[w] + LY::OFF_GB,
+    double *mt = wlds[w] + LY::OFF_M, *gt = wlds[w] + LY::OFF_G, *pw = wlds[w] + LY::OFF_PW,
            *vb = wlds[w] + LY::OFF_V;   // vb: after the primitive loop
 
     // the lane's columns: c = lane + 64 s -> (u, v), u + v = q, c = q (q + 1) / 2 + v
@@ -907,7 +905,7 @@ __attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(N
                 const double *ch = a.charges + 4 * (live ? I0 + lane : 0);
                 const double X = P[0] - ch[0], Y = P[1] - ch[1], Z = P[2] - ch[2];
                 double F[L + 1], S[L + 1];
-                boys_eval_rows<L>(p * (X * X + Y * Y + Z * Z), F, rows);
+                boys_eval<L>(p * (X * X + Y * Y + Z * Z), F, a.boys);
                 double f = live ? ch[3] * g : 0.0;
 #pragma unroll
                 for (int m = 0; m <= L; ++m) {
@@ -941,16 +939,15 @@ __attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(N
                     if (e <= cn[s]) mt[herm_index(e, cu[s], cv[s])] = v;
                 }
             }
-            // the binomial shift tables of this primitive pair, [axis][i][k] = C(i,k) (P - centre)^(i-k)
-            for (int e = lane; e < 2 * 3 * 7 * 7; e += 64) {
-                const int side = e / (3 * 7 * 7), ax = (e / 49) % 3, i = (e / 7) % 7, k = e % 7;
+            // powers (P - centre)^n of this primitive pair, [side][axis][n], n <= 6
+            if (lane < 6) {
+                const int side = lane / 3, ax = lane % 3;
                 const double d = side == 0 ? P[ax] - A[ax] : P[ax] - B[ax];
-                double v = 0.0;
-                if (k <= i) {
-                    v = (double)binom(i, k);
-                    for (int n = 0; n < i - k; ++n) v *= d;
+                double v = 1.0;
+                for (int n = 0; n < 7; ++n) {
+                    pw[(side * 3 + ax) * 7 + n] = v;
+                    v *= d;
                 }
-                (side == 0 ? ga : gb)[e % (3 * 7 * 7)] = v;
             }
             wave_lds_sync();
             // y stage (lines (e_x, v) along u), then z stage (lines (e_x, e_y) along v)
@@ -974,37 +971,51 @@ __attribute__((amdgpu_waves_per_eu(LA + LB <= 9 ? 3 : 2))) nuclear_wave_kernel(N
                 }
                 wave_lds_sync();
             }
-            // shifts: V_ab += f sum_{k<=a, k'<=b} C(a,k) C(b,k') (P-A)^{a-k} (P-B)^{b-k'} M_{k+k'}
+            // per-axis products of the two shifts,
+            //   G[ax][i][j][e] = sum_{k+k'=e} C(i,k) C(j,k') (P-A)_ax^{i-k} (P-B)_ax^{j-k'}
+            // (zero for e > i + j), so that V_ab = f sum_e G_x G_y G_z M_e
+            for (int e = lane; e < LY::NGD; e += 64) {
+                const int ax = e / ((LA + 1) * (LB + 1) * (L + 1)), i = (e / ((LB + 1) * (L + 1))) % (LA + 1),
+                          j = (e / (L + 1)) % (LB + 1), q = e % (L + 1);
+                double v = 0.0;
+                for (int k = q - j > 0 ? q - j : 0; k <= i && k <= q; ++k)
+                    v = fma((double)(binom(i, k) * binom(j, q - k)) * pw[ax * 7 + i - k], pw[(3 + ax) * 7 + j - q + k], v);
+                gt[e] = v;
+            }
+            wave_lds_sync();
+            // the contraction, lanes over Cartesian function pairs, uniform loops
+            // over the whole monomial table (G's zeros drop the terms beyond a + b)
             const double f = -ca * cb * exp(-za * zb * rp * AB2);
-#pragma unroll
+#pragma unroll 1
             for (int s = 0; s < NVS; ++s) {
-                const int fp = lane + 64 * s;
-                if (fp >= NF) continue;
+                // keeps the table's loads inside the loop (hoisted, hundreds of them stayed live and spilled)
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int fp = lane + 64 * s < NF ? lane + 64 * s : 0;
                 const int ia = fp / NB, ib = fp % NB;
-                const int ax = cart_exp(LA, ia, 0), ay = cart_exp(LA, ia, 1), az = cart_exp(LA, ia, 2);
-                const int bx = cart_exp(LB, ib, 0), by = cart_exp(LB, ib, 1), bz = cart_exp(LB, ib, 2);
-                double sum = 0.0;
-                for (int kx = 0; kx <= ax; ++kx) {
-                    const double cx = ga[(0 * 7 + ax) * 7 + kx];
-                    for (int ky = 0; ky <= ay; ++ky) {
-                        const double cxy = cx * ga[(1 * 7 + ay) * 7 + ky];
-                        for (int kz = 0; kz <= az; ++kz) {
-                            const double cxyz = cxy * ga[(2 * 7 + az) * 7 + kz];
-                            double t = 0.0;
-                            for (int qx = 0; qx <= bx; ++qx) {
-                                const double dx = gb[(0 * 7 + bx) * 7 + qx];
-                                for (int qy = 0; qy <= by; ++qy) {
-                                    const double dxy = dx * gb[(1 * 7 + by) * 7 + qy];
-                                    for (int qz = 0; qz <= bz; ++qz)
-                                        t = fma(dxy * gb[(2 * 7 + bz) * 7 + qz],
-                                                mt[herm_index(kx + qx, ky + qy, kz + qz)], t);
-                                }
-                            }
-                            sum = fma(cxyz, t, sum);
-                        }
+                const int gi[3] = {cart_exp(LA, ia, 0), cart_exp(LA, ia, 1), cart_exp(LA, ia, 2)};
+                const int gj[3] = {cart_exp(LB, ib, 0), cart_exp(LB, ib, 1), cart_exp(LB, ib, 2)};
+                const double *gxp = gt + ((0 * (LA + 1) + gi[0]) * (LB + 1) + gj[0]) * (L + 1);
+                const double *gyp = gt + ((1 * (LA + 1) + gi[1]) * (LB + 1) + gj[1]) * (L + 1);
+                const double *gzp = gt + ((2 * (LA + 1) + gi[2]) * (LB + 1) + gj[2]) * (L + 1);
+                double gz[L + 1];
+#pragma unroll
+                for (int e = 0; e <= L; ++e) gz[e] = gzp[e];
+                double acc = 0.0;
+#pragma unroll
+                for (int ex = 0; ex <= L; ++ex) {
+                    double sx = 0.0;
+#pragma unroll
+                    for (int ey = 0; ex + ey <= L; ++ey) {
+                        double sy = 0.0;
+#pragma unroll
+                        for (int ez = 0; ex + ey + ez <= L; ++ez) sy = fma(gz[ez], mt[herm_index(ex, ey, ez)], sy);
+                        sx = fma(gyp[ey], sy, sx);
                     }
+                    acc = fma(gxp[ex], sx, acc);
                 }
-                V[s] = fma(f, sum, V[s]);
+#pragma unroll
+                for (int s2 = 0; s2 < NVS; ++s2)
+                    if (s2 == s) V[s2] = fma(f, acc, V[s2]);
             }
             wave_lds_sync();   // the table and shift tables are rewritten by the next primitive pair
         }

@@ -189,18 +189,17 @@ __global__ void __launch_bounds__(64) onebody_kernel(OneBodyArgs a)
 }
 
 // Overlap and kinetic energy of shells beyond the lane kernels (l <= 6): one
-// shell pair per wave.  Per primitive pair the lanes build the E tables of
-// Eqs. (10)-(11) in LDS (lanes over (axis, t), one recursion step at a time),
-// reduce them to the 1-D overlap and kinetic factors, and then every lane
-// accumulates its share of the Cartesian function pairs.  The solid transform
-// of Eq. (18) runs through LDS, ket index first.
+// shell pair per wave.  Per primitive pair three lanes (one per axis) run the
+// t = 0 column of Eqs. (10)-(11) in registers and write the 1-D overlap and
+// kinetic factors to LDS; after one barrier every lane accumulates its share
+// of the Cartesian function pairs.  The solid transform of Eq. (18) runs
+// through LDS, ket index first.
 template <int LA, int LB, bool CART>
 __global__ void __launch_bounds__(64) onebody_wave_kernel(OneBodyArgs a)
 {
     constexpr int NA = ncart(LA), NB = ncart(LB), NF = NA * NB, R = (NF + 63) / 64;
-    constexpr int JB = LB + 3, TT = LA + LB + 3;   // kinetic needs j + 2
+    constexpr int JB = LB + 3;   // kinetic needs j + 2
     constexpr int MA = CART ? NA : 2 * LA + 1, MB = CART ? NB : 2 * LB + 1;
-    __shared__ double E[3][LA + 1][JB][TT];
     __shared__ double s1[3][LA + 1][LB + 1], t1[3][LA + 1][LB + 1];
     __shared__ double X[NF];
     __shared__ double U[NA * MB];
@@ -222,35 +221,42 @@ __global__ void __launch_bounds__(64) onebody_wave_kernel(OneBodyArgs a)
     double S[R], T[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) S[r] = T[r] = 0.0;
-    const int ax = lane / 16, t = lane % 16;   // recursion lane: axis ax, Hermite index t
     for (int ka = 0; ka < pr.ka; ++ka) {
         const double za = a.expo[pr.offa + ka], ca = a.coef[pr.offa + ka];
         for (int kb = 0; kb < pr.kb; ++kb) {
             const double zb = a.expo[pr.offb + kb], cb = a.coef[pr.offb + kb];
             const double p = za + zb, i2p = 0.5 / p;
-            // X_PA, X_PB from centre differences: exactly 0 on one centre
-            const double XPA = ax < 3 ? zb / p * (B[ax] - A[ax]) : 0.0, XPB = ax < 3 ? za / p * (A[ax] - B[ax]) : 0.0;
             __syncthreads();   // the previous primitive pair's readers are done
-            auto get = [&](int i, int j, int tt) -> double { return (tt < 0 || tt > i + j) ? 0.0 : E[ax][i][j][tt]; };
-            for (int i = 0; i <= LA; ++i) {
-                if (ax < 3 && t <= i) {
-                    E[ax][i][0][t] = i == 0 ? 1.0
-                                            : i2p * get(i - 1, 0, t - 1) + XPA * get(i - 1, 0, t) + (t + 1) * get(i - 1, 0, t + 1);
+            if (lane < 3) {
+                // lane = axis: the t = 0 column E^{ij}_0 of Eqs. (10)-(11), i <= l_a,
+                // j <= l_b + 2, in registers.  With E^{ij}_1 = (i E^{i-1,j}_0 + j E^{i,j-1}_0)/(2p)
+                // the recursion closes on t = 0:
+                //   E^{i+1,j}_0 = X_PA E^{ij}_0 + (i E^{i-1,j}_0 + j E^{i,j-1}_0)/(2p), likewise for j.
+                // X_PA, X_PB from centre differences: exactly 0 on one centre
+                const double XPA = zb / p * (B[lane] - A[lane]), XPB = za / p * (A[lane] - B[lane]);
+                double e0[LA + 1][JB];
+#pragma unroll
+                for (int i = 0; i <= LA; ++i) {
+                    if (i == 0) e0[0][0] = 1.0;
+                    else e0[i][0] = XPA * e0[i - 1][0] + (i >= 2 ? (i - 1) * i2p * e0[i - 2][0] : 0.0);
+#pragma unroll
+                    for (int j = 1; j < JB; ++j) {
+                        double v = XPB * e0[i][j - 1];
+                        if (i >= 1) v = fma(i * i2p, e0[i - 1][j - 1], v);
+                        if (j >= 2) v = fma((j - 1) * i2p, e0[i][j - 2], v);
+                        e0[i][j] = v;
+                    }
                 }
-                __syncthreads();
-                for (int j = 1; j < JB; ++j) {
-                    if (ax < 3 && t <= i + j)
-                        E[ax][i][j][t] = i2p * get(i, j - 1, t - 1) + XPB * get(i, j - 1, t) + (t + 1) * get(i, j - 1, t + 1);
-                    __syncthreads();
-                }
-            }
-            // 1-D overlap and kinetic factors (the Laplacian on the ket Gaussian)
-            for (int e = lane; e < 3 * (LA + 1) * (LB + 1); e += 64) {
-                const int x = e / ((LA + 1) * (LB + 1)), ia = (e / (LB + 1)) % (LA + 1), jb = e % (LB + 1);
-                s1[x][ia][jb] = E[x][ia][jb][0];
-                double d2 = 4.0 * zb * zb * E[x][ia][jb + 2][0] - 2.0 * zb * (2 * jb + 1) * E[x][ia][jb][0];
-                if (jb >= 2) d2 += (double)(jb * (jb - 1)) * E[x][ia][jb - 2][0];
-                t1[x][ia][jb] = -0.5 * d2;
+                // 1-D overlap and kinetic factors (the Laplacian on the ket Gaussian)
+#pragma unroll
+                for (int ia = 0; ia <= LA; ++ia)
+#pragma unroll
+                    for (int jb = 0; jb <= LB; ++jb) {
+                        s1[lane][ia][jb] = e0[ia][jb];
+                        double d2 = 4.0 * zb * zb * e0[ia][jb + 2] - 2.0 * zb * (2 * jb + 1) * e0[ia][jb];
+                        if (jb >= 2) d2 += (double)(jb * (jb - 1)) * e0[ia][jb - 2];
+                        t1[lane][ia][jb] = -0.5 * d2;
+                    }
             }
             __syncthreads();
             // c_a c_b (pi/p)^{3/2} exp(-za zb/p |A-B|^2), Eqs. (8), (14)

@@ -64,7 +64,17 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
         PrimRec B1{};
         if constexpr (!GB) B1 = bp[kb];
 
+        // one ket primitive per iteration (wave-uniform, scalar loads): the
+        // next one is fetched while this one is computed
+        constexpr bool PREF = !GK && UJ;
+        PrimRec Kn{};
+        if constexpr (PREF) Kn = load_const(kp);
         for (int kk = 0; kk < nkk; ++kk) {
+            PrimRec Kc{};
+            if constexpr (PREF) {
+                Kc = Kn;
+                Kn = load_const(kp + (kk + 1 < nkk ? kk + 1 : kk));
+            }
             double S[L + 1];
 #pragma unroll
             for (int m = 0; m <= L; ++m) S[m] = 0.0;
@@ -74,7 +84,7 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
             for (int ib = b0; ib < b1; ++ib) {
                 const PrimRec B = GB ? bp[ib] : B1;
                 for (int ik = k0; ik < k1; ++ik) {
-                    const PrimRec K = UJ ? load_const(kp + ik) : kp[ik];   // the wave's ket pair: scalar
+                    const PrimRec K = PREF ? Kc : (UJ ? load_const(kp + ik) : kp[ik]);   // the wave's ket pair: scalar
                     const double pq = B.p + K.p;
                     const double y = rsqrt_d(pq);            // 1/sqrt(p+q)
                     const double rho = B.p * K.p * (y * y);

@@ -354,13 +354,14 @@ __device__ __forceinline__ void boys_eval_rows(double x, double *__restrict__ F,
 // through LDS at the end.  Splitting the charges gives a batch of 65,536
 // pairs G waves per SIMD instead of one, at the price of G transforms per
 // primitive pair -- worth it where registers leave room for more waves
-// (measured: 4 waves up to L = 2, 2 for L = 3 and 4).  At L = 4 the kernel
+// (measured: 8 waves up to L = 1, 4 for L = 2 (8 were 20 % slower there),
+// 2 for L = 3 and 4).  At L = 4 the kernel
 // is held to 256 registers so that two waves share a SIMD ((d|d) K=5 took
 // 14 % less time than with one wave of 264 registers); L = 5, 6 keep one
 // wave of up to 512.  LT: Boys rows staged in LDS (else read from the
 // global table; LDS was faster for every class).
 template <int LA, int LB>
-constexpr int nuclear_waves() { return LA + LB <= 2 ? 4 : (LA + LB <= 4 ? 2 : 1); }
+constexpr int nuclear_waves() { return LA + LB <= 1 ? 8 : (LA + LB == 2 ? 4 : (LA + LB <= 4 ? 2 : 1)); }
 template <int LA, int LB>
 constexpr int nuclear_wpe() { return LA + LB == 4 ? 2 : 1; }
 template <int LA, int LB>

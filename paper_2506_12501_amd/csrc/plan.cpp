@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <numeric>
 #include <cstring>
 #include <map>
 #include <string>
@@ -209,8 +210,22 @@ mdx_status build_graph(mdx_plan *p, const mdx_shells *sh, double *out, char *ws,
         // fork: one persistent launch per kernel instance over the streams
         HIP_TRY2(hipEventRecord(p->ev[mdx_plan::NS], s0));
         for (int k = 1; k < mdx_plan::NS; ++k) HIP_TRY2(hipStreamWaitEvent(p->cs[k], p->ev[mdx_plan::NS], 0));
+        // launch order: the matrix-core groups first, highest total angular
+        // momentum first, then the register-kernel groups in plan order.  The
+        // matrix-core classes have few, long work items (one shellset per
+        // workgroup); launched last they run nearly alone at the end of the
+        // graph.  The register-kernel groups have many short items and end
+        // the graph with several of them draining together.
+        std::vector<int> order(p->q.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            const QueueGroup &u = p->q[x], &v = p->q[y];
+            if (u.mfma != v.mfma) return u.mfma;
+            return u.mfma && u.key.LB + u.key.LK > v.key.LB + v.key.LK;
+        });
         int rr = 0;
-        for (const QueueGroup &g : p->q) {
+        for (const int gix : order) {
+            const QueueGroup &g = p->q[gix];
             QueueArgs qa{};
             qa.desc = (const EriArgs *)(p->dtab + g.t_desc);
             qa.base = (const int32_t *)(p->dtab + g.t_base);

@@ -17,12 +17,14 @@
 
 namespace mdx {
 
-// Shellset (bra pair I, ket pair J) of the calling lane into out[ab][cd].
+// Shellset (bra pair I, ket pair J) of the calling lane into out[ab][cd],
+// for the ket functions cd = C0 .. C0 + NCS - 1 (all of them by default).
 // UJ: J is the same for the whole wave, so its ket data are scalar loads
 // (false only for paired batches, one quartet per lane).
-template <int LB, int LK, int NAB, int NCD, bool GB, bool GK, bool UJ = true>
-__device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, const int J, double (&out)[NAB][NCD])
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK, bool UJ = true, int C0 = 0, int NCS = NCD>
+__device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, const int J, double (&out)[NAB][NCS])
 {
+    static_assert(C0 >= 0 && NCS >= 1 && C0 + NCS <= NCD, "ket function range");
     constexpr int L = LB + LK;
     constexpr int NH = nherm(L);
     constexpr int NHB = GB ? ncart(LB) : nherm(LB);           // bra rows per primitive
@@ -46,7 +48,7 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
 #pragma unroll
     for (int i = 0; i < NAB; ++i)
 #pragma unroll
-        for (int j = 0; j < NCD; ++j) out[i][j] = 0.0;
+        for (int j = 0; j < NCS; ++j) out[i][j] = 0.0;
 
     // The bra primitive loop runs to the side's largest count (the same for
     // every lane), each lane contributing while kb < its own count: the ket
@@ -56,11 +58,11 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
     const int nkk = GK ? 1 : npk;
     for (int kb = 0; kb < nkbw; ++kb) {
         if (!GB && kb >= npb) continue;
-        double X[NHB][NCD];
+        double X[NHB][NCS];
 #pragma unroll
         for (int i = 0; i < NHB; ++i)
 #pragma unroll
-            for (int j = 0; j < NCD; ++j) X[i][j] = 0.0;
+            for (int j = 0; j < NCS; ++j) X[i][j] = 0.0;
         PrimRec B1{};
         if constexpr (!GB) B1 = bp[kb];
 
@@ -112,14 +114,15 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
             for (int r = 0; r < NKN + NKT; ++r) {
                 const int hrow = r < NKN ? r : NTPAD + (r - NKN);
                 const int qh = r < NKN ? r : nherm(LK - 1) + (r - NKN);
-                double hk[NCD];
+                double hk[NCS];
 #pragma unroll
-                for (int j = 0; j < NCD; ++j) hk[j] = UJ ? load_const(Hk + hrow * NCDP + j) : Hk[hrow * NCDP + j];
+                for (int j = 0; j < NCS; ++j)
+                    hk[j] = UJ ? load_const(Hk + hrow * NCDP + C0 + j) : Hk[hrow * NCDP + C0 + j];
 #pragma unroll
                 for (int i = 0; i < NHB; ++i) {
                     const double v = R[sum.idx[HB0 + i][qh]];
 #pragma unroll
-                    for (int j = 0; j < NCD; ++j) X[i][j] = fma(v, hk[j], X[i][j]);
+                    for (int j = 0; j < NCS; ++j) X[i][j] = fma(v, hk[j], X[i][j]);
                 }
             }
         }
@@ -131,27 +134,49 @@ __device__ __forceinline__ void eri_valu_compute(const EriArgs &a, const int I, 
             for (int ab = 0; ab < NAB; ++ab) {
                 const double hb = Hbk[i * NABP + ab];
 #pragma unroll
-                for (int j = 0; j < NCD; ++j) out[ab][j] = fma(hb, X[i][j], out[ab][j]);
+                for (int j = 0; j < NCS; ++j) out[ab][j] = fma(hb, X[i][j], out[ab][j]);
             }
         }
     }
 
 }
 
-// Shellset (I, J) of the calling lane, stored in the caller's layout; I < nI.
-template <int LB, int LK, int NAB, int NCD, bool GB, bool GK, bool UJ = true>
-__device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I, const int J, const int nI)
+// Ket functions per part of a shellset.  A lane holds its outputs and the
+// ket-transformed block X (NAB + NHB values per ket function); where these
+// exceed the registers by far, the lane takes the ket functions in parts,
+// running the primitive loops once per part.  Every output element gets the
+// same operations in the same order either way.
+template <int LB, int NAB, int NCD, bool GB>
+__host__ __device__ constexpr int valu_part_cols()
 {
-    double out[NAB][NCD];
-    eri_valu_compute<LB, LK, NAB, NCD, GB, GK, UJ>(a, I, J, out);
+    constexpr int per = NAB + (GB ? ncart(LB) : nherm(LB));
+    if (per * NCD <= 200) return NCD;
+    return 128 / per < 1 ? 1 : (128 / per < NCD ? 128 / per : NCD);
+}
+
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK, bool UJ, int C0>
+__device__ __forceinline__ void eri_valu_shellset_part(const EriArgs &a, const int I, const int J, const int nI)
+{
+    constexpr int NCS0 = valu_part_cols<LB, NAB, NCD, GB>();
+    constexpr int NCS = C0 + NCS0 <= NCD ? NCS0 : NCD - C0;
+    double out[NAB][NCS];
+    eri_valu_compute<LB, LK, NAB, NCD, GB, GK, UJ, C0, NCS>(a, I, J, out);
     // store, [ij,ab,cd,kl] addressing of the caller
     const int64_t base = (a.om.count ? a.om.obase[J] : (int64_t)J * a.om.sJ) + (int64_t)I * a.om.sI;
     const int64_t mult = a.om.count ? (int64_t)nI : a.om.mult;
 #pragma unroll
     for (int ab = 0; ab < NAB; ++ab)
 #pragma unroll
-        for (int j = 0; j < NCD; ++j)
-            a.om.out[base + mult * (int64_t)(a.om.oab[ab] + a.om.ocd[j])] = out[ab][j];
+        for (int j = 0; j < NCS; ++j)
+            a.om.out[base + mult * (int64_t)(a.om.oab[ab] + a.om.ocd[C0 + j])] = out[ab][j];
+    if constexpr (C0 + NCS < NCD) eri_valu_shellset_part<LB, LK, NAB, NCD, GB, GK, UJ, C0 + NCS>(a, I, J, nI);
+}
+
+// Shellset (I, J) of the calling lane, stored in the caller's layout; I < nI.
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK, bool UJ = true>
+__device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I, const int J, const int nI)
+{
+    eri_valu_shellset_part<LB, LK, NAB, NCD, GB, GK, UJ, 0>(a, I, J, nI);
 }
 
 // Digestion of shellsets (I0, J), one per lane, J uniform over the wave (a
@@ -159,6 +184,41 @@ __device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I,
 // adds its Jb rows with atomics, the Jk terms are summed over groups of 8
 // lanes first.  Every lane of the wave must call it; lanes with I0 >= nI
 // compute a copy of bra pair nI - 1 and contribute nothing.
+// One part of the ket functions (see valu_part_cols): the Jk terms of its
+// columns go out at once, the Jb rows are summed into jb over the parts, in
+// the same column order as a whole shellset.
+template <int LB, int LK, int NAB, int NCD, bool GB, bool GK, int C0>
+__device__ __forceinline__ void eri_valu_digest_part(const EriArgs &a, const int I, const int J, const bool live,
+                                                     const int lane, double (&jb)[NAB])
+{
+    constexpr int NCS0 = valu_part_cols<LB, NAB, NCD, GB>();
+    constexpr int NCS = C0 + NCS0 <= NCD ? NCS0 : NCD - C0;
+    const Digest &d = a.dig;
+    double out[NAB][NCS];
+    eri_valu_compute<LB, LK, NAB, NCD, GB, GK, true, C0, NCS>(a, I, J, out);
+    if (d.Jb) {
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab)
+#pragma unroll
+            for (int j = 0; j < NCS; ++j) jb[ab] = fma(out[ab][j], d.Dk[J + d.nk * (C0 + j)], jb[ab]);
+    }
+    if (d.Jk) {
+#pragma unroll
+        for (int j = 0; j < NCS; ++j) {
+            double v = 0.0;
+            if (live) {
+#pragma unroll
+                for (int ab = 0; ab < NAB; ++ab) v = fma(out[ab][j], d.Db[I + d.nb * ab], v);
+            }
+            v += __shfl_xor(v, 1);
+            v += __shfl_xor(v, 2);
+            v += __shfl_xor(v, 4);
+            if ((lane & 7) == 0) atomicAdd(d.Jk + J + d.nk * (C0 + j), v);
+        }
+    }
+    if constexpr (C0 + NCS < NCD) eri_valu_digest_part<LB, LK, NAB, NCD, GB, GK, C0 + NCS>(a, I, J, live, lane, jb);
+}
+
 template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
 __device__ __forceinline__ void eri_valu_digest_one(const EriArgs &a, const int I0, const int J, const int nI)
 {
@@ -166,6 +226,16 @@ __device__ __forceinline__ void eri_valu_digest_one(const EriArgs &a, const int 
     const bool live = I0 < nI;
     const int I = live ? I0 : nI - 1;
     const Digest &d = a.dig;
+    if constexpr (valu_part_cols<LB, NAB, NCD, GB>() < NCD) {
+        double jb[NAB];
+#pragma unroll
+        for (int ab = 0; ab < NAB; ++ab) jb[ab] = 0.0;
+        eri_valu_digest_part<LB, LK, NAB, NCD, GB, GK, 0>(a, I, J, live, lane, jb);
+        if (d.Jb && live)
+#pragma unroll
+            for (int ab = 0; ab < NAB; ++ab) atomicAdd(d.Jb + I + d.nb * ab, jb[ab]);
+        return;
+    }
     double out[NAB][NCD];
     eri_valu_compute<LB, LK, NAB, NCD, GB, GK>(a, I, J, out);
     if (d.Jb && live) {

@@ -179,11 +179,6 @@ __device__ __forceinline__ void eri_valu_shellset(const EriArgs &a, const int I,
     eri_valu_shellset_part<LB, LK, NAB, NCD, GB, GK, UJ, 0>(a, I, J, nI);
 }
 
-// Digestion of shellsets (I0, J), one per lane, J uniform over the wave (a
-// ragged tile: ket pair J and 64 bra pairs of its prefix I < nI): each lane
-// adds its Jb rows with atomics, the Jk terms are summed over groups of 8
-// lanes first.  Every lane of the wave must call it; lanes with I0 >= nI
-// compute a copy of bra pair nI - 1 and contribute nothing.
 // One part of the ket functions (see valu_part_cols): the Jk terms of its
 // columns go out at once, the Jb rows are summed into jb over the parts, in
 // the same column order as a whole shellset.
@@ -219,6 +214,11 @@ __device__ __forceinline__ void eri_valu_digest_part(const EriArgs &a, const int
     if constexpr (C0 + NCS < NCD) eri_valu_digest_part<LB, LK, NAB, NCD, GB, GK, C0 + NCS>(a, I, J, live, lane, jb);
 }
 
+// Digestion of shellsets (I0, J), one per lane, J uniform over the wave (a
+// ragged tile: ket pair J and 64 bra pairs of its prefix I < nI): each lane
+// adds its Jb rows with atomics, the Jk terms are summed over groups of 8
+// lanes first.  Every lane of the wave must call it; lanes with I0 >= nI
+// compute a copy of bra pair nI - 1 and contribute nothing.
 template <int LB, int LK, int NAB, int NCD, bool GB, bool GK>
 __device__ __forceinline__ void eri_valu_digest_one(const EriArgs &a, const int I0, const int J, const int nI)
 {

@@ -227,13 +227,18 @@ __device__ __forceinline__ void eri_mfma_shellset(const EriArgs &a, const int I,
                     }
                 }
                 if (fresh) {
-                    // one-axis sweeps of Eq. (31): z and y per column v, then x per (u, v)
+                    // one-axis sweeps of Eq. (31): z and y per column v, then x per (u, v).
+                    // The whole workgroup waits for them at the next barrier, while the
+                    // other resident workgroup's matrix instructions can wait: the sweeps
+                    // issue at a raised wave priority.
+                    __builtin_amdgcn_s_setprio(2);
                     const double *Sk = S + kk0 * nqmax * D, *PQk = PQ + kk0 * nqmax * 4;
                     ysweeps<CB, NW, YSER>(cube, Sk, PQk, NQ, nk * nqmax, nqmax, w, lane,
                                           std::make_integer_sequence<int, NW>{});
                     __syncthreads();
                     xsweeps<CB, NW, KP * NQCT, YSER>(cube, PQk, NQ, nk * nqmax, nqmax, w, lane,
                                                      std::make_integer_sequence<int, NW>{});
+                    __builtin_amdgcn_s_setprio(0);
                 }
 #pragma unroll
                 for (int j = 0; j < KP; ++j)

@@ -181,12 +181,16 @@ eri_grad_kernel(GradArgs a)
                     hv[j][i] = (j < nk && e < NTPAD * NQW) ? HkG[(int64_t)(kk0 + j) * RPB * NQW + e] : 0.0;
                 }
             {
+                // the sweeps gate the whole workgroup: raised wave priority, as in the
+                // forward kernel
+                __builtin_amdgcn_s_setprio(2);
                 const double *Sk = S + kk0 * nqmax * D, *PQk = PQ + kk0 * nqmax * 4;
                 ysweeps<CB, NW, YSER>(cube, Sk, PQk, NQ, nk * nqmax, nqmax, w, lane,
                                       std::make_integer_sequence<int, NW>{});
                 __syncthreads();
                 xsweeps<CB, NW, KP * NQCT, YSER>(cube, PQk, NQ, nk * nqmax, nqmax, w, lane,
                                                  std::make_integer_sequence<int, NW>{});
+                __builtin_amdgcn_s_setprio(0);
             }
 #pragma unroll
             for (int j = 0; j < KP; ++j)
